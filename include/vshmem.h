@@ -1,0 +1,526 @@
+/*
+ * vshmem: device-initiated OpenSHMEM on virtual PEs, for one MI355X (gfx950).
+ *
+ * Host C-ABI of libvshmem.so.  Every entry point is `extern "C"` and takes
+ * plain pointers and sizes.  "Device pointer" means memory the HIP runtime
+ * allocated on the GPU (hipMalloc or a PyTorch CUDA tensor); "host pointer"
+ * means ordinary process memory.  A `void *stream` argument is a hipStream_t
+ * (NULL = the default stream); every launcher is asynchronous on it.
+ *
+ * Virtual PEs.  One device allocation of npes * stride bytes is the
+ * symmetric heap; PE p owns [base + p*stride, base + (p+1)*stride).  The
+ * first `user_bytes` of each slice are allocatable; the tail holds the
+ * library's per-PE scratch (barrier words).  A "canonical symmetric
+ * address" is PE 0's copy of an object, base + offset; PE p's copy of the
+ * object is that address + p*stride (the symmetric heap of the paper's
+ * Section 2.1: same size and allocation order on every PE, so remote
+ * addresses are computable; no per-operation pointer classification,
+ * Section 6.3).
+ *
+ * Errors.  The paper leaves the error model to a later OpenSHMEM release
+ * (Section 6.6).  Here: calls that return int give 0 (SHMEMX_OK) or a
+ * negative SHMEMX_ERR_* code; allocators return NULL; OpenSHMEM calls that
+ * return void record their failure for shmemx_last_error().  Device-side
+ * failures (a wait that timed out, an out-of-heap descriptor) latch bits in
+ * a device error word read by shmemx_device_errors().
+ *
+ * Threading.  Host calls are single-threaded except shmemx_progress_submit
+ * and shmemx_progress_poll, which are safe from any number of threads.
+ */
+#ifndef VSHMEM_H
+#define VSHMEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define SHMEMX_OK 0
+#define SHMEMX_ERR_ARG (-1)         /* bad argument (range, NULL, alignment) */
+#define SHMEMX_ERR_NOMEM (-2)       /* heap, budget or host memory exhausted */
+#define SHMEMX_ERR_STATE (-3)       /* not initialised, already initialised, finalised */
+#define SHMEMX_ERR_HIP (-4)         /* a HIP runtime call failed */
+#define SHMEMX_ERR_BUSY (-5)        /* resource in use (progress kernel running, ring full) */
+#define SHMEMX_ERR_TIMEOUT (-6)     /* a bounded wait expired */
+#define SHMEMX_ERR_DEVICE (-7)      /* the device latched an error */
+#define SHMEMX_ERR_UNSUPPORTED (-8) /* valid request this implementation does not provide */
+
+/* Device error-word bits (shmemx_device_errors). */
+#define SHMEMX_DEVERR_WAIT_TIMEOUT 0x1u   /* wait_until / barrier spin limit reached */
+#define SHMEMX_DEVERR_BAD_DESC 0x2u       /* descriptor outside the heap or bad op */
+#define SHMEMX_DEVERR_PROGRESS_IDLE 0x4u  /* progress kernel stopped by its idle limit */
+
+/* -------------------------------------------------- operations and scopes
+ * Operation codes of a descriptor (Section 2.1 operation list; put with
+ * signal and signal wait from Section 4.3; fence/quiet from Section 6.4). */
+#define SHMEMX_OP_NOP 0
+#define SHMEMX_OP_PUT 1
+#define SHMEMX_OP_GET 2
+#define SHMEMX_OP_PUT_SIGNAL 3
+#define SHMEMX_OP_AMO_FETCH_ADD 4
+#define SHMEMX_OP_AMO_FETCH_XOR 5
+#define SHMEMX_OP_AMO_COMPARE_SWAP 6
+#define SHMEMX_OP_AMO_ADD 7
+#define SHMEMX_OP_AMO_XOR 8
+#define SHMEMX_OP_AMO_SET 9
+#define SHMEMX_OP_AMO_FETCH 10
+#define SHMEMX_OP_AMO_SWAP 11
+#define SHMEMX_OP_WAIT_UNTIL 12
+#define SHMEMX_OP_FENCE 13
+#define SHMEMX_OP_QUIET 14
+#define SHMEMX_OP_BARRIER_ALL 15
+
+/* Participation scopes (Section 4.1 and Section 6.3: thread, wavefront,
+ * work-group, grid; every thread of the scope calls with identical
+ * arguments). */
+#define SHMEMX_SCOPE_THREAD 0
+#define SHMEMX_SCOPE_WAVE 1
+#define SHMEMX_SCOPE_WG 2
+#define SHMEMX_SCOPE_GRID 3
+#define SHMEMX_SCOPE_AUTO 255     /* let the tune table pick per size class */
+
+#define SHMEM_SIGNAL_SET 0
+#define SHMEM_SIGNAL_ADD 1
+
+#define SHMEM_CMP_EQ 0
+#define SHMEM_CMP_NE 1
+#define SHMEM_CMP_GT 2
+#define SHMEM_CMP_GE 3
+#define SHMEM_CMP_LT 4
+#define SHMEM_CMP_LE 5
+
+#define SHMEMX_NO_RESULT 0xFFFFFFFFu
+
+/*
+ * One operation, 64 bytes.  Heap locations are byte OFFSETS into the
+ * symmetric heap (the same on every PE), not addresses.
+ *   PUT:  target's [dst, dst+nbytes) <- issuer's [src, src+nbytes)
+ *   GET:  issuer's [dst, dst+nbytes) <- target's [src, src+nbytes)
+ *   PUT_SIGNAL: PUT, then the uint64 at target's `cond` is set to (aux =
+ *         SHMEM_SIGNAL_SET) or increased by (SHMEM_SIGNAL_ADD) `value`.
+ *   AMO_*: on the int64 at target's `src` (8-byte aligned); operand `value`;
+ *         COMPARE_SWAP compares with `cond`; fetching AMOs write the old
+ *         value to results[result_idx] unless result_idx == SHMEMX_NO_RESULT.
+ *   WAIT_UNTIL: issuer waits until its int64 at `src` satisfies `aux`
+ *         (SHMEM_CMP_*) against `value`; flags bit 0 = unsigned compare.
+ *   FENCE, QUIET, BARRIER_ALL: ordering points of the issuing PE (barrier:
+ *         of all PEs; every PE's program has the same number of them).
+ */
+typedef struct shmemx_desc {
+    uint8_t op;
+    uint8_t scope;
+    uint8_t aux;
+    uint8_t flags;
+    int32_t issuer_pe;
+    int32_t target_pe;
+    uint32_t result_idx;
+    uint64_t src;
+    uint64_t dst;
+    uint64_t nbytes;
+    uint64_t value;
+    uint64_t cond;
+    uint64_t reserved;
+} shmemx_desc_t;
+
+/* ------------------------------------------------------------------ teams
+ * Teams (Section 2.2; device teams of Section 4.1).  On one GPU the world
+ * and shared teams have the same members: every virtual PE. */
+typedef int32_t shmem_team_t;
+#define SHMEM_TEAM_INVALID (-1)
+#define SHMEM_TEAM_WORLD 0
+#define SHMEM_TEAM_SHARED 1
+#define SHMEM_DEVICE_TEAM_WORLD 2
+#define SHMEM_DEVICE_TEAM_SHARED 3
+
+/* ------------------------------------------------------------ capabilities
+ * Capability record (Section 6.5: queries distinguish host GPU-aware
+ * support from device-initiated APIs, report stream variants separately,
+ * report the active mode and the communication path).  Shape is ours. */
+#define SHMEMX_PROGRESS_KERNEL_LAUNCH 0x1
+#define SHMEMX_PROGRESS_PERSISTENT_GPU 0x2
+#define SHMEMX_PATH_SINGLE_GPU_LOADSTORE 1
+#define SHMEMX_PTR_DOMAIN_DEVICE 2
+
+typedef struct shmemx_caps {
+    int32_t gpu_heap;              /* 1: a GPU-attached symmetric heap exists */
+    int32_t default_heap_is_gpu;   /* 1: GPU-first; shmem_malloc == shmemg_malloc */
+    int32_t host_initiated;        /* host-issued RMA on GPU buffers (0 here) */
+    int32_t device_initiated;      /* 1: device-initiated RMA, AMO, sync */
+    int32_t device_ctx_default;    /* 1: SHMEM_DEVICE_CTX_DEFAULT available */
+    int32_t explicit_device_ctx;   /* 0: not provided */
+    uint32_t scopes;               /* bit (1 << SHMEMX_SCOPE_*) per supported scope */
+    int32_t device_collectives;    /* 1 */
+    int32_t stream_triggered;      /* 0: no _on_stream host APIs */
+    uint32_t progress;             /* SHMEMX_PROGRESS_* bits */
+    int32_t path;                  /* SHMEMX_PATH_* */
+    int32_t ptr_domain;            /* domain of shmem_ptr results */
+    int32_t team_npes;             /* members of the queried team */
+    int32_t team_start;
+    int32_t team_stride;
+    int32_t npes;                  /* virtual PEs */
+    uint64_t heap_user_bytes;      /* allocatable bytes per PE */
+    uint64_t heap_stride;          /* bytes between PE slices */
+    int32_t debug;                 /* VSHMEM_DEBUG */
+    int32_t reserved[7];
+} shmemx_caps_t;
+
+/* ---------------------------------------------------- init and allocation */
+
+/* Attach an existing device allocation as the symmetric heap (the paper's
+ * GPU heap created at initialisation, Section 6.1; context creation and
+ * publication of the device-visible default context, Section 6.2).
+ * heap: device pointer, 2 MiB aligned, heap_bytes >= npes * 2 MiB and a
+ * multiple of npes; stride = heap_bytes / npes must be a multiple of 2 MiB.
+ * The caller keeps ownership of the memory and must keep it alive until
+ * shmem_finalize.  The library clears its per-PE scratch tail on `stream`
+ * and waits for it.  Returns SHMEMX_OK, SHMEMX_ERR_ARG, SHMEMX_ERR_STATE
+ * (already initialised) or SHMEMX_ERR_HIP. */
+int shmemx_init_attach(void *heap, size_t heap_bytes, int npes, void *stream);
+
+/* OpenSHMEM initialisation (Section 6.1, heaps created at init with traits
+ * from the environment): VSHMEM_NPES (default 4) virtual PEs with
+ * VSHMEM_SYMMETRIC_SIZE allocatable bytes each (default 64 MiB; suffixes
+ * K, M, G); the library allocates the heap with hipMalloc and owns it.
+ * Failure is recorded for shmemx_last_error(). */
+void shmem_init(void);
+
+/* Destroy the device context and release library resources (Section 6.2
+ * context lifecycle: teardown at finalisation).  Every symmetric address,
+ * plan and team becomes invalid. */
+void shmem_finalize(void);
+
+/* Number of virtual PEs; 0 before init. */
+int shmem_n_pes(void);
+
+/* On the host the calling thread acts for PE 0: returns 0 after init and
+ * -1 before. */
+int shmem_my_pe(void);
+
+/* Symmetric allocation (Section 6.1: same size and order on every PE).
+ * Returns a canonical symmetric address (device pointer into PE 0's slice),
+ * aligned to 256 bytes, or NULL when size is 0 or the heap is exhausted.
+ * First-fit over a coalescing free list, so the result depends only on the
+ * sequence of calls.  shmemg_malloc is the paper's GPU-heap allocator; the
+ * GPU heap is the default heap here, so the two are the same. */
+void *shmem_malloc(size_t size);
+void *shmemg_malloc(size_t size);
+/* Zeroed allocation on every PE (waits for the clear). */
+void *shmem_calloc(size_t count, size_t size);
+/* Allocation aligned to `alignment` (a power of two >= 256). */
+void *shmem_align(size_t alignment, size_t size);
+/* Free a canonical symmetric address returned by an allocator; other
+ * pointers are ignored and recorded as SHMEMX_ERR_ARG. */
+void shmem_free(void *ptr);
+
+/* PE `pe`'s copy of a symmetric object (Section 6.3 pointer queries).  The
+ * result is a DEVICE pointer: valid for loads and stores in kernels, not on
+ * the host (access domain reported as SHMEMX_PTR_DOMAIN_DEVICE).  NULL if
+ * `sym` is not inside the heap or pe is out of range. */
+void *shmem_ptr(const void *sym, int pe);
+
+/* Capability query for a team (Section 6.5).  Returns SHMEMX_OK or an
+ * error for an unknown team / NULL out. */
+int shmem_query_capabilities(shmem_team_t team, shmemx_caps_t *caps);
+
+/* Heap geometry: device base address, bytes per PE slice, allocatable bytes
+ * per PE.  0 before init. */
+void *shmemx_heap_base(void);
+uint64_t shmemx_heap_stride(void);
+uint64_t shmemx_heap_user_bytes(void);
+
+/* Device pointer to the published device context (the GPU-visible
+ * SHMEM_DEVICE_CTX_DEFAULT of Section 6.2), for user kernels that include
+ * vshmem_device.hpp.  NULL before init. */
+const void *shmemx_device_ctx(void);
+
+/* Strided team split (OpenSHMEM teams, Section 2.2): members are parent
+ * members start, start+stride, ... (size of them).  config/config_mask are
+ * accepted for OpenSHMEM signature compatibility and ignored.  On success
+ * *new_team is a device team usable by the collective launchers. */
+int shmem_team_split_strided(shmem_team_t parent, int start, int stride, int size,
+                             const void *config, long config_mask, shmem_team_t *new_team);
+int shmem_team_n_pes(shmem_team_t team);
+/* Team index of PE `pe` in `team`, or -1 if it is not a member. */
+int shmemx_team_pe_index(shmem_team_t team, int pe);
+void shmem_team_destroy(shmem_team_t team);
+
+/* Error reporting. */
+const char *shmemx_strerror(int code);
+int shmemx_last_error(void);
+/* Read and clear the device error word (SHMEMX_DEVERR_* bits); waits for
+ * the device.  Returns the bits, or a negative code if not initialised. */
+int shmemx_device_errors(void);
+/* Spin limit of device-side waits in nanoseconds (default 10 s).  A wait
+ * that exceeds it gives up, latches SHMEMX_DEVERR_WAIT_TIMEOUT and returns,
+ * so every kernel terminates. */
+int shmemx_set_wait_timeout_ns(uint64_t ns);
+
+/* ---------------------------------------------- device-initiated launches
+ * Per-launch geometry.  NULL selects defaults.  wgs_per_pe: work-groups
+ * that act for each virtual PE (a virtual PE is a heap slice plus the
+ * work-groups the launcher maps to it: pe = blockIdx.x / wgs_per_pe).
+ * wg_size: threads per work-group (multiple of 64, <= 1024).  chunk_bytes:
+ * unit of work handed to one work-group when a message or collective is
+ * split across work-groups (multiple of 16). */
+typedef struct shmemx_launch {
+    int32_t wgs_per_pe;
+    int32_t wg_size;
+    uint64_t chunk_bytes;
+    int32_t flags;                 /* SHMEMX_LAUNCH_* */
+    int32_t reserved;
+} shmemx_launch_t;
+#define SHMEMX_LAUNCH_NONTEMPORAL 0x1  /* streaming loads/stores in copies */
+
+/*
+ * Pattern put/get (device-initiated RMA, Section 6.3): every PE p with
+ * targets[p] >= 0 issues nmsg messages of msg_bytes at the given scope:
+ * message j moves [src_off + j*src_step, +msg_bytes) to
+ * [dst_off + j*dst_step, +msg_bytes); for SHMEMX_OP_PUT the source is on p
+ * and the destination on targets[p]; for SHMEMX_OP_GET the source is on
+ * targets[p] and the destination on p.  Each PE ends with quiet.
+ * Scope THREAD: each lane issues whole messages; WAVE: each wavefront; WG:
+ * each work-group; GRID: all work-groups of the PE share each message.
+ * targets: DEVICE pointer to npes int32.  Ranges must lie in the user part
+ * of the heap and destinations must not overlap (the result would be
+ * undefined); SHMEMX_ERR_ARG otherwise.
+ */
+int shmemx_rma_pattern(int op, int scope, const int32_t *targets, uint64_t src_off, uint64_t dst_off,
+                       uint64_t msg_bytes, uint64_t nmsg, uint64_t src_step, uint64_t dst_step,
+                       const shmemx_launch_t *launch, void *stream);
+
+/*
+ * Random-access atomics (GUPS-style; remote atomic updates of Section 4.4
+ * case study 2, atomics of Section 2.1).  The table is 2^log2_table int64
+ * words spread evenly over the PEs: global index g lives on PE
+ * g >> (log2_table - log2(npes)) at heap offset table_off + 8*(g mod
+ * per-PE entries); npes must be a power of two.  Update u (0 <= u <
+ * nupdates) draws x_{3u}, x_{3u+1}, x_{3u+2} from the SplitMix64 stream
+ * `seed`: index x_{3u} mod 2^log2_table, value x_{3u+1}, and it is
+ * fetch_add when x_{3u+2} mod add_every == 0, else fetch_xor.  Update u is
+ * issued by PE u / (nupdates / npes).  fetched: DEVICE array of nupdates
+ * uint64 receiving each fetched value, or NULL; acc: DEVICE uint64 that
+ * receives the XOR of all fetched values (so fetches are not elided), or
+ * NULL.  Atomics are relaxed, agent scope (atomicity without ordering).
+ */
+int shmemx_gups(uint64_t table_off, int log2_table, uint64_t nupdates, uint64_t seed, int add_every,
+                uint64_t *fetched, uint64_t *acc, const shmemx_launch_t *launch, void *stream);
+
+/*
+ * Signal ping-pong (put with signal and signal wait, Section 4.3 and the
+ * wait/test operations of Section 2.1).  For pair k, PEs a = pairs[2k] and
+ * b = pairs[2k+1]: in round r (1..rounds) a puts payload_bytes from its
+ * [data_off] to b's [data_off] with signal SET r on b's uint64 at sig_off,
+ * waits until its own signal equals r; b waits for r and answers the same
+ * way.  rtt_cycles: DEVICE array of npairs*rounds uint64 receiving each
+ * round trip in wall-clock ticks (see shmemx_wallclock_hz), or NULL.
+ * same_xcd != 0 places both work-groups of a pair on one XCD, else on
+ * different XCDs.  pairs: DEVICE int32 array.
+ */
+int shmemx_pingpong(uint64_t data_off, uint64_t sig_off, const int32_t *pairs, int npairs, int rounds,
+                    uint64_t payload_bytes, int same_xcd, uint64_t *rtt_cycles, void *stream);
+
+/* Device-side wait launched from the host (wait_until of Section 2.1): one
+ * work-group acting for PE `pe` waits until its int64 at heap offset ivar_off
+ * satisfies cmp (SHMEM_CMP_*) against value (unsigned compare when
+ * is_unsigned), then writes the value it observed to *out (DEVICE pointer,
+ * may be NULL).  The wait is bounded by the spin limit
+ * (shmemx_set_wait_timeout_ns); on expiry it latches
+ * SHMEMX_DEVERR_WAIT_TIMEOUT and the kernel ends. */
+int shmemx_wait_until_launch(int pe, uint64_t ivar_off, int cmp, uint64_t value, int is_unsigned, uint64_t *out,
+                             void *stream);
+
+/* Frequency of the device wall clock used by timing outputs, in Hz. */
+uint64_t shmemx_wallclock_hz(void);
+
+/*
+ * Team barrier (barrier_all / team_sync, Section 6.3; barrier implies
+ * quiet): one work-group per member, `iters` consecutive barriers; with
+ * tokens_off != UINT64_MAX each member writes a token (iteration, pe) to
+ * every member's [tokens_off + 8*member] before each barrier and checks
+ * after it that all tokens of that iteration are present, counting
+ * failures into *bad (DEVICE uint64, may be NULL).  cycles: DEVICE uint64
+ * receiving the total wall-clock ticks of member 0, or NULL.
+ */
+int shmemx_barrier_launch(shmem_team_t team, int iters, uint64_t tokens_off, uint64_t *bad,
+                          uint64_t *cycles, void *stream);
+
+/*
+ * Team collectives executed by every member's work-groups (device
+ * collectives with uniform participation, Section 6.3; the collectives
+ * named in Section 4.3).  dest/src are canonical symmetric addresses; each
+ * call starts and ends with a team barrier and implies quiet for its own
+ * traffic.  Source and destination ranges must not overlap (except for
+ * the reductions, which may run in place).
+ *   broadcast: every member's dest[0, n) <- root member's src[0, n), the
+ *              root's dest included; root is a team index.
+ *   fcollect:  member p's dest[q*n, +n) <- member q's src[0, n).
+ *   alltoall:  member p's dest[q*n, +n) <- member q's src[p*n, +n).
+ *   reduce:    every member's dest[k] <- TREE(member 0's src[k], ...,
+ *              member P-1's src[k]) where TREE pairs adjacent elements
+ *              level by level and carries an odd last element; dtype int64
+ *              (wrapping), fp32 (round-to-nearest-even adds), bf16 (inputs
+ *              widened exactly to fp32, result rounded once to bf16); op
+ *              SUM or MAX with max(a, b) = (b > a) ? b : a.
+ * Every member's work-groups must be co-resident: the launch fails with
+ * SHMEMX_ERR_ARG if team size * wgs_per_pe work-groups cannot be.
+ */
+#define SHMEMX_DT_INT64 0
+#define SHMEMX_DT_FP32 1
+#define SHMEMX_DT_BF16 2
+#define SHMEMX_RED_SUM 0
+#define SHMEMX_RED_MAX 1
+int shmemx_broadcastmem_launch(shmem_team_t team, void *dest, const void *src, size_t n, int root,
+                               const shmemx_launch_t *launch, void *stream);
+int shmemx_fcollectmem_launch(shmem_team_t team, void *dest, const void *src, size_t n,
+                              const shmemx_launch_t *launch, void *stream);
+int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, size_t n,
+                              const shmemx_launch_t *launch, void *stream);
+int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const void *src, size_t nreduce,
+                         const shmemx_launch_t *launch, void *stream);
+
+/* ---------------------------------------------------- batched execution
+ * A plan is a program of descriptors prepared once and launched many times.
+ * Each PE's program is the subsequence of descriptors it issues, in order.
+ * Operations between two ordering points of their issuer (fence, quiet,
+ * barrier_all) may run concurrently; results equal issuing the operations
+ * one at a time (operations in one such phase must not conflict).
+ * WAIT_UNTIL is not accepted in plans (SHMEMX_ERR_UNSUPPORTED); use the
+ * device API or the progress kernel.  Forms: one fused launch, one launch
+ * per operation, or either form captured in a hipGraph.
+ */
+#define SHMEMX_TUNE_CLASSES 40
+typedef struct shmemx_tune {
+    int32_t wg_size;                          /* threads per work-group of the fused kernel */
+    int32_t grid_wgs;                         /* cap on fused work-groups (0 = automatic) */
+    uint8_t scope[SHMEMX_TUNE_CLASSES];       /* scope per floor(log2(nbytes)) class */
+    uint64_t chunk[SHMEMX_TUNE_CLASSES];      /* bytes per work-group task per class */
+} shmemx_tune_t;
+
+typedef struct shmemx_plan shmemx_plan_t;
+
+/* Fill a tune table with the built-in defaults. */
+void shmemx_tune_default(shmemx_tune_t *tune);
+/* Build a plan from HOST descriptors (copied).  tune may be NULL.
+ * Validates every descriptor (ranges inside the user heap, PEs, op codes,
+ * equal barrier counts) and returns SHMEMX_ERR_ARG with no plan otherwise. */
+int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t *tune, shmemx_plan_t **plan);
+/* One fused launch of the whole plan.  results: DEVICE uint64 array with
+ * room for every result index used, or NULL if none. */
+int shmemx_plan_launch_fused(shmemx_plan_t *plan, uint64_t *results, void *stream);
+/* One kernel launch per operation, in program order. */
+int shmemx_plan_launch_per_op(shmemx_plan_t *plan, uint64_t *results, void *stream);
+/* Capture form 0 (per-op) or 1 (fused) into a hipGraph bound to `results`. */
+int shmemx_plan_graph_build(shmemx_plan_t *plan, int form, uint64_t *results, void *stream);
+int shmemx_plan_graph_launch(shmemx_plan_t *plan, void *stream);
+/* Number of fused work-group tasks / phases / kernel launches per per-op run. */
+int shmemx_plan_info(const shmemx_plan_t *plan, uint64_t *ntasks, uint64_t *nphases, uint64_t *nlaunches);
+void shmemx_plan_destroy(shmemx_plan_t *plan);
+
+/* Autotuner: for each size class from min_bytes to max_bytes (powers of
+ * two) and each candidate (scope, work-group size, chunk), time `reps`
+ * fused launches of `msgs` puts between distinct PEs inside the user heap
+ * range [scratch_off, scratch_off + scratch_bytes) of every PE (its
+ * contents are overwritten), and keep the fastest (median time).  Writes
+ * the result to *tune.  Synchronous. */
+int shmemx_autotune(uint64_t scratch_off, uint64_t scratch_bytes, uint64_t min_bytes, uint64_t max_bytes,
+                    int msgs, int reps, shmemx_tune_t *tune, void *stream);
+/* Save / load a tune table as JSON keyed by the device name. */
+int shmemx_tune_save(const shmemx_tune_t *tune, const char *path);
+int shmemx_tune_load(shmemx_tune_t *tune, const char *path);
+
+/* ------------------------------------------------------------- serving
+ * Persistent progress kernel (long-lived kernels, Section 3; GPU-driven
+ * progress, Section 6.4 and Section 7).  Host threads submit descriptors
+ * (PUT, GET, AMO_FETCH_ADD with nbytes/8 counters) into a ring in pinned
+ * host memory; resident work-groups claim requests, split large ones into
+ * chunks that several work-groups share, execute them, quiet, and post a
+ * completion record.  The kernel exits when stopped or after
+ * idle_timeout_ms without work.
+ */
+typedef struct shmemx_progress_cfg {
+    int32_t nwg;              /* resident work-groups (0 = one per CU) */
+    int32_t wg_size;          /* threads per work-group */
+    int32_t ring_slots;       /* power of two */
+    int32_t verify;           /* 1: completion carries a hash of the output */
+    uint64_t chunk_bytes;     /* split unit for large requests */
+    uint64_t idle_timeout_ms; /* 0 = 30000 */
+} shmemx_progress_cfg_t;
+
+typedef struct shmemx_completion {
+    uint64_t ticket;
+    uint64_t t_start;         /* device wall clock when first claimed */
+    uint64_t t_end;           /* device wall clock at completion */
+    uint64_t hash;            /* output hash when verify is on */
+    int32_t status;           /* 0 ok */
+    int32_t reserved;
+} shmemx_completion_t;
+
+int shmemx_progress_start(const shmemx_progress_cfg_t *cfg, void *stream);
+/* Multi-producer: enqueue one request; *ticket identifies it.  AMO fetch
+ * results go to the issuer's [dst, dst + nbytes).  Returns
+ * SHMEMX_ERR_BUSY when the ring is full. */
+int shmemx_progress_submit(const shmemx_desc_t *desc, uint64_t *ticket);
+/* 1 = complete (out filled), 0 = not yet, <0 = error. */
+int shmemx_progress_poll(uint64_t ticket, shmemx_completion_t *out);
+/* Stop the kernel after it drains the ring; waits up to timeout_ms. */
+int shmemx_progress_stop(int timeout_ms);
+
+/*
+ * Trace-driven serving run in native code: `lanes` producer threads replay
+ * the requests at their arrival times (seconds from start), admission
+ * reserves each request's destination range from a per-PE first-fit list
+ * inside [region_off, region_off + region_bytes) under a total budget of
+ * budget_bytes (requests wait while it is exceeded), a completion thread
+ * frees reservations as requests finish (continuous batching).  Sources
+ * are read from [src_off, ...) as given.  Fills latency_ns[i] (arrival to
+ * observed completion) and completions[i].  The progress kernel must be
+ * running.  Returns SHMEMX_OK or an error.
+ */
+typedef struct shmemx_request {
+    int32_t op;               /* SHMEMX_OP_PUT / GET / AMO_FETCH_ADD */
+    int32_t issuer_pe;
+    int32_t target_pe;
+    int32_t lane;
+    uint64_t nbytes;
+    uint64_t src_off;         /* source offset (read-only region) */
+    double arrival_s;
+} shmemx_request_t;
+
+typedef struct shmemx_serve_stats {
+    double wall_s;
+    uint64_t bytes;
+    uint64_t amo_ops;
+    uint64_t max_reserved_bytes;
+    uint64_t admission_waits;
+} shmemx_serve_stats_t;
+
+int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
+                     uint64_t region_bytes, uint64_t budget_bytes, uint64_t *dst_off_out,
+                     uint64_t *latency_ns, shmemx_completion_t *completions, shmemx_serve_stats_t *stats);
+
+/* ------------------------------------------------------------ utilities */
+/* Fill device memory with bytes [word_offset*8, ...) of the SplitMix64
+ * stream `seed` (little-endian words): the seeded synthetic payload. */
+int shmemx_fill_random(void *dst, uint64_t nbytes, uint64_t seed, uint64_t word_offset, void *stream);
+/* Plain device-to-device copy kernel of nbytes (16-byte aligned) used as
+ * the achievable-bandwidth probe and as the counter-scaling reference. */
+int shmemx_probe_copy(void *dst, const void *src, uint64_t nbytes, int nwg, int wg_size, void *stream);
+/* Agent-scope int64 fetch_add to random words of a DEVICE table of nwords
+ * (a power of two): atomic-throughput probe. */
+int shmemx_probe_atomics(uint64_t *table, uint64_t nwords, uint64_t nupdates, uint64_t seed, uint64_t *acc,
+                         void *stream);
+/* XCD id (hardware register XCC_ID) of each of nblocks work-groups. */
+int shmemx_probe_xcd(int32_t *out, int nblocks, void *stream);
+/* Empty kernel: launch-latency probe. */
+int shmemx_probe_empty(void *stream);
+
+/* Library version string. */
+const char *shmemx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VSHMEM_H */

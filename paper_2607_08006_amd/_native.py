@@ -1,0 +1,140 @@
+"""ctypes declarations of libvshmem.so (the C-ABI in include/vshmem.h)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvshmem.so")
+
+TUNE_CLASSES = 40
+
+
+class Desc(C.Structure):
+    _fields_ = [("op", C.c_uint8), ("scope", C.c_uint8), ("aux", C.c_uint8), ("flags", C.c_uint8),
+                ("issuer_pe", C.c_int32), ("target_pe", C.c_int32), ("result_idx", C.c_uint32),
+                ("src", C.c_uint64), ("dst", C.c_uint64), ("nbytes", C.c_uint64), ("value", C.c_uint64),
+                ("cond", C.c_uint64), ("reserved", C.c_uint64)]
+
+
+class Caps(C.Structure):
+    _fields_ = [("gpu_heap", C.c_int32), ("default_heap_is_gpu", C.c_int32), ("host_initiated", C.c_int32),
+                ("device_initiated", C.c_int32), ("device_ctx_default", C.c_int32),
+                ("explicit_device_ctx", C.c_int32), ("scopes", C.c_uint32), ("device_collectives", C.c_int32),
+                ("stream_triggered", C.c_int32), ("progress", C.c_uint32), ("path", C.c_int32),
+                ("ptr_domain", C.c_int32), ("team_npes", C.c_int32), ("team_start", C.c_int32),
+                ("team_stride", C.c_int32), ("npes", C.c_int32), ("heap_user_bytes", C.c_uint64),
+                ("heap_stride", C.c_uint64), ("debug", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("wgs_per_pe", C.c_int32), ("wg_size", C.c_int32), ("chunk_bytes", C.c_uint64),
+                ("flags", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("wg_size", C.c_int32), ("grid_wgs", C.c_int32), ("scope", C.c_uint8 * TUNE_CLASSES),
+                ("chunk", C.c_uint64 * TUNE_CLASSES)]
+
+
+class ProgressCfg(C.Structure):
+    _fields_ = [("nwg", C.c_int32), ("wg_size", C.c_int32), ("ring_slots", C.c_int32), ("verify", C.c_int32),
+                ("chunk_bytes", C.c_uint64), ("idle_timeout_ms", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("t_start", C.c_uint64), ("t_end", C.c_uint64), ("hash", C.c_uint64),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("op", C.c_int32), ("issuer_pe", C.c_int32), ("target_pe", C.c_int32), ("lane", C.c_int32),
+                ("nbytes", C.c_uint64), ("src_off", C.c_uint64), ("arrival_s", C.c_double)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("wall_s", C.c_double), ("bytes", C.c_uint64), ("amo_ops", C.c_uint64),
+                ("max_reserved_bytes", C.c_uint64), ("admission_waits", C.c_uint64)]
+
+
+vp, i32, u64, sz = C.c_void_p, C.c_int, C.c_uint64, C.c_size_t
+P = C.POINTER
+
+# name: (restype, argtypes)
+SIGNATURES = {
+    "shmemx_init_attach": (i32, [vp, sz, i32, vp]),
+    "shmem_init": (None, []),
+    "shmem_finalize": (None, []),
+    "shmem_n_pes": (i32, []),
+    "shmem_my_pe": (i32, []),
+    "shmem_malloc": (vp, [sz]),
+    "shmemg_malloc": (vp, [sz]),
+    "shmem_calloc": (vp, [sz, sz]),
+    "shmem_align": (vp, [sz, sz]),
+    "shmem_free": (None, [vp]),
+    "shmem_ptr": (vp, [vp, i32]),
+    "shmem_query_capabilities": (i32, [C.c_int32, P(Caps)]),
+    "shmemx_heap_base": (vp, []),
+    "shmemx_heap_stride": (u64, []),
+    "shmemx_heap_user_bytes": (u64, []),
+    "shmemx_device_ctx": (vp, []),
+    "shmem_team_split_strided": (i32, [C.c_int32, i32, i32, i32, vp, C.c_long, P(C.c_int32)]),
+    "shmem_team_n_pes": (i32, [C.c_int32]),
+    "shmemx_team_pe_index": (i32, [C.c_int32, i32]),
+    "shmem_team_destroy": (None, [C.c_int32]),
+    "shmemx_strerror": (C.c_char_p, [i32]),
+    "shmemx_last_error": (i32, []),
+    "shmemx_device_errors": (i32, []),
+    "shmemx_set_wait_timeout_ns": (i32, [u64]),
+    "shmemx_rma_pattern": (i32, [i32, i32, vp, u64, u64, u64, u64, u64, u64, P(Launch), vp]),
+    "shmemx_gups": (i32, [u64, i32, u64, u64, i32, vp, vp, P(Launch), vp]),
+    "shmemx_pingpong": (i32, [u64, u64, vp, i32, i32, u64, i32, vp, vp]),
+    "shmemx_wallclock_hz": (u64, []),
+    "shmemx_wait_until_launch": (i32, [i32, u64, i32, u64, i32, vp, vp]),
+    "shmemx_barrier_launch": (i32, [C.c_int32, i32, u64, vp, vp, vp]),
+    "shmemx_broadcastmem_launch": (i32, [C.c_int32, vp, vp, sz, i32, P(Launch), vp]),
+    "shmemx_fcollectmem_launch": (i32, [C.c_int32, vp, vp, sz, P(Launch), vp]),
+    "shmemx_alltoallmem_launch": (i32, [C.c_int32, vp, vp, sz, P(Launch), vp]),
+    "shmemx_reduce_launch": (i32, [C.c_int32, i32, i32, vp, vp, sz, P(Launch), vp]),
+    "shmemx_tune_default": (None, [P(Tune)]),
+    "shmemx_plan_create": (i32, [vp, sz, P(Tune), P(vp)]),
+    "shmemx_plan_launch_fused": (i32, [vp, vp, vp]),
+    "shmemx_plan_launch_per_op": (i32, [vp, vp, vp]),
+    "shmemx_plan_graph_build": (i32, [vp, i32, vp, vp]),
+    "shmemx_plan_graph_launch": (i32, [vp, vp]),
+    "shmemx_plan_info": (i32, [vp, P(u64), P(u64), P(u64)]),
+    "shmemx_plan_destroy": (None, [vp]),
+    "shmemx_autotune": (i32, [u64, u64, u64, u64, i32, i32, P(Tune), vp]),
+    "shmemx_tune_save": (i32, [P(Tune), C.c_char_p]),
+    "shmemx_tune_load": (i32, [P(Tune), C.c_char_p]),
+    "shmemx_progress_start": (i32, [P(ProgressCfg), vp]),
+    "shmemx_progress_submit": (i32, [P(Desc), P(u64)]),
+    "shmemx_progress_poll": (i32, [u64, P(Completion)]),
+    "shmemx_progress_stop": (i32, [i32]),
+    "shmemx_serve_run": (i32, [P(Request), sz, i32, u64, u64, u64, vp, vp, P(Completion), P(ServeStats)]),
+    "shmemx_fill_random": (i32, [vp, u64, u64, u64, vp]),
+    "shmemx_probe_copy": (i32, [vp, vp, u64, i32, i32, vp]),
+    "shmemx_probe_atomics": (i32, [vp, u64, u64, u64, vp, vp]),
+    "shmemx_probe_xcd": (i32, [vp, i32, vp]),
+    "shmemx_probe_empty": (i32, [vp]),
+    "shmemx_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libvshmem.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libvshmem.so not found at {LIB_PATH}: build it with "
+                          "`python -c 'import __graft_entry__; __graft_entry__.build()'`")
+    lib = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,486 @@
+// Host runtime: symmetric heap, allocator, published device context, teams,
+// capability query and error reporting.
+#include "runtime.hpp"
+
+#include <cctype>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+namespace vshmem {
+
+static State g_state;
+static thread_local int g_last_error = SHMEMX_OK;
+
+State &st() { return g_state; }
+void set_last_error(int code) { g_last_error = code; }
+
+int check_ready()
+{
+    if (!g_state.initialised) {
+        set_last_error(SHMEMX_ERR_STATE);
+        return SHMEMX_ERR_STATE;
+    }
+    return SHMEMX_OK;
+}
+
+shmemx_dctx_pub_t pub()
+{
+    shmemx_dctx_pub_t c{};
+    c.base = g_state.base;
+    c.stride = g_state.stride;
+    c.user_bytes = g_state.user_bytes;
+    c.scratch_off = g_state.user_bytes;
+    c.err = g_state.d_err;
+    c.wait_timeout_ticks = g_state.wait_timeout_ticks;
+    c.npes = g_state.npes;
+    c.debug = g_state.debug;
+    return c;
+}
+
+bool in_user_heap(uint64_t off, uint64_t n)
+{
+    return off <= g_state.user_bytes && n <= g_state.user_bytes - off;
+}
+
+uint64_t sym_offset(const void *p, uint64_t n)
+{
+    uintptr_t a = (uintptr_t)p, b = (uintptr_t)g_state.base;
+    if (a < b) return UINT64_MAX;
+    uint64_t off = a - b;
+    if (!in_user_heap(off, n)) return UINT64_MAX;
+    return off;
+}
+
+int team_get(shmem_team_t t, shmemx_dteam_t *out)
+{
+    if (t < 0 || t >= (int)g_state.teams.size() || !g_state.teams[t].live) return SHMEMX_ERR_ARG;
+    const Team &tm = g_state.teams[t];
+    out->start = tm.start;
+    out->stride = tm.stride;
+    out->size = tm.size;
+    out->slot = tm.slot;
+    return SHMEMX_OK;
+}
+
+bool valid_wg_size(int wg) { return wg >= 64 && wg <= 1024 && (wg % 64) == 0; }
+
+const shmemx_launch_t &launch_or_default(const shmemx_launch_t *l, shmemx_launch_t &tmp, int def_wgs, int def_wg,
+                                         uint64_t def_chunk)
+{
+    tmp = l ? *l : shmemx_launch_t{};
+    if (tmp.wgs_per_pe <= 0) tmp.wgs_per_pe = def_wgs;
+    if (tmp.wg_size <= 0) tmp.wg_size = def_wg;
+    if (tmp.chunk_bytes == 0) tmp.chunk_bytes = def_chunk;
+    return tmp;
+}
+
+// ------------------------------------------------------------- allocator
+void SymAllocator::reset(uint64_t capacity)
+{
+    free_.clear();
+    live_.clear();
+    cap_ = capacity;
+    used_ = 0;
+    if (capacity) free_[0] = capacity;
+}
+
+uint64_t SymAllocator::alloc(uint64_t size, uint64_t align)
+{
+    if (size == 0) return UINT64_MAX;
+    size = (size + kMinAlign - 1) & ~(kMinAlign - 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        uint64_t off = it->first, len = it->second;
+        uint64_t a = (off + align - 1) & ~(align - 1);
+        if (a < off || a - off > len || len - (a - off) < size) continue;
+        uint64_t end = off + len;
+        free_.erase(it);
+        if (a > off) free_[off] = a - off;
+        if (a + size < end) free_[a + size] = end - (a + size);
+        live_[a] = size;
+        used_ += size;
+        return a;
+    }
+    return UINT64_MAX;
+}
+
+bool SymAllocator::free(uint64_t off)
+{
+    auto it = live_.find(off);
+    if (it == live_.end()) return false;
+    uint64_t len = it->second;
+    live_.erase(it);
+    used_ -= len;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + len) {   // merge with the next hole
+        len += nx->second;
+        nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {                           // merge with the previous hole
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == off) {
+            pv->second += len;
+            return true;
+        }
+    }
+    free_[off] = len;
+    return true;
+}
+
+static void reset_teams()
+{
+    g_state.teams.assign(4, Team{});
+    for (int t = 0; t < 4; ++t) {
+        g_state.teams[t].live = true;
+        g_state.teams[t].start = 0;
+        g_state.teams[t].stride = 1;
+        g_state.teams[t].size = g_state.npes;
+        g_state.teams[t].slot = t;
+    }
+}
+
+static uint64_t parse_size(const char *s, uint64_t def)
+{
+    if (!s || !*s) return def;
+    char *end = nullptr;
+    double v = strtod(s, &end);
+    if (end == s || v < 0) return def;
+    uint64_t mul = 1;
+    if (end && *end) {
+        switch (toupper((unsigned char)*end)) {
+        case 'K': mul = 1ull << 10; break;
+        case 'M': mul = 1ull << 20; break;
+        case 'G': mul = 1ull << 30; break;
+        case 'T': mul = 1ull << 40; break;
+        default: mul = 1;
+        }
+    }
+    return (uint64_t)(v * (double)mul);
+}
+
+static int finish_init(void *heap, size_t heap_bytes, int npes, hipStream_t stream)
+{
+    State &s = g_state;
+    s.base = (uint8_t *)heap;
+    s.npes = npes;
+    s.stride = heap_bytes / (uint64_t)npes;
+    s.user_bytes = s.stride - VSHMEM_SCRATCH_BYTES;
+    const char *dbg = getenv("VSHMEM_DEBUG");
+    s.debug = dbg ? atoi(dbg) : 0;
+    VSHMEM_HIP(hipGetDevice(&s.device));
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s.device) == hipSuccess && khz > 0)
+        s.wallclock_hz = (uint64_t)khz * 1000ull;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device) == hipSuccess && cus > 0)
+        s.num_cus = cus;
+    s.wait_timeout_ticks = s.wallclock_hz * 10ull;        // 10 s
+    VSHMEM_HIP(hipMalloc((void **)&s.d_err, 256));
+    VSHMEM_HIP(hipMemsetAsync(s.d_err, 0, 256, stream));
+    for (int p = 0; p < npes; ++p)
+        VSHMEM_HIP(hipMemsetAsync(s.base + (uint64_t)p * s.stride + s.user_bytes, 0, VSHMEM_SCRATCH_BYTES, stream));
+    VSHMEM_HIP(hipMalloc((void **)&s.d_ctx, sizeof(shmemx_dctx_pub_t)));
+    s.heap.reset(s.user_bytes);
+    reset_teams();
+    s.initialised = true;
+    shmemx_dctx_pub_t c = pub();
+    hipError_t e = hipMemcpyAsync(s.d_ctx, &c, sizeof(c), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        s.initialised = false;
+        set_last_error(SHMEMX_ERR_HIP);
+        return SHMEMX_ERR_HIP;
+    }
+    return SHMEMX_OK;
+}
+
+static int republish()
+{
+    shmemx_dctx_pub_t c = pub();
+    VSHMEM_HIP(hipMemcpy(g_state.d_ctx, &c, sizeof(c), hipMemcpyHostToDevice));
+    return SHMEMX_OK;
+}
+
+}  // namespace vshmem
+
+using namespace vshmem;
+
+extern "C" {
+
+int shmemx_init_attach(void *heap, size_t heap_bytes, int npes, void *stream)
+{
+    State &s = st();
+    if (s.initialised) {
+        set_last_error(SHMEMX_ERR_STATE);
+        return SHMEMX_ERR_STATE;
+    }
+    if (!heap || npes <= 0 || npes > 65536 || heap_bytes == 0 || heap_bytes % (uint64_t)npes != 0 ||
+        ((uintptr_t)heap % kSliceAlign) != 0 || (heap_bytes / (uint64_t)npes) % kSliceAlign != 0) {
+        set_last_error(SHMEMX_ERR_ARG);
+        return SHMEMX_ERR_ARG;
+    }
+    s.owns_heap = false;
+    return finish_init(heap, heap_bytes, npes, (hipStream_t)stream);
+}
+
+void shmem_init(void)
+{
+    State &s = st();
+    if (s.initialised) {
+        set_last_error(SHMEMX_ERR_STATE);
+        return;
+    }
+    const char *np = getenv("VSHMEM_NPES");
+    int npes = np ? atoi(np) : 4;
+    uint64_t user = parse_size(getenv("VSHMEM_SYMMETRIC_SIZE"), 64ull << 20);
+    if (npes <= 0 || user == 0) {
+        set_last_error(SHMEMX_ERR_ARG);
+        return;
+    }
+    uint64_t stride = (user + VSHMEM_SCRATCH_BYTES + kSliceAlign - 1) & ~(kSliceAlign - 1);
+    void *heap = nullptr;
+    if (hipMalloc(&heap, stride * (uint64_t)npes) != hipSuccess) {
+        set_last_error(SHMEMX_ERR_NOMEM);
+        return;
+    }
+    s.owns_heap = true;
+    if (finish_init(heap, stride * (uint64_t)npes, npes, nullptr) != SHMEMX_OK) {
+        (void)hipFree(heap);
+        s.owns_heap = false;
+    }
+}
+
+void shmem_finalize(void)
+{
+    State &s = st();
+    if (!s.initialised) {
+        set_last_error(SHMEMX_ERR_STATE);
+        return;
+    }
+    (void)hipDeviceSynchronize();
+    if (s.d_ctx) (void)hipFree(s.d_ctx);
+    if (s.d_err) (void)hipFree(s.d_err);
+    if (s.owns_heap && s.base) (void)hipFree(s.base);
+    s = State{};
+}
+
+int shmem_n_pes(void) { return st().initialised ? st().npes : 0; }
+int shmem_my_pe(void) { return st().initialised ? 0 : -1; }
+
+void *shmem_align(size_t alignment, size_t size)
+{
+    State &s = st();
+    if (!s.initialised || size == 0 || alignment == 0 || (alignment & (alignment - 1))) {
+        set_last_error(s.initialised ? SHMEMX_ERR_ARG : SHMEMX_ERR_STATE);
+        return nullptr;
+    }
+    if (alignment < kMinAlign) alignment = kMinAlign;
+    uint64_t off = s.heap.alloc(size, alignment);
+    if (off == UINT64_MAX) {
+        set_last_error(SHMEMX_ERR_NOMEM);
+        return nullptr;
+    }
+    return s.base + off;
+}
+
+void *shmem_malloc(size_t size) { return shmem_align(kMinAlign, size); }
+void *shmemg_malloc(size_t size) { return shmem_align(kMinAlign, size); }
+
+void *shmem_calloc(size_t count, size_t size)
+{
+    if (count && size > SIZE_MAX / count) {
+        set_last_error(SHMEMX_ERR_ARG);
+        return nullptr;
+    }
+    void *p = shmem_malloc(count * size);
+    if (!p) return nullptr;
+    State &s = st();
+    for (int pe = 0; pe < s.npes; ++pe) {
+        if (hipMemsetAsync((uint8_t *)p + (uint64_t)pe * s.stride, 0, count * size, nullptr) != hipSuccess) {
+            set_last_error(SHMEMX_ERR_HIP);
+            shmem_free(p);
+            return nullptr;
+        }
+    }
+    if (hipStreamSynchronize(nullptr) != hipSuccess) {
+        set_last_error(SHMEMX_ERR_HIP);
+        shmem_free(p);
+        return nullptr;
+    }
+    return p;
+}
+
+void shmem_free(void *ptr)
+{
+    State &s = st();
+    if (!ptr) return;
+    if (!s.initialised) {
+        set_last_error(SHMEMX_ERR_STATE);
+        return;
+    }
+    uintptr_t a = (uintptr_t)ptr, b = (uintptr_t)s.base;
+    if (a < b || a - b >= s.user_bytes || !s.heap.free(a - b)) set_last_error(SHMEMX_ERR_ARG);
+}
+
+void *shmem_ptr(const void *sym, int pe)
+{
+    State &s = st();
+    if (!s.initialised || pe < 0 || pe >= s.npes) return nullptr;
+    uintptr_t a = (uintptr_t)sym, b = (uintptr_t)s.base;
+    if (a < b || a - b >= s.user_bytes) return nullptr;
+    return (uint8_t *)sym + (uint64_t)pe * s.stride;
+}
+
+int shmem_query_capabilities(shmem_team_t team, shmemx_caps_t *caps)
+{
+    if (int rc = check_ready()) return rc;
+    shmemx_dteam_t t;
+    if (!caps || team_get(team, &t) != SHMEMX_OK) {
+        set_last_error(SHMEMX_ERR_ARG);
+        return SHMEMX_ERR_ARG;
+    }
+    State &s = st();
+    memset(caps, 0, sizeof(*caps));
+    caps->gpu_heap = 1;
+    caps->default_heap_is_gpu = 1;
+    caps->host_initiated = 0;
+    caps->device_initiated = 1;
+    caps->device_ctx_default = 1;
+    caps->explicit_device_ctx = 0;
+    caps->scopes = (1u << SHMEMX_SCOPE_THREAD) | (1u << SHMEMX_SCOPE_WAVE) | (1u << SHMEMX_SCOPE_WG) |
+                   (1u << SHMEMX_SCOPE_GRID);
+    caps->device_collectives = 1;
+    caps->stream_triggered = 0;
+    caps->progress = SHMEMX_PROGRESS_KERNEL_LAUNCH | SHMEMX_PROGRESS_PERSISTENT_GPU;
+    caps->path = SHMEMX_PATH_SINGLE_GPU_LOADSTORE;
+    caps->ptr_domain = SHMEMX_PTR_DOMAIN_DEVICE;
+    caps->team_npes = t.size;
+    caps->team_start = t.start;
+    caps->team_stride = t.stride;
+    caps->npes = s.npes;
+    caps->heap_user_bytes = s.user_bytes;
+    caps->heap_stride = s.stride;
+    caps->debug = s.debug;
+    return SHMEMX_OK;
+}
+
+void *shmemx_heap_base(void) { return st().initialised ? st().base : nullptr; }
+uint64_t shmemx_heap_stride(void) { return st().initialised ? st().stride : 0; }
+uint64_t shmemx_heap_user_bytes(void) { return st().initialised ? st().user_bytes : 0; }
+const void *shmemx_device_ctx(void) { return st().initialised ? st().d_ctx : nullptr; }
+uint64_t shmemx_wallclock_hz(void) { return st().wallclock_hz; }
+
+int shmem_team_split_strided(shmem_team_t parent, int start, int stride, int size, const void *config,
+                             long config_mask, shmem_team_t *new_team)
+{
+    (void)config;
+    (void)config_mask;
+    if (int rc = check_ready()) return rc;
+    shmemx_dteam_t p;
+    if (!new_team || team_get(parent, &p) != SHMEMX_OK || size <= 0 || start < 0 || stride <= 0 ||
+        start + (int64_t)(size - 1) * stride >= p.size) {
+        if (new_team) *new_team = SHMEM_TEAM_INVALID;
+        set_last_error(SHMEMX_ERR_ARG);
+        return SHMEMX_ERR_ARG;
+    }
+    State &s = st();
+    int idx = -1;
+    for (int i = 4; i < (int)s.teams.size(); ++i)
+        if (!s.teams[i].live) {
+            idx = i;
+            break;
+        }
+    if (idx < 0) {
+        if ((int)s.teams.size() >= VSHMEM_MAX_TEAMS - 8) {
+            *new_team = SHMEM_TEAM_INVALID;
+            set_last_error(SHMEMX_ERR_NOMEM);
+            return SHMEMX_ERR_NOMEM;
+        }
+        idx = (int)s.teams.size();
+        s.teams.push_back(Team{});
+    }
+    Team &t = s.teams[idx];
+    t.live = true;
+    t.start = p.start + start * p.stride;
+    t.stride = p.stride * stride;
+    t.size = size;
+    t.slot = idx;
+    // Clear the new team's barrier words in its first member's scratch.
+    uint64_t *slot = (uint64_t *)(s.base + (uint64_t)t.start * s.stride + s.user_bytes +
+                                  (uint64_t)t.slot * VSHMEM_SYNC_SLOT_BYTES);
+    if (hipMemset(slot, 0, VSHMEM_SYNC_SLOT_BYTES) != hipSuccess) {
+        t.live = false;
+        set_last_error(SHMEMX_ERR_HIP);
+        return SHMEMX_ERR_HIP;
+    }
+    *new_team = idx;
+    return SHMEMX_OK;
+}
+
+int shmem_team_n_pes(shmem_team_t team)
+{
+    shmemx_dteam_t t;
+    if (!st().initialised || team_get(team, &t) != SHMEMX_OK) return -1;
+    return t.size;
+}
+
+int shmemx_team_pe_index(shmem_team_t team, int pe)
+{
+    shmemx_dteam_t t;
+    if (!st().initialised || team_get(team, &t) != SHMEMX_OK) return -1;
+    int d = pe - t.start;
+    if (d < 0 || d % t.stride) return -1;
+    int k = d / t.stride;
+    return k < t.size ? k : -1;
+}
+
+void shmem_team_destroy(shmem_team_t team)
+{
+    State &s = st();
+    if (!s.initialised || team < 4 || team >= (int)s.teams.size()) {
+        set_last_error(SHMEMX_ERR_ARG);
+        return;
+    }
+    s.teams[team].live = false;
+}
+
+const char *shmemx_strerror(int code)
+{
+    switch (code) {
+    case SHMEMX_OK: return "success";
+    case SHMEMX_ERR_ARG: return "invalid argument";
+    case SHMEMX_ERR_NOMEM: return "out of memory or budget";
+    case SHMEMX_ERR_STATE: return "library not in the required state";
+    case SHMEMX_ERR_HIP: return "HIP runtime error";
+    case SHMEMX_ERR_BUSY: return "resource busy";
+    case SHMEMX_ERR_TIMEOUT: return "timed out";
+    case SHMEMX_ERR_DEVICE: return "device reported an error";
+    case SHMEMX_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+    }
+}
+
+int shmemx_last_error(void) { return vshmem::g_last_error; }
+
+int shmemx_device_errors(void)
+{
+    if (int rc = check_ready()) return rc;
+    uint32_t v = 0;
+    VSHMEM_HIP(hipDeviceSynchronize());
+    VSHMEM_HIP(hipMemcpy(&v, st().d_err, 4, hipMemcpyDeviceToHost));
+    VSHMEM_HIP(hipMemset(st().d_err, 0, 4));
+    return (int)(v & 0x7fffffffu);
+}
+
+int shmemx_set_wait_timeout_ns(uint64_t ns)
+{
+    if (int rc = check_ready()) return rc;
+    State &s = st();
+    uint64_t ticks = (uint64_t)((double)ns * (double)s.wallclock_hz / 1e9);
+    s.wait_timeout_ticks = ticks ? ticks : 1;
+    return republish();
+}
+
+const char *shmemx_version(void) { return "vshmem 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal host-side state shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "vshmem.h"
+#include "vshmem_device.hpp"
+
+namespace vshmem {
+
+constexpr uint64_t kSliceAlign = 2ull << 20;      // PE slices are 2 MiB aligned
+constexpr uint64_t kMinAlign = 256;               // default allocation alignment
+constexpr int kTeamSlotPlan = 250;                // grid barrier of fused plans
+constexpr int kTeamSlotColl = 251;                // spare
+
+struct Team {
+    bool live = false;
+    int start = 0, stride = 1, size = 0;
+    int slot = 0;
+};
+
+// First-fit allocator over [0, capacity) with a coalescing free list.  The
+// same call sequence always yields the same offsets: allocation is
+// symmetric by construction because one offset names the object on every PE.
+class SymAllocator {
+  public:
+    void reset(uint64_t capacity);
+    // Returns the offset or UINT64_MAX.
+    uint64_t alloc(uint64_t size, uint64_t align);
+    bool free(uint64_t off);
+    uint64_t used() const { return used_; }
+    uint64_t capacity() const { return cap_; }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;   // offset -> length
+    std::map<uint64_t, uint64_t> live_;   // offset -> length
+    uint64_t cap_ = 0, used_ = 0;
+};
+
+struct State {
+    bool initialised = false;
+    bool owns_heap = false;
+    int device = 0;
+    uint8_t *base = nullptr;
+    uint64_t stride = 0;
+    uint64_t user_bytes = 0;
+    int npes = 0;
+    int debug = 0;
+    uint32_t *d_err = nullptr;
+    shmemx_dctx_pub_t *d_ctx = nullptr;     // published, GPU-visible copy
+    uint64_t wait_timeout_ticks = 0;
+    uint64_t wallclock_hz = 100000000ull;
+    int num_cus = 256;
+    SymAllocator heap;
+    std::vector<Team> teams;
+};
+
+State &st();
+void set_last_error(int code);
+int check_ready();
+shmemx_dctx_pub_t pub();
+int team_get(shmem_team_t t, shmemx_dteam_t *out);
+bool in_user_heap(uint64_t off, uint64_t n);
+// Offset of a canonical symmetric address, or UINT64_MAX if outside PE 0's user range.
+uint64_t sym_offset(const void *p, uint64_t n);
+const shmemx_launch_t &launch_or_default(const shmemx_launch_t *l, shmemx_launch_t &tmp, int def_wgs,
+                                         int def_wg, uint64_t def_chunk);
+bool valid_wg_size(int wg);
+
+}  // namespace vshmem
+
+#define VSHMEM_HIP(call)                                                                                  \
+    do {                                                                                                  \
+        hipError_t e_ = (call);                                                                           \
+        if (e_ != hipSuccess) {                                                                           \
+            vshmem::set_last_error(SHMEMX_ERR_HIP);                                                       \
+            return SHMEMX_ERR_HIP;                                                                        \
+        }                                                                                                 \
+    } while (0)

@@ -1,0 +1,90 @@
+"""CPU-side checks of the C-ABI boundary: the library loads, exports every
+function include/vshmem.h declares, the binding declares exactly those, and
+host-side argument and state errors are reported without touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vshmem.h")
+LIB = os.path.join(ROOT, "paper_2607_08006_amd", "libvshmem.so")
+
+
+def _ensure_built():
+    if not os.path.exists(LIB):
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("vbuild", os.path.join(ROOT, "paper_2607_08006_amd", "build.py"))
+        m = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(m)
+        m.build()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    src = re.sub(r"#[^\n]*", "", src)
+    # drop typedef/struct bodies
+    src = re.sub(r"typedef\s+struct\s+\w*\s*\{.*?\}\s*\w+\s*;", "", src, flags=re.S)
+    names = re.findall(r"\b([A-Za-z_]\w*)\s*\([^;{}]*\)\s*;", src)
+    return sorted(set(n for n in names if n.startswith("shmem")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("shmemx_init_attach", "shmem_init", "shmem_finalize", "shmem_n_pes", "shmem_my_pe",
+                 "shmem_malloc", "shmemg_malloc", "shmem_free", "shmem_ptr", "shmem_query_capabilities",
+                 "shmemx_rma_pattern", "shmemx_gups", "shmemx_pingpong", "shmemx_barrier_launch",
+                 "shmemx_broadcastmem_launch", "shmemx_fcollectmem_launch", "shmemx_alltoallmem_launch",
+                 "shmemx_reduce_launch", "shmemx_plan_create", "shmemx_plan_launch_fused",
+                 "shmemx_plan_launch_per_op", "shmemx_plan_graph_build", "shmemx_autotune",
+                 "shmemx_progress_start", "shmemx_progress_submit", "shmemx_serve_run"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    _ensure_built()
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+def test_binding_declares_exactly_the_header():
+    _ensure_built()
+    from paper_2607_08006_amd import _native
+    assert sorted(_native.SIGNATURES) == declared_functions()
+
+
+def test_struct_sizes_match_header():
+    from paper_2607_08006_amd import _native
+    assert ctypes.sizeof(_native.Desc) == 64
+    assert ctypes.sizeof(_native.Launch) == 24
+    assert ctypes.sizeof(_native.Completion) == 40
+    import workload
+    assert workload.DESC_DTYPE.itemsize == ctypes.sizeof(_native.Desc)
+    for f, _ in _native.Desc._fields_:
+        name = {"issuer_pe": "issuer", "target_pe": "target"}.get(f, f)
+        assert workload.DESC_DTYPE.fields[name][1] == getattr(_native.Desc, f).offset
+
+
+def test_calls_before_init_fail_cleanly():
+    _ensure_built()
+    import paper_2607_08006_amd as v
+    lib = v.lib
+    assert lib.shmem_n_pes() == 0
+    assert lib.shmem_my_pe() == -1
+    assert not lib.shmem_malloc(64)
+    assert lib.shmemx_last_error() == v.ERR_STATE
+    assert lib.shmemx_rma_pattern(1, 2, None, 0, 0, 8, 1, 8, 8, None, None) == v.ERR_STATE
+    assert lib.shmemx_gups(0, 10, 1, 1, 5, None, None, None, None) == v.ERR_STATE
+    caps = v.Caps()
+    assert lib.shmem_query_capabilities(0, ctypes.byref(caps)) == v.ERR_STATE
+    assert lib.shmemx_device_errors() == v.ERR_STATE
+    assert lib.shmemx_init_attach(None, 1 << 21, 1, None) == v.ERR_ARG
+    assert lib.shmemx_init_attach(ctypes.c_void_p(1 << 21), 3 << 20, 2, None) == v.ERR_ARG   # odd split
+    assert lib.shmemx_strerror(v.ERR_TIMEOUT).decode() == "timed out"
+    assert v.version().startswith("vshmem")

@@ -1,0 +1,147 @@
+"""GPU parity: team collectives (broadcast, fcollect, alltoall, reductions)
+against the CPU oracle, bit-exact (including fp32 and bf16, whose order is
+the documented TREE on both sides)."""
+import numpy as np
+import pytest
+
+import oracle
+import workload as W
+from tests.gpu_helpers import assert_no_device_errors, download, heap, upload
+
+pytestmark = pytest.mark.gpu
+
+LAUNCHES = [dict(wgs_per_pe=2, wg_size=128, chunk_bytes=4096), dict(wgs_per_pe=1, wg_size=256, chunk_bytes=65536),
+            dict(wgs_per_pe=3, wg_size=64, chunk_bytes=16, flags=1)]
+
+
+@pytest.mark.parametrize("npes", [1, 2, 5, 8])
+def test_data_movement_collectives(npes):
+    with heap(npes, 4 << 20) as v:
+        src = v.malloc(1 << 20)
+        dst = v.malloc(2 << 20)
+        so, do = v.offset(src), v.offset(dst)
+        region = do + (2 << 20)
+        init = W.heap_fill(W.SEED_COLL + npes, npes, region)
+        for li, L in enumerate(LAUNCHES):
+            launch = v.launch_cfg(**L)
+            for n in (1, 40, 4096 + 24, 100_003):
+                # broadcast from every root index
+                root = (n + li) % npes
+                upload(init)
+                v.broadcastmem(dst, src, n, root, launch=launch)
+                got = download(region)
+                ref = init.copy()
+                oracle.broadcast(ref, do, so, n, root)
+                assert np.array_equal(got, ref), ("broadcast", n, root, L)
+                if n * npes <= (1 << 20):
+                    upload(init)
+                    v.fcollectmem(dst, src, n, launch=launch)
+                    got = download(region)
+                    ref = init.copy()
+                    oracle.fcollect(ref, do, so, n)
+                    assert np.array_equal(got, ref), ("fcollect", n, L)
+                    upload(init)
+                    v.alltoallmem(dst, src, n, launch=launch)
+                    got = download(region)
+                    ref = init.copy()
+                    oracle.alltoall(ref, do, so, n)
+                    assert np.array_equal(got, ref), ("alltoall", n, L)
+        assert_no_device_errors()
+
+
+def test_alltoall_tags_transpose_and_involution():
+    npes, n = 6, 1000
+    with heap(npes, 1 << 20) as v:
+        a = v.malloc(npes * n)
+        b = v.malloc(npes * n)
+        tags = np.zeros((npes, v.offset(b) + npes * n), dtype=np.uint8)
+        for q in range(npes):
+            for p in range(npes):
+                tags[q, v.offset(a) + p * n: v.offset(a) + (p + 1) * n] = 16 * q + p
+        upload(tags)
+        v.alltoallmem(b, a, n)
+        v.alltoallmem(a, b, n)
+        got = download(tags.shape[1])
+        for p in range(npes):
+            for q in range(npes):
+                assert np.all(got[p, v.offset(b) + q * n: v.offset(b) + (q + 1) * n] == 16 * q + p)
+        assert np.array_equal(got[:, v.offset(a):v.offset(a) + npes * n], tags[:, v.offset(a):v.offset(a) + npes * n])
+
+
+def _red_inputs(dt, npes, nreduce, seed):
+    if dt == oracle.DT_INT64:
+        rows = [W.coll_i64(seed, p, nreduce).view(np.uint8) for p in range(npes)]
+    elif dt == oracle.DT_FP32:
+        rows = [W.coll_f32(seed, p, nreduce).view(np.uint8) for p in range(npes)]
+    else:
+        rows = [W.coll_bf16(seed, p, nreduce).view(np.uint8) for p in range(npes)]
+    return np.stack(rows)
+
+
+@pytest.mark.parametrize("dt", [oracle.DT_INT64, oracle.DT_FP32, oracle.DT_BF16])
+@pytest.mark.parametrize("rop", [oracle.RO_SUM, oracle.RO_MAX])
+def test_reductions_bit_exact(dt, rop):
+    es = {oracle.DT_INT64: 8, oracle.DT_FP32: 4, oracle.DT_BF16: 2}[dt]
+    for npes in (1, 3, 8, 13):
+        with heap(npes, 2 << 20) as v:
+            nmax = 70_001
+            src = v.malloc(nmax * es)
+            dst = v.malloc(nmax * es)
+            so, do = v.offset(src), v.offset(dst)
+            region = do + nmax * es
+            for nreduce in (1, 7, 1000, nmax):
+                init = np.zeros((npes, region), dtype=np.uint8)
+                init[:, so:so + nreduce * es] = _red_inputs(dt, npes, nreduce, 1000 * npes + nreduce)
+                for L in (dict(wgs_per_pe=2, wg_size=256, chunk_bytes=4096), dict(wgs_per_pe=1, wg_size=64)):
+                    upload(init)
+                    v.reduce(dt, rop, dst, src, nreduce, launch=v.launch_cfg(**L))
+                    got = download(region)
+                    ref = init.copy()
+                    oracle.reduce(ref, dt, rop, do, so, nreduce)
+                    assert np.array_equal(got, ref), (dt, rop, npes, nreduce, L)
+            # in place
+            init = np.zeros((npes, region), dtype=np.uint8)
+            init[:, so:so + 999 * es] = _red_inputs(dt, npes, 999, 7)
+            upload(init)
+            v.reduce(dt, rop, src, src, 999)
+            got = download(region)
+            ref = init.copy()
+            oracle.reduce(ref, dt, rop, so, so, 999)
+            assert np.array_equal(got, ref)
+            assert_no_device_errors()
+
+
+def test_strided_team_collectives():
+    npes = 10
+    with heap(npes, 2 << 20) as v:
+        team = v.team_split_strided(v.DEVICE_TEAM_WORLD, 1, 2, 4)       # PEs 1, 3, 5, 7
+        tri = (1, 2, 4)
+        src = v.malloc(64 << 10)
+        dst = v.malloc(256 << 10)
+        so, do = v.offset(src), v.offset(dst)
+        region = do + (256 << 10)
+        init = W.heap_fill(99, npes, region)
+        n = 10_000
+        upload(init)
+        v.alltoallmem(dst, src, n // 4, team=team)
+        got = download(region)
+        ref = init.copy()
+        oracle.alltoall(ref, do, so, n // 4, team=tri)
+        assert np.array_equal(got, ref)
+        upload(init)
+        v.broadcastmem(dst, src, n, 3, team=team)
+        got = download(region)
+        ref = init.copy()
+        oracle.broadcast(ref, do, so, n, 3, team=tri)
+        assert np.array_equal(got, ref)
+        init2 = np.zeros((npes, region), dtype=np.uint8)
+        init2[:, so:so + 4 * 3000] = _red_inputs(oracle.DT_FP32, npes, 3000, 5)
+        upload(init2)
+        v.reduce(v.DT_FP32, v.RED_SUM, dst, src, 3000, team=team)
+        got = download(region)
+        ref = init2.copy()
+        oracle.reduce(ref, oracle.DT_FP32, oracle.RO_SUM, do, so, 3000, team=tri)
+        assert np.array_equal(got, ref)
+        with pytest.raises(v.VshmemError):
+            v.alltoallmem(dst, dst + 8, 64)                  # overlapping ranges
+        assert_no_device_errors()
