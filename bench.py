@@ -1,0 +1,442 @@
+#!/usr/bin/env python3
+"""Benchmark of the device-initiated SHMEM hot path on one MI355X.
+
+One step is one pass of every hot-path row over one batch of synthetic
+input on 64 virtual PEs with a 1 GiB symmetric heap each: put/get at
+work-group, wavefront and thread scope (ring and derangement patterns, each
+ending in quiet), random-access atomics, put-with-signal ping-pong, barrier,
+broadcast, fcollect, alltoall, sum/max reductions (int64, fp32, bf16 with fp32
+accumulation), a batch of mixed operations in its fused, per-operation and
+hipGraph forms, and the persistent progress kernel serving a request burst.
+
+Prints one JSON line.  `value` is the whole step's algorithmic HBM traffic
+(bytes read + written by the operations' definitions) divided by the step
+time.  Per-row figures, the latency comparison and the roofline of the
+dominant kernel ride along in the same line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workload as W  # noqa: E402
+
+MiB = 1 << 20
+GiB = 1 << 30
+HBM_PEAK_GBS = 8000.0
+METRIC = "put/get/alltoall GB/s vs HBM peak; AMO Mops/s; p50/p99 op latency batched vs per-op"
+
+
+def log(msg: str) -> None:
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--npes", type=int, default=64)
+    ap.add_argument("--heap-mib", type=int, default=1024)
+    ap.add_argument("--rows", default="", help="comma-separated subset of rows (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--probe-copy-mib", type=int, default=0,
+                    help="also run one plain copy of this size (counter scaling reference)")
+    ap.add_argument("--out", default="", help="also write the JSON line to this file")
+    return ap.parse_args()
+
+
+class Layout:
+    """Per-PE heap layout (offsets in bytes, identical on every PE)."""
+
+    def __init__(self, v, heap_mib: int):
+        scale = heap_mib / 1024.0
+        sz = lambda mib: int(mib * scale) * MiB  # noqa: E731
+        self.A = v.offset(v.malloc(sz(256)))   # put/get source (uint8 payload)
+        self.B = v.offset(v.malloc(sz(256)))   # destinations of put/get and collectives
+        self.C = v.offset(v.malloc(sz(256)))   # broadcast / fcollect / alltoall sources
+        self.D = v.offset(v.malloc(sz(128)))   # int64 reduction input
+        self.E = v.offset(v.malloc(sz(64)))    # fp32 reduction input
+        self.F = v.offset(v.malloc(sz(32)))    # bf16 reduction input
+        self.G = v.offset(v.malloc(sz(16)))    # GUPS table slice
+        self.H = v.offset(v.malloc(sz(16)))    # batch, ping-pong, barrier area
+        self.scale = scale
+        self.addr = lambda off: v.heap_base() + off  # noqa: E731
+
+
+def fill_heap(v, L: Layout, npes: int):
+    base = v.heap_base()
+    stride = v.heap_stride()
+    for p in range(npes):
+        pe = base + p * stride
+        v.fill_random(pe + L.A, L.B - L.A, W.subseed(W.SEED_SWEEP, W.TAG_HEAP + p))
+        v.fill_random(pe + L.B, L.C - L.B, W.subseed(W.SEED_SWEEP, 0x200 + p))
+        v.fill_typed(pe + L.C, (L.D - L.C) // 4, v.DT_FP32, W.subseed(W.SEED_COLL, W.TAG_HEAP + p))
+        v.fill_typed(pe + L.D, (L.E - L.D) // 8, v.DT_INT64, W.subseed(W.SEED_COLL, 0x300 + p))
+        v.fill_typed(pe + L.E, (L.F - L.E) // 4, v.DT_FP32, W.subseed(W.SEED_COLL, 0x400 + p))
+        v.fill_typed(pe + L.F, (L.G - L.F) // 2, v.DT_BF16, W.subseed(W.SEED_COLL, 0x500 + p))
+        v.fill_typed(pe + L.G, (L.H - L.G) // 8, v.DT_INT64, W.subseed(W.SEED_GUPS, W.TAG_HEAP + p))
+        v.fill_random(pe + L.H, int(16 * MiB * L.scale), W.subseed(W.SEED_SMALL, W.TAG_HEAP + p))
+
+
+class Row:
+    def __init__(self, name, fn, bytes_=0, ops=0, kernel=""):
+        self.name, self.fn, self.bytes, self.ops, self.kernel = name, fn, bytes_, ops, kernel
+        self.ms = []
+
+
+def build_rows(v, torch, L: Layout, npes: int, want):
+    rows = []
+    scale = L.scale
+    ring = torch.from_numpy(W.ring(npes).astype(np.int32)).cuda()
+    perm = torch.from_numpy(W.derangement(W.subseed(W.SEED_SWEEP, W.TAG_PERM), npes).astype(np.int32)).cuda()
+
+    def add(name, fn, b=0, ops=0, kernel=""):
+        if not want or name in want:
+            rows.append(Row(name, fn, b, ops, kernel))
+
+    # ---- put/get (a2, a3): k(s) = min(2^28 / s, 2^14) messages per PE, each PE ends in quiet
+    def rma(op, scope, tgts, size, wgs, wg, nmsg=None):
+        k = nmsg if nmsg is not None else W.msgs_per_pe(size)
+        span = L.B - L.A
+        while k * size > span:
+            k //= 2
+        lc = v.launch_cfg(wgs_per_pe=wgs, wg_size=wg)
+        return (lambda: v.rma_pattern(op, scope, tgts, L.A, L.B, size, k, launch=lc)), 2 * npes * k * size
+
+    big = int(16 * MiB * min(1.0, scale))
+    f, b = rma(v.OP_PUT, v.SCOPE_WG, ring, big, 16, 512)
+    add("put_wg_16MiB_ring", f, b, kernel="k_rma_pattern<2,true,false>")
+    f, b = rma(v.OP_GET, v.SCOPE_WG, perm, big, 16, 512)
+    add("get_wg_16MiB_perm", f, b, kernel="k_rma_pattern<2,false,false>")
+    f, b = rma(v.OP_PUT, v.SCOPE_WAVE, perm, 4096, 16, 256)
+    add("put_wave_4KiB_perm", f, b)
+    f, b = rma(v.OP_GET, v.SCOPE_THREAD, ring, 64, 4, 256)
+    add("get_thread_64B_ring", f, b)
+    f, b = rma(v.OP_PUT, v.SCOPE_THREAD, perm, 8, 4, 256)
+    add("put_thread_8B_perm", f, b)
+
+    # ---- atomics (a4): 2^26 random fetch_xor / fetch_add updates on a 2^27-entry table
+    log2_table = 27 if scale >= 1.0 else max(10, 27 - int(np.ceil(np.log2(1 / scale))))
+    nupd = 1 << (log2_table - 1)
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gseed = W.subseed(W.SEED_GUPS, W.TAG_OPS)
+    add("gups_fetch_xor_add", lambda: v.gups(L.G, log2_table, nupd, gseed, 5, acc=acc), 16 * nupd, nupd)
+
+    # ---- signal ping-pong (a5): 32 pairs, 200 round trips, 8-byte payload
+    npairs, rounds = min(32, npes // 2), 200
+    pairs = torch.arange(2 * npairs, dtype=torch.int32, device="cuda")
+    rtt = torch.zeros(npairs * rounds, dtype=torch.int64, device="cuda")
+    add("pingpong_signal_8B", lambda: v.pingpong(L.H, L.H + 64, pairs, npairs, rounds, 8, False, rtt),
+        0, 2 * npairs * rounds)
+
+    # ---- barrier (a6)
+    add("barrier_all", lambda: v.barrier(v.DEVICE_TEAM_WORLD, iters=100), 0, 100)
+
+    # ---- collectives (a7-a10)
+    blk = int(1 * MiB * min(1.0, scale))
+    add("alltoall_1MiB_fp32", lambda: v.alltoallmem(L.addr(L.B), L.addr(L.C), blk), 2 * npes * npes * blk,
+        kernel="k_alltoall<false>")
+    fc = int(4 * MiB * min(1.0, scale))
+    add("fcollect_4MiB", lambda: v.fcollectmem(L.addr(L.B), L.addr(L.C), fc), npes * fc + npes * npes * fc)
+    bc = L.D - L.C
+    add("broadcast_256MiB", lambda: v.broadcastmem(L.addr(L.B), L.addr(L.C), bc, 0), bc + npes * bc)
+    nred = (L.E - L.D) // 8
+    for dt, src, es, tag in ((v.DT_INT64, L.D, 8, "i64"), (v.DT_FP32, L.E, 4, "f32"), (v.DT_BF16, L.F, 2, "bf16")):
+        n = min(nred, (L.G - src) // es) if dt != v.DT_INT64 else nred
+        add(f"reduce_sum_{tag}", (lambda dt=dt, src=src, n=n: v.reduce(dt, v.RED_SUM, L.addr(L.B), L.addr(src), n)),
+            2 * npes * n * es)
+    add("reduce_max_i64", lambda: v.reduce(v.DT_INT64, v.RED_MAX, L.addr(L.B), L.addr(L.D), nred), 2 * npes * nred * 8)
+    add("reduce_max_f32", lambda: v.reduce(v.DT_FP32, v.RED_MAX, L.addr(L.B), L.addr(L.E), nred),
+        2 * npes * nred * 4)
+    return rows
+
+
+def batch_setup(v, torch, L: Layout, npes: int):
+    """A burst of 1000 uneven put/get and 1000 fetch_add over all PEs, with
+    completion stamps for the fused, per-op and graph forms."""
+    region = int(16 * MiB * L.scale) - 4 * 4096
+    wl = W.small_workload(npes=npes, heap_bytes=region, n_rma=1000, epoch_ops=1000, n_amo=1000,
+                          base_off=L.H + 4 * 4096, fill=False)
+    nd = len(wl.descs)
+    res = torch.zeros(wl.n_amo, dtype=torch.int64, device="cuda")
+    st = {k: torch.zeros(nd, dtype=torch.int64, device="cuda") for k in ("fused", "per_op", "graph")}
+    t0 = {k: torch.zeros(1, dtype=torch.int64, device="cuda") for k in ("fused", "per_op", "graph")}
+    plan = v.Plan(wl.descs)
+    plan_graph = v.Plan(wl.descs)
+    plan_graph.set_stamps(st["graph"])
+    plan_graph.graph_build(1, results=res)
+    ops = wl.descs["op"]
+    is_op = (ops == W.OP_PUT) | (ops == W.OP_GET) | (ops == W.OP_AMO_FETCH_ADD)
+    payload = int(wl.descs["nbytes"][(ops == W.OP_PUT) | (ops == W.OP_GET)].sum())
+    return dict(wl=wl, plan=plan, graph=plan_graph, res=res, stamps=st, t0=t0, is_op=is_op,
+                bytes=2 * payload + 16 * wl.n_amo, nops=int(is_op.sum()))
+
+
+def batch_step(v, B):
+    """One burst in each form; returns nothing (stamps stay on the device)."""
+    for k in ("fused", "per_op", "graph"):
+        B["stamps"][k].zero_()
+    plan = B["plan"]
+    v.stamp(B["t0"]["fused"])
+    plan.set_stamps(B["stamps"]["fused"])
+    plan.launch_fused(results=B["res"])
+    v.stamp(B["t0"]["per_op"])
+    plan.set_stamps(B["stamps"]["per_op"])
+    plan.launch_per_op(results=B["res"])
+    v.stamp(B["t0"]["graph"])
+    B["graph"].graph_launch()
+
+
+def batch_latencies(v, B):
+    hz = v.wallclock_hz()
+    out = {}
+    for k in ("fused", "per_op", "graph"):
+        st = B["stamps"][k].cpu().numpy()[B["is_op"]]
+        t0 = int(B["t0"][k].cpu().numpy()[0])
+        out[k] = (st - t0) / hz * 1e6        # microseconds from burst submission to op completion
+    return out
+
+
+def percentile(a, q):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for d in ("paper_2607_08006_amd/csrc", "include"):
+        for fn in sorted(os.listdir(os.path.join(ROOT, d))):
+            with open(os.path.join(ROOT, d, fn), "rb") as f:
+                h.update(fn.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel: str, launches_bytes: int):
+    """HBM traffic of the dominant kernel from the committed counter summary,
+    or None when there is none or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        ent = d.get("kernels", {}).get(kernel)
+        if not ent or d.get("source_digest") != source_digest():
+            return None
+        return int(ent["fetch_bytes"] + ent["write_bytes"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(seconds: float):
+    """Time the CPU oracle (single thread, as written) on bounded samples of
+    the step's rows and report algorithmic GB/s."""
+    import oracle
+    samples = []
+    # put ring, 16 MiB messages: 4 PEs x 4 messages
+    npes, msg, k = 4, 16 * MiB, 4
+    heap = np.zeros((npes, 2 * k * msg), dtype=np.uint8)
+    heap[:, :k * msg] = np.frombuffer(np.random.default_rng(1).bytes(npes * k * msg), dtype=np.uint8).reshape(npes, -1)
+    recs = [(W.OP_PUT, 0, 0, p, (p + 1) % npes, W.NO_RESULT, j * msg, k * msg + j * msg, msg, 0, 0)
+            for p in range(npes) for j in range(k)]
+    d = W.descs(recs)
+    samples.append(("put_ring_16MiB 4PEx4msg", lambda: oracle.run_program(heap, d), 2 * npes * k * msg))
+    # alltoall 1 MiB blocks over 8 PEs
+    P, blk = 8, 1 * MiB
+    h2 = np.zeros((P, 2 * P * blk), dtype=np.uint8)
+    samples.append(("alltoall_1MiB 8PE", lambda: oracle.alltoall(h2, P * blk, 0, blk), 2 * P * P * blk))
+    # broadcast 32 MiB over 8 PEs
+    h3 = np.zeros((P, 64 * MiB), dtype=np.uint8)
+    samples.append(("broadcast_32MiB 8PE", lambda: oracle.broadcast(h3, 32 * MiB, 0, 32 * MiB, 0),
+                    32 * MiB * (P + 1)))
+    # reductions 2^18 elements over 8 PEs
+    nr = 1 << 18
+    h4 = np.zeros((P, 2 * nr * 8), dtype=np.uint8)
+    for p in range(P):
+        h4[p, :nr * 8] = W.coll_i64(5, p, nr).view(np.uint8)
+    samples.append(("reduce_sum_i64 2^18 8PE", lambda: oracle.reduce(h4, oracle.DT_INT64, oracle.RO_SUM, nr * 8, 0, nr),
+                    2 * P * nr * 8))
+    h5 = np.zeros((P, 2 * nr * 4), dtype=np.uint8)
+    for p in range(P):
+        h5[p, :nr * 4] = W.coll_f32(6, p, nr).view(np.uint8)
+    samples.append(("reduce_sum_f32 2^18 8PE", lambda: oracle.reduce(h5, oracle.DT_FP32, oracle.RO_SUM, nr * 4, 0, nr),
+                    2 * P * nr * 4))
+    # GUPS 2^22 updates on 2^20 entries
+    idx, val, is_add = W.gups_updates(W.SEED_GUPS, 0, 1 << 22, 20)
+    table = np.zeros(1 << 20, dtype=np.int64)
+    samples.append(("gups 2^22 upd", lambda: oracle.gups(table, idx, val, is_add), 16 << 22))
+    tot_b, tot_t, reps = 0, 0.0, 0
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end or reps == 0:
+        for _, fn, b in samples:
+            t0 = time.perf_counter()
+            fn()
+            tot_t += time.perf_counter() - t0
+            tot_b += b
+        reps += 1
+    return {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle as written, one thread, repeated %dx over: %s (algorithmic read+write bytes / time)"
+                      % (reps, "; ".join(s[0] for s in samples)),
+            "seconds": round(tot_t, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        msg = ("this build runs on one GPU: virtual PEs are slices of one device's heap; "
+               "--gpus must be 1")
+        print(msg, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2607_08006_amd as v
+
+    torch.cuda.set_device(0)
+    npes = args.npes
+    want = set(r for r in args.rows.split(",") if r)
+    log(f"init {npes} PEs x {args.heap_mib} MiB")
+    if v.initialized():
+        v.finalize()
+    v.init(npes, args.heap_mib * MiB)
+    L = Layout(v, args.heap_mib)
+    fill_heap(v, L, npes)
+    torch.cuda.synchronize()
+    rows = build_rows(v, torch, L, npes, want)
+    do_batch = not want or "batch" in want
+    if do_batch:
+        log("building batch plan")
+        B = batch_setup(v, torch, L, npes)
+    stream = torch.cuda.current_stream()
+
+    def one_step(record):
+        for r in rows:
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            r.fn()
+            if record:
+                e1.record(stream)
+                r._ev = (e0, e1)
+        lat = None
+        if do_batch:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            batch_step(v, B)
+            e1.record(stream)
+            if record:
+                torch.cuda.synchronize()
+                lat = (batch_latencies(v, B), (e0, e1))
+        return lat
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    log(f"timed {args.steps} steps")
+    lats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lat = one_step(True)
+        for r in rows:
+            r._evs = getattr(r, "_evs", []) + [r._ev]
+        lats.append(lat)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    errs = v.device_errors()
+    for r in rows:
+        r.ms = [a.elapsed_time(b) for a, b in r._evs]
+    ms_per_step = wall * 1e3 / args.steps
+    step_bytes = sum(r.bytes for r in rows)
+    out_rows = {}
+    for r in rows:
+        ms = float(np.mean(r.ms))
+        d = {"ms": round(ms, 4)}
+        if r.bytes:
+            d["GB_s"] = round(r.bytes / (ms * 1e-3) / 1e9, 2)
+            d["hbm_frac"] = round(d["GB_s"] / HBM_PEAK_GBS, 4)
+        if r.ops:
+            d["Mops_s"] = round(r.ops / (ms * 1e-3) / 1e6, 2)
+        out_rows[r.name] = d
+    latency = None
+    if do_batch:
+        step_bytes += 3 * B["bytes"]
+        forms = {}
+        for k in ("fused", "per_op", "graph"):
+            allv = np.concatenate([a[0][k] for a in lats])
+            last = np.array([a[0][k].max() for a in lats])
+            forms[k] = {"p50_us": round(percentile(allv, 50), 2), "p99_us": round(percentile(allv, 99), 2),
+                        "burst_us": round(float(np.median(last)), 2),
+                        "Mops_s": round(B["nops"] / (float(np.median(last)) * 1e-6) / 1e6, 3)}
+        batch_ms = float(np.mean([a[1][0].elapsed_time(a[1][1]) for a in lats]))
+        out_rows["batch_all_forms"] = {"ms": round(batch_ms, 4)}
+        latency = {
+            "burst_ops": B["nops"], "npes": npes,
+            "definition": "a burst of mixed put/get (8 B-4 KiB) and fetch_add submitted together; an op's latency "
+                          "is device wall-clock time from the burst's start on the stream to the op's completion "
+                          "(its stores completed device-wide). per_op = one kernel launch per op; fused = one "
+                          "launch; graph = the fused launch replayed from a hipGraph",
+            **forms,
+        }
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    dom = max((r for r in rows if r.bytes), key=lambda r: float(np.sum(r.ms)), default=None)
+    roof = None
+    if dom is not None:
+        avg_ms = float(np.mean(dom.ms))
+        achieved = dom.bytes / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom.kernel or dom.name, dom.bytes),
+                "kernel": dom.kernel or dom.name, "row": dom.name, "algorithmic_bytes_per_launch": dom.bytes,
+                "avg_launch_ms": round(avg_ms, 4)}
+    gups = out_rows.get("gups_fetch_xor_add", {})
+    rec = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"{npes} virtual PEs x {args.heap_mib} MiB symmetric heap each; one pass of every "
+                               "hot-path row (put/get sweep points at thread/wavefront/work-group scope on ring and "
+                               "derangement patterns, random atomics, signal ping-pong, barrier, broadcast 256 MiB, "
+                               "fcollect 4 MiB, alltoall 1 MiB blocks, sum/max reduce 2^24 elements int64/fp32/bf16, "
+                               "2000-op mixed batch in fused, per-op and graph forms)",
+                   "npes": npes, "heap_bytes_per_pe": args.heap_mib * MiB, "step_algorithmic_bytes": step_bytes},
+        "amo_Mops_s": gups.get("Mops_s"),
+        "rows": out_rows,
+        "latency": latency,
+        "roofline": roof,
+        "device_errors": errs,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    if args.probe_copy_mib:
+        n = args.probe_copy_mib * MiB
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        v.probe_copy(b, a, n, nwg=4096, wg_size=256)
+        torch.cuda.synchronize()
+        rec["probe_copy_bytes"] = n
+    line = json.dumps(rec)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+    v.finalize()
+
+
+if __name__ == "__main__":
+    main()

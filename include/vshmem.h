@@ -264,7 +264,9 @@ int shmemx_set_wait_timeout_ns(uint64_t ns);
  * work-groups the launcher maps to it: pe = blockIdx.x / wgs_per_pe).
  * wg_size: threads per work-group (multiple of 64, <= 1024).  chunk_bytes:
  * unit of work handed to one work-group when a message or collective is
- * split across work-groups (multiple of 16). */
+ * split across work-groups (multiple of 16).  Zero fields take defaults;
+ * for the team collectives wgs_per_pe = 0 means as many work-groups per
+ * member as stay co-resident on the device (at most 16). */
 typedef struct shmemx_launch {
     int32_t wgs_per_pe;
     int32_t wg_size;
@@ -415,6 +417,16 @@ int shmemx_plan_launch_per_op(shmemx_plan_t *plan, uint64_t *results, void *stre
 /* Capture form 0 (per-op) or 1 (fused) into a hipGraph bound to `results`. */
 int shmemx_plan_graph_build(shmemx_plan_t *plan, int form, uint64_t *results, void *stream);
 int shmemx_plan_graph_launch(shmemx_plan_t *plan, void *stream);
+/* Measurement mode: when stamps (DEVICE uint64 array with one entry per
+ * descriptor of the plan, zeroed by the caller) is non-NULL, every later
+ * launch of the plan (fused or per-op; graphs capture the setting at build
+ * time) records for descriptor i, once its operation has completed, the
+ * device wall clock into stamps[i] (the latest of its work-groups).
+ * NULL turns it off. */
+int shmemx_plan_set_stamps(shmemx_plan_t *plan, uint64_t *stamps);
+/* Record the device wall clock into *dst (DEVICE) when the stream reaches
+ * this point: the start reference for completion stamps. */
+int shmemx_stamp_launch(uint64_t *dst, void *stream);
 /* Number of fused work-group tasks / phases / kernel launches per per-op run. */
 int shmemx_plan_info(const shmemx_plan_t *plan, uint64_t *ntasks, uint64_t *nphases, uint64_t *nlaunches);
 void shmemx_plan_destroy(shmemx_plan_t *plan);
@@ -505,6 +517,12 @@ int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t
 /* Fill device memory with bytes [word_offset*8, ...) of the SplitMix64
  * stream `seed` (little-endian words): the seeded synthetic payload. */
 int shmemx_fill_random(void *dst, uint64_t nbytes, uint64_t seed, uint64_t word_offset, void *stream);
+/* Fill `count` elements of type dtype (SHMEMX_DT_INT64, SHMEMX_DT_FP32,
+ * SHMEMX_DT_BF16) from SplitMix64 outputs index0, index0+1, ... of `seed`:
+ * int64 = the raw output; fp32 = ((x >> 40) * 2^-24) * 2 - 1 (uniform in
+ * [-1, 1), exact); bf16 = that fp32 rounded to nearest even.  dst must be
+ * aligned to the element size. */
+int shmemx_fill_typed(void *dst, uint64_t count, int dtype, uint64_t seed, uint64_t index0, void *stream);
 /* Plain device-to-device copy kernel of nbytes (16-byte aligned) used as
  * the achievable-bandwidth probe and as the counter-scaling reference. */
 int shmemx_probe_copy(void *dst, const void *src, uint64_t nbytes, int nwg, int wg_size, void *stream);

@@ -272,6 +272,10 @@ def fill_random(dst, nbytes: int, seed: int, word_offset: int = 0, stream=None) 
     _check(lib.shmemx_fill_random(_ptr(dst), nbytes, seed, word_offset, _stream(stream)), "shmemx_fill_random")
 
 
+def fill_typed(dst, count: int, dtype: int, seed: int, index0: int = 0, stream=None) -> None:
+    _check(lib.shmemx_fill_typed(_ptr(dst), count, dtype, seed, index0, _stream(stream)), "shmemx_fill_typed")
+
+
 def probe_copy(dst, src, nbytes: int, nwg: int = 4096, wg_size: int = 256, stream=None) -> None:
     _check(lib.shmemx_probe_copy(_ptr(dst), _ptr(src), nbytes, nwg, wg_size, _stream(stream)), "shmemx_probe_copy")
 
@@ -320,6 +324,9 @@ class Plan:
     def graph_launch(self, stream=None) -> None:
         _check(lib.shmemx_plan_graph_launch(self._h, _stream(stream)), "shmemx_plan_graph_launch")
 
+    def set_stamps(self, stamps) -> None:
+        _check(lib.shmemx_plan_set_stamps(self._h, _ptr(stamps)), "shmemx_plan_set_stamps")
+
     def info(self) -> dict:
         a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
         _check(lib.shmemx_plan_info(self._h, C.byref(a), C.byref(b), C.byref(c)), "shmemx_plan_info")
@@ -335,6 +342,10 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+def stamp(dst, stream=None) -> None:
+    _check(lib.shmemx_stamp_launch(_ptr(dst), _stream(stream)), "shmemx_stamp_launch")
 
 
 def autotune(scratch_off: int, scratch_bytes: int, min_bytes: int, max_bytes: int, msgs: int = 256,

@@ -102,6 +102,8 @@ SIGNATURES = {
     "shmemx_plan_launch_per_op": (i32, [vp, vp, vp]),
     "shmemx_plan_graph_build": (i32, [vp, i32, vp, vp]),
     "shmemx_plan_graph_launch": (i32, [vp, vp]),
+    "shmemx_plan_set_stamps": (i32, [vp, vp]),
+    "shmemx_stamp_launch": (i32, [vp, vp]),
     "shmemx_plan_info": (i32, [vp, P(u64), P(u64), P(u64)]),
     "shmemx_plan_destroy": (None, [vp]),
     "shmemx_autotune": (i32, [u64, u64, u64, u64, i32, i32, P(Tune), vp]),
@@ -113,6 +115,7 @@ SIGNATURES = {
     "shmemx_progress_stop": (i32, [i32]),
     "shmemx_serve_run": (i32, [P(Request), sz, i32, u64, u64, u64, vp, vp, P(Completion), P(ServeStats)]),
     "shmemx_fill_random": (i32, [vp, u64, u64, u64, vp]),
+    "shmemx_fill_typed": (i32, [vp, u64, i32, u64, u64, vp]),
     "shmemx_probe_copy": (i32, [vp, vp, u64, i32, i32, vp]),
     "shmemx_probe_atomics": (i32, [vp, u64, u64, u64, vp, vp]),
     "shmemx_probe_xcd": (i32, [vp, i32, vp]),

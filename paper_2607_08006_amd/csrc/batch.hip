@@ -31,6 +31,7 @@ struct shmemx_plan {
     uint64_t ntasks = 0, nphases = 0, nlaunch = 0;
     int wg = 256;
     int grid = 1;
+    uint64_t *stamps = nullptr;             // optional per-op completion stamps (device)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -145,28 +146,55 @@ __device__ __forceinline__ void exec_wg(const shmemx_dctx_pub_t &c, const shmemx
     }
 }
 
+// Completion stamp of operation `idx` (measurement mode): the caller's
+// stores are completed first, then the device wall clock is recorded; when
+// several work-groups share an operation the latest stamp wins.
+__device__ __forceinline__ void stamp(uint64_t *stamps, uint64_t idx)
+{
+    __hip_atomic_fetch_max(stamps + idx, (uint64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void run_task(const shmemx_dctx_pub_t &c, const shmemx_desc_t *D, const PlanTask &t,
-                                         uint64_t *results)
+                                         uint64_t *results, uint64_t *stamps)
 {
     if (t.kind == TK_THREAD) {
-        if (threadIdx.x < t.count) exec_thread(c, D[t.first + threadIdx.x], results);
+        if (threadIdx.x < t.count) {
+            const shmemx_desc_t &d = D[t.first + threadIdx.x];
+            exec_thread(c, d, results);
+            if (stamps) {
+                vshmem_detail::release_agent();
+                stamp(stamps, d.reserved);
+            }
+        }
     } else if (t.kind == TK_WAVE) {
         const uint32_t w = threadIdx.x / 64;
-        if (w < t.count) exec_wave(c, D[t.first + w], results);
+        if (w < t.count) {
+            const shmemx_desc_t &d = D[t.first + w];
+            exec_wave(c, d, results);
+            if (stamps) {
+                vshmem_detail::release_agent();
+                if (__lane_id() == 0) stamp(stamps, d.reserved);
+            }
+        }
     } else {
         exec_wg(c, D[t.first], t.lo, t.hi, results);
+        if (stamps) {
+            vshmem_detail::release_agent();
+            __syncthreads();
+            if (threadIdx.x == 0) stamp(stamps, D[t.first].reserved);
+        }
     }
 }
 
 __global__ void __launch_bounds__(1024) k_plan_fused(shmemx_dctx_pub_t c, const shmemx_desc_t *__restrict__ D,
                                                      const PlanTask *__restrict__ T, const uint32_t *__restrict__ phase,
-                                                     int nphases, uint64_t *results)
+                                                     int nphases, uint64_t *results, uint64_t *stamps)
 {
     for (int ph = 0; ph < nphases; ++ph) {
         const uint32_t t1 = phase[ph + 1];
         for (uint32_t t = phase[ph] + blockIdx.x; t < t1; t += gridDim.x) {
             const PlanTask task = T[t];
-            run_task(c, D, task, results);
+            run_task(c, D, task, results, stamps);
         }
         if (ph + 1 < nphases) {
             // Ordering point: every work-group's earlier operations complete
@@ -184,7 +212,7 @@ __global__ void __launch_bounds__(1024) k_plan_fused(shmemx_dctx_pub_t c, const 
 
 // Per-operation form: the kernel receives its descriptor by value.
 __global__ void __launch_bounds__(1024) k_plan_one(shmemx_dctx_pub_t c, shmemx_desc_t d, int scope, uint64_t chunk,
-                                                   uint64_t *results)
+                                                   uint64_t *results, uint64_t *stamps)
 {
     if (scope == SHMEMX_SCOPE_THREAD) {
         if (threadIdx.x == 0) exec_thread(c, d, results);
@@ -196,7 +224,13 @@ __global__ void __launch_bounds__(1024) k_plan_one(shmemx_dctx_pub_t c, shmemx_d
         if (lo < hi || (blockIdx.x == 0 && d.nbytes == 0)) exec_wg(c, d, lo, hi, results);
     }
     vshmem_detail::release_agent();
+    if (stamps) {
+        __syncthreads();
+        if (threadIdx.x == 0) stamp(stamps, d.reserved);
+    }
 }
+
+__global__ void k_stamp(uint64_t *dst) { if (threadIdx.x == 0) *dst = wall_clock64(); }
 
 bool is_sync(uint8_t op) { return op == SHMEMX_OP_FENCE || op == SHMEMX_OP_QUIET || op == SHMEMX_OP_BARRIER_ALL; }
 bool is_amo_h(uint8_t op) { return op >= SHMEMX_OP_AMO_FETCH_ADD && op <= SHMEMX_OP_AMO_SWAP; }
@@ -281,6 +315,7 @@ int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t
     std::vector<std::pair<uint64_t, uint32_t>> keyed;   // (phase key, op index)
     auto plan = new shmemx_plan();
     plan->host.assign(descs, descs + n);
+    for (size_t i = 0; i < n; ++i) plan->host[i].reserved = i;
     plan->host_scope.assign(n, 0);
     plan->host_chunk.assign(n, 0);
     plan->wg = tune.wg_size;
@@ -338,6 +373,7 @@ int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t
             const uint64_t nb = descs[idx].nbytes, ch = plan->host_chunk[idx];
             const uint32_t first = (uint32_t)dd.size();
             dd.push_back(descs[idx]);
+            dd.back().reserved = idx;
             if (nb == 0 || ch >= nb) {
                 tasks.push_back(PlanTask{TK_WG, 1, first, 0, 0, nb});
             } else {
@@ -348,12 +384,18 @@ int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t
         for (size_t k = 0; k < wv.size(); k += waves) {
             uint32_t cnt = (uint32_t)std::min<size_t>(waves, wv.size() - k);
             tasks.push_back(PlanTask{TK_WAVE, cnt, (uint32_t)dd.size(), 0, 0, 0});
-            for (uint32_t u = 0; u < cnt; ++u) dd.push_back(descs[wv[k + u]]);
+            for (uint32_t u = 0; u < cnt; ++u) {
+                dd.push_back(descs[wv[k + u]]);
+                dd.back().reserved = wv[k + u];
+            }
         }
         for (size_t k = 0; k < th.size(); k += (size_t)tune.wg_size) {
             uint32_t cnt = (uint32_t)std::min<size_t>((size_t)tune.wg_size, th.size() - k);
             tasks.push_back(PlanTask{TK_THREAD, cnt, (uint32_t)dd.size(), 0, 0, 0});
-            for (uint32_t u = 0; u < cnt; ++u) dd.push_back(descs[th[k + u]]);
+            for (uint32_t u = 0; u < cnt; ++u) {
+                dd.push_back(descs[th[k + u]]);
+                dd.back().reserved = th[k + u];
+            }
         }
         phase.push_back((uint32_t)tasks.size());
         i = j;
@@ -388,7 +430,7 @@ int shmemx_plan_launch_fused(shmemx_plan_t *plan, uint64_t *results, void *strea
     if (!plan) return SHMEMX_ERR_ARG;
     if (plan->nphases == 0) return SHMEMX_OK;
     hipLaunchKernelGGL(k_plan_fused, dim3(plan->grid), dim3(plan->wg), 0, (hipStream_t)stream, pub(), plan->d_descs,
-                       plan->d_tasks, plan->d_phase, (int)plan->nphases, results);
+                       plan->d_tasks, plan->d_phase, (int)plan->nphases, results, plan->stamps);
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
 }
@@ -408,7 +450,8 @@ int shmemx_plan_launch_per_op(shmemx_plan_t *plan, uint64_t *results, void *stre
             block = (unsigned)plan->wg;
             grid = (unsigned)std::max<uint64_t>(1, (d.nbytes + ch - 1) / ch);
         }
-        hipLaunchKernelGGL(k_plan_one, dim3(grid), dim3(block), 0, (hipStream_t)stream, c, d, sc, ch, results);
+        hipLaunchKernelGGL(k_plan_one, dim3(grid), dim3(block), 0, (hipStream_t)stream, c, d, sc, ch, results,
+                           plan->stamps);
     }
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
@@ -446,6 +489,21 @@ int shmemx_plan_graph_launch(shmemx_plan_t *plan, void *stream)
     if (int rc = check_ready()) return rc;
     if (!plan || !plan->exec) return SHMEMX_ERR_STATE;
     VSHMEM_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    return SHMEMX_OK;
+}
+
+int shmemx_plan_set_stamps(shmemx_plan_t *plan, uint64_t *stamps)
+{
+    if (!plan) return SHMEMX_ERR_ARG;
+    plan->stamps = stamps;
+    return SHMEMX_OK;
+}
+
+int shmemx_stamp_launch(uint64_t *dst, void *stream)
+{
+    if (!dst) return SHMEMX_ERR_ARG;
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, (hipStream_t)stream, dst);
+    VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
 }
 

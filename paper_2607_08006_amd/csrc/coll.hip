@@ -1,6 +1,9 @@
 // Team collectives executed by the work-groups of every team member:
 // broadcast, fcollect, alltoall and reductions to all (sum, max) over int64,
 // fp32 and bf16 with fp32 accumulation, in the fixed TREE order.
+#include <algorithm>
+#include <cstdio>
+
 #include "runtime.hpp"
 
 using namespace vshmem;
@@ -123,21 +126,20 @@ struct TreeAcc {
     A s[LEVELS][E];
     __device__ __forceinline__ void push(uint32_t count, const A (&x)[E])
     {
+        // The new input merges with the tz occupied slots below the first
+        // free one (tz = trailing ones of count) and lands in slot tz.
+        const uint32_t tz = (uint32_t)__builtin_ctz(~count);
         A c[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) c[e] = x[e];
-        bool done = false;
 #pragma unroll
         for (int j = 0; j < LEVELS; ++j) {
-            if (!done) {
-                if ((count >> j) & 1u) {
+            if ((uint32_t)j < tz) {
 #pragma unroll
-                    for (int e = 0; e < E; ++e) c[e] = OP::f(s[j][e], c[e]);
-                } else {
+                for (int e = 0; e < E; ++e) c[e] = OP::f(s[j][e], c[e]);
+            } else if ((uint32_t)j == tz) {
 #pragma unroll
-                    for (int e = 0; e < E; ++e) s[j][e] = c[e];
-                    done = true;
-                }
+                for (int e = 0; e < E; ++e) s[j][e] = c[e];
             }
         }
     }
@@ -313,33 +315,46 @@ int check_coresident(K kernel, int grid, int wg)
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, wg, 0) != hipSuccess) return SHMEMX_ERR_HIP;
-    if ((int64_t)per_cu * st().num_cus < grid) return SHMEMX_ERR_ARG;
+    if ((int64_t)per_cu * st().num_cus < grid) {
+        if (st().debug)
+            fprintf(stderr, "vshmem: %d work-groups of %d threads cannot be co-resident (%d per CU x %d CUs)\n", grid,
+                    wg, per_cu, st().num_cus);
+        return SHMEMX_ERR_ARG;
+    }
     return SHMEMX_OK;
 }
 
+// Launch a kernel whose work-groups synchronise with each other.  When the
+// caller left wgs_per_pe at 0, fill the device: as many work-groups per
+// member as stay co-resident (at most 16).
 template <typename K, typename... Args>
-int launch_team_kernel(K kernel, int grid, int wg, hipStream_t s, Args... args)
+int launch_team_kernel(K kernel, Geo &g, int wg, hipStream_t s, bool auto_wgs, Args... args)
 {
+    if (auto_wgs) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, wg, 0) != hipSuccess) return SHMEMX_ERR_HIP;
+        int64_t cap = (int64_t)per_cu * st().num_cus;
+        g.wgs_per_pe = (int)std::max<int64_t>(1, std::min<int64_t>(16, cap / g.team.size));
+    }
+    const int grid = g.wgs_per_pe * g.team.size;
     int rc = check_coresident(kernel, grid, wg);
     if (rc) {
         set_last_error(rc);
         return rc;
     }
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(wg), 0, s, args...);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(wg), 0, s, g, args...);
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
 }
-
-int default_wgs(int size) { return size >= 1024 ? 1 : (1024 / size); }
 
 int make_geo(shmem_team_t team, const void *dest, const void *src, uint64_t dst_bytes, uint64_t src_bytes,
              const shmemx_launch_t *launch, int def_wg, Geo &g, shmemx_launch_t &L)
 {
     if (int rc = check_ready()) return rc;
     if (team_get(team, &g.team) != SHMEMX_OK) return SHMEMX_ERR_ARG;
-    launch_or_default(launch, L, default_wgs(g.team.size), def_wg, 256ull << 10);
-    if (!valid_wg_size(L.wg_size) || (L.chunk_bytes & 15) || L.wgs_per_pe <= 0 ||
-        (int64_t)L.wgs_per_pe * g.team.size > (1 << 24))
+    launch_or_default(launch, L, 1, def_wg, 256ull << 10);
+    if (launch && launch->wgs_per_pe < 0) return SHMEMX_ERR_ARG;
+    if (!valid_wg_size(L.wg_size) || (L.chunk_bytes & 15) || (int64_t)L.wgs_per_pe * g.team.size > (1 << 24))
         return SHMEMX_ERR_ARG;
     g.dst_off = sym_offset(dest, dst_bytes);
     g.src_off = sym_offset(src, src_bytes);
@@ -368,10 +383,10 @@ int shmemx_broadcastmem_launch(shmem_team_t team, void *dest, const void *src, s
         return rc;
     }
     g.n = n;
-    const int grid = L.wgs_per_pe * g.team.size;
+    const bool aw = !launch || launch->wgs_per_pe == 0;
     if (L.flags & SHMEMX_LAUNCH_NONTEMPORAL)
-        return launch_team_kernel(k_broadcast<true>, grid, L.wg_size, (hipStream_t)stream, g, root);
-    return launch_team_kernel(k_broadcast<false>, grid, L.wg_size, (hipStream_t)stream, g, root);
+        return launch_team_kernel(k_broadcast<true>, g, L.wg_size, (hipStream_t)stream, aw, root);
+    return launch_team_kernel(k_broadcast<false>, g, L.wg_size, (hipStream_t)stream, aw, root);
 }
 
 int shmemx_fcollectmem_launch(shmem_team_t team, void *dest, const void *src, size_t n, const shmemx_launch_t *launch,
@@ -390,10 +405,10 @@ int shmemx_fcollectmem_launch(shmem_team_t team, void *dest, const void *src, si
         return rc;
     }
     g.n = n;
-    const int grid = L.wgs_per_pe * g.team.size;
+    const bool aw = !launch || launch->wgs_per_pe == 0;
     if (L.flags & SHMEMX_LAUNCH_NONTEMPORAL)
-        return launch_team_kernel(k_fcollect<true>, grid, L.wg_size, (hipStream_t)stream, g);
-    return launch_team_kernel(k_fcollect<false>, grid, L.wg_size, (hipStream_t)stream, g);
+        return launch_team_kernel(k_fcollect<true>, g, L.wg_size, (hipStream_t)stream, aw);
+    return launch_team_kernel(k_fcollect<false>, g, L.wg_size, (hipStream_t)stream, aw);
 }
 
 int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, size_t n, const shmemx_launch_t *launch,
@@ -411,10 +426,10 @@ int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, si
         return rc;
     }
     g.n = n;
-    const int grid = L.wgs_per_pe * g.team.size;
+    const bool aw = !launch || launch->wgs_per_pe == 0;
     if (L.flags & SHMEMX_LAUNCH_NONTEMPORAL)
-        return launch_team_kernel(k_alltoall<true>, grid, L.wg_size, (hipStream_t)stream, g);
-    return launch_team_kernel(k_alltoall<false>, grid, L.wg_size, (hipStream_t)stream, g);
+        return launch_team_kernel(k_alltoall<true>, g, L.wg_size, (hipStream_t)stream, aw);
+    return launch_team_kernel(k_alltoall<false>, g, L.wg_size, (hipStream_t)stream, aw);
 }
 
 int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const void *src, size_t nreduce,
@@ -438,15 +453,15 @@ int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const
         return rc;
     }
     g.n = nreduce;
-    const int grid = L.wgs_per_pe * g.team.size;
+    const bool aw = !launch || launch->wgs_per_pe == 0;
     hipStream_t s = (hipStream_t)stream;
     const bool nt = (L.flags & SHMEMX_LAUNCH_NONTEMPORAL) != 0;
 #define VSHMEM_RED(CODEC)                                                                                   \
     if (op == SHMEMX_RED_SUM)                                                                               \
-        return nt ? launch_team_kernel(k_reduce<CODEC, OpSum, true>, grid, L.wg_size, s, g)                 \
-                  : launch_team_kernel(k_reduce<CODEC, OpSum, false>, grid, L.wg_size, s, g);               \
-    return nt ? launch_team_kernel(k_reduce<CODEC, OpMax, true>, grid, L.wg_size, s, g)                     \
-              : launch_team_kernel(k_reduce<CODEC, OpMax, false>, grid, L.wg_size, s, g);
+        return nt ? launch_team_kernel(k_reduce<CODEC, OpSum, true>, g, L.wg_size, s, aw)                   \
+                  : launch_team_kernel(k_reduce<CODEC, OpSum, false>, g, L.wg_size, s, aw);                 \
+    return nt ? launch_team_kernel(k_reduce<CODEC, OpMax, true>, g, L.wg_size, s, aw)                       \
+              : launch_team_kernel(k_reduce<CODEC, OpMax, false>, g, L.wg_size, s, aw);
     if (dtype == SHMEMX_DT_INT64) {
         VSHMEM_RED(CodecI64)
     } else if (dtype == SHMEMX_DT_FP32) {

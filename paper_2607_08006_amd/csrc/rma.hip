@@ -78,6 +78,24 @@ __global__ void k_fill_random(uint8_t *dst, uint64_t nbytes, uint64_t seed, uint
     }
 }
 
+__global__ void k_fill_typed(uint8_t *dst, uint64_t count, int dtype, uint64_t seed, uint64_t index0)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = splitmix_at(seed, index0 + i);
+        if (dtype == SHMEMX_DT_INT64) {
+            ((uint64_t *)dst)[i] = x;
+        } else {
+            const float f = (float)((double)(x >> 40) * 0x1.0p-24 * 2.0 - 1.0);
+            if (dtype == SHMEMX_DT_FP32) {
+                ((float *)dst)[i] = f;
+            } else {
+                const uint32_t u = __float_as_uint(f);
+                ((uint16_t *)dst)[i] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------------- probes
 __global__ void __launch_bounds__(1024) k_probe_copy(vshmem_detail::v4u *__restrict__ d,
                                                      const vshmem_detail::v4u *__restrict__ s, uint64_t nv)
@@ -163,6 +181,20 @@ int shmemx_fill_random(void *dst, uint64_t nbytes, uint64_t seed, uint64_t word_
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(k_fill_random, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, (uint8_t *)dst, nbytes,
                        seed, word_offset);
+    VSHMEM_HIP(hipGetLastError());
+    return SHMEMX_OK;
+}
+
+int shmemx_fill_typed(void *dst, uint64_t count, int dtype, uint64_t seed, uint64_t index0, void *stream)
+{
+    const uint64_t es = dtype == SHMEMX_DT_INT64 ? 8 : dtype == SHMEMX_DT_FP32 ? 4 : 2;
+    if (dtype < SHMEMX_DT_INT64 || dtype > SHMEMX_DT_BF16 || (!dst && count) || ((uintptr_t)dst % es))
+        return SHMEMX_ERR_ARG;
+    if (count == 0) return SHMEMX_OK;
+    uint64_t grid = (count + 255) / 256;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL(k_fill_typed, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, (uint8_t *)dst, count,
+                       dtype, seed, index0);
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
 }

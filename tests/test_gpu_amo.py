@@ -10,8 +10,8 @@ from tests.gpu_helpers import assert_no_device_errors, device_array, download, h
 pytestmark = pytest.mark.gpu
 
 
-def _gups_check(v, npes, log2_table, nupd, seed, table_off, init_table, got_table, fetched):
-    idx, val, is_add = W.gups_updates(seed, 0, nupd, log2_table)
+def _gups_check(v, npes, log2_table, nupd, base_seed, table_off, init_table, got_table, fetched):
+    idx, val, is_add = W.gups_updates(base_seed, 0, nupd, log2_table)
     kind = np.where(is_add, oracle.KIND_FETCH_ADD, oracle.KIND_FETCH_XOR).astype(np.uint8)
     assert oracle.witness_check(idx, kind, val, fetched, init_table.view(np.uint64),
                                 got_table.view(np.uint64)) == 0
@@ -41,7 +41,7 @@ def test_gups_witness_replay(npes, log2_table, nupd):
         assert int(acc.cpu().numpy().view(np.uint64)[0]) == int(x)
         init_table = init.view(np.int64).reshape(-1)      # PE-major = global index order
         got_table = got.view(np.int64).reshape(-1)
-        _gups_check(v, npes, log2_table, nupd, seed, 0, init_table, got_table, f)
+        _gups_check(v, npes, log2_table, nupd, W.SEED_GUPS, 0, init_table, got_table, f)
         assert_no_device_errors()
 
 
@@ -50,12 +50,12 @@ def test_gups_without_fetch_matches_closed_forms():
     per_pe = 8 << (log2_table - 3)
     with heap(npes, 1 << 20) as v:
         t = torch()
-        seed = W.subseed(W.SEED_GUPS, 9)
+        base = W.SEED_GUPS + 9
         init = np.zeros((npes, per_pe), dtype=np.uint8)
         upload(init)
-        v.gups(0, log2_table, nupd, seed, 1)          # add_every = 1: all fetch_add
+        v.gups(0, log2_table, nupd, W.subseed(base, W.TAG_OPS), 1)          # add_every = 1: all fetch_add
         got = download(per_pe).view(np.int64).reshape(-1)
-        idx, val, is_add = W.gups_updates(seed, 0, nupd, log2_table, add_every=1)
+        idx, val, is_add = W.gups_updates(base, 0, nupd, log2_table, add_every=1)
         assert is_add.all()
         ref = np.zeros(1 << log2_table, dtype=np.int64)
         oracle.gups(ref, idx, val, is_add)

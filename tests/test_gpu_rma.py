@@ -213,3 +213,20 @@ def test_heap_allocator_symmetry_and_queries():
         tm = v.team_split_strided(v.DEVICE_TEAM_WORLD, 1, 2, 2)
         assert v.query_capabilities(tm)["team_start"] == 1 and v.team_n_pes(tm) == 2
         v.team_destroy(tm)
+
+
+def test_device_input_generators_match_workload():
+    t = torch_mod = __import__("torch")
+    import paper_2607_08006_amd as v
+    n = 100_003
+    buf = t.zeros(n * 8 + 16, dtype=t.uint8, device="cuda")
+    v.fill_random(buf, 1001, 0xABCDEF, word_offset=7)
+    assert np.array_equal(buf[:1001].cpu().numpy(), W.payload(0xABCDEF, 56, 1001))
+    v.fill_typed(buf, n, v.DT_INT64, 42, index0=5)
+    assert np.array_equal(buf[:8 * n].cpu().numpy().view(np.uint64), W.splitmix64(42, 5, n))
+    v.fill_typed(buf, n, v.DT_FP32, 43)
+    assert np.array_equal(buf[:4 * n].cpu().numpy().view(np.float32), W.uniform_f32(W.splitmix64(43, 0, n)))
+    v.fill_typed(buf, n, v.DT_BF16, 44)
+    assert np.array_equal(buf[:2 * n].cpu().numpy().view(np.uint16),
+                          W.f32_to_bf16_bits(W.uniform_f32(W.splitmix64(44, 0, n))))
+    torch_mod.cuda.synchronize()

@@ -233,18 +233,24 @@ def _overlaps(iv: List[Tuple[int, int]], lo: int, hi: int) -> bool:
 def small_workload(seed: int = SEED_SMALL, npes: int = 4, heap_bytes: int = 1 << 20,
                    n_rma: int = 1000, epoch_ops: int = 125, n_amo: int = 10_000,
                    ncounters: int = 64, min_size: int = 8, max_size: int = 4096,
-                   scope: int = SCOPE_AUTO, amo_scope: int = SCOPE_THREAD) -> SmallWorkload:
+                   scope: int = SCOPE_AUTO, amo_scope: int = SCOPE_THREAD,
+                   base_off: int = 0, fill: bool = True) -> SmallWorkload:
     """Mixed put/get traffic plus contended fetch_add on one small heap.
 
     The put/get ops are grouped into epochs of ``epoch_ops``; every epoch is
     conflict free (no byte written by one op is read or written by another op
     of that epoch) by rejection, and epochs are separated by barrier_all.
-    The AMO epoch follows, then quiet and barrier_all.
+    The AMO epoch follows, then quiet and barrier_all.  All offsets are
+    relative to ``base_off``: the workload occupies [base_off, base_off +
+    heap_bytes) of every PE and ``init`` holds that window.
     """
     counter_off = heap_bytes - 4096
     data_bytes = counter_off
-    init = heap_fill(seed, npes, heap_bytes)
-    init[:, counter_off:counter_off + 8 * ncounters] = 0
+    if fill:
+        init = heap_fill(seed, npes, heap_bytes)
+        init[:, counter_off:counter_off + 8 * ncounters] = 0
+    else:
+        init = np.zeros((0, 0), dtype=np.uint8)
     rs = subseed(seed, TAG_OPS)
     ctr = 0
 
@@ -282,7 +288,7 @@ def small_workload(seed: int = SEED_SMALL, npes: int = 4, heap_bytes: int = 1 <<
                 continue
             writes[wpe].append((dst, dst + n))
             reads[rpe].append((src, src + n))
-            recs.append((kind, scope, 0, issuer, target, NO_RESULT, src, dst, n, 0, 0))
+            recs.append((kind, scope, 0, issuer, target, NO_RESULT, base_off + src, base_off + dst, n, 0, 0))
             k += 1
         made += nthis
         for p in range(npes):
@@ -295,7 +301,7 @@ def small_workload(seed: int = SEED_SMALL, npes: int = 4, heap_bytes: int = 1 <<
     for i in range(n_amo):
         c = int(cidx[i])
         recs.append((OP_AMO_FETCH_ADD, amo_scope, 0, int(issuers[i]), int(home[c]), i,
-                     counter_off + 8 * c, 0, 8, 1, 0))
+                     base_off + counter_off + 8 * c, 0, 8, 1, 0))
     for p in range(npes):
         recs.append((OP_QUIET, SCOPE_WG, 0, p, p, NO_RESULT, 0, 0, 0, 0, 0))
     for p in range(npes):
