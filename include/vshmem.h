@@ -52,6 +52,7 @@ extern "C" {
 #define SHMEMX_DEVERR_WAIT_TIMEOUT 0x1u   /* wait_until / barrier spin limit reached */
 #define SHMEMX_DEVERR_BAD_DESC 0x2u       /* descriptor outside the heap or bad op */
 #define SHMEMX_DEVERR_PROGRESS_IDLE 0x4u  /* progress kernel stopped by its idle limit */
+#define SHMEMX_DEVERR_PROGRESS_STATE 0x8u /* progress kernel saw an inconsistent request record */
 
 /* -------------------------------------------------- operations and scopes
  * Operation codes of a descriptor (Section 2.1 operation list; put with
@@ -475,7 +476,10 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg, void *stream);
  * results go to the issuer's [dst, dst + nbytes).  Returns
  * SHMEMX_ERR_BUSY when the ring is full. */
 int shmemx_progress_submit(const shmemx_desc_t *desc, uint64_t *ticket);
-/* 1 = complete (out filled), 0 = not yet, <0 = error. */
+/* 1 = complete (out filled), 0 = not yet, <0 = error.  The first poll that
+ * sees a request complete consumes its completion record and frees its ring
+ * slot; later polls of the same ticket return 1 with only `ticket` set.
+ * Every submitted ticket must be polled to completion, or the ring fills. */
 int shmemx_progress_poll(uint64_t ticket, shmemx_completion_t *out);
 /* Stop the kernel after it drains the ring; waits up to timeout_ms. */
 int shmemx_progress_stop(int timeout_ms);

@@ -1,14 +1,522 @@
-// Persistent progress kernel and trace-driven serving (in progress).
+// Persistent progress kernel (GPU-driven progress for requests that arrive
+// while the kernel runs) and the host side of its request ring.
+//
+// Host producers publish 64-byte descriptors into a ring in pinned, coherent
+// host memory, one sequence word per slot (a bounded multi-producer queue:
+// slot s is free for ticket t when seq[s] == t and published when t + 1).
+// The device reports completion in a separate word (done[s] = t + 1, after
+// the completion record); the host's poll consumes the record and only then
+// frees the slot for ticket t + slots, so a record is never overwritten
+// before it was read.  On the device one front-end wavefront reads
+// published descriptors in ticket order and expands each into work items of
+// at most chunk_bytes in a device-memory queue; every other wavefront of the
+// grid claims items from that queue, executes them, and the wavefront that
+// finishes a request's last item writes its completion record to host
+// memory and then releases the slot with a system-scope store.  The kernel
+// ends when the host raises the stop flag or after idle_timeout_ms without
+// a request; either way every wavefront reaches its exit.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <thread>
+
 #include "runtime.hpp"
 
-extern "C" {
-int shmemx_progress_start(const shmemx_progress_cfg_t *, void *) { return SHMEMX_ERR_UNSUPPORTED; }
-int shmemx_progress_submit(const shmemx_desc_t *, uint64_t *) { return SHMEMX_ERR_UNSUPPORTED; }
-int shmemx_progress_poll(uint64_t, shmemx_completion_t *) { return SHMEMX_ERR_UNSUPPORTED; }
-int shmemx_progress_stop(int) { return SHMEMX_ERR_UNSUPPORTED; }
-int shmemx_serve_run(const shmemx_request_t *, size_t, int, uint64_t, uint64_t, uint64_t, uint64_t *, uint64_t *,
-                     shmemx_completion_t *, shmemx_serve_stats_t *)
+using namespace vshmem;
+
+namespace {
+
+constexpr uint64_t kItemPoison = ~0ull;
+
+struct Item {              // 64 bytes, device memory
+    uint64_t seq;
+    uint64_t parent;       // ring slot of the request, or kItemPoison
+    uint64_t ticket;       // ticket of the request (consistency check)
+    uint64_t lo, hi;       // byte range of the request's payload
+    uint64_t pad[3];
+};
+
+struct alignas(128) Parent {   // device memory, one per ring slot, own cache line
+    shmemx_desc_t d;
+    uint64_t ticket;
+    uint64_t remaining;    // items not yet finished
+    uint64_t t_start;
+    uint64_t hash;
+    int32_t status;
+    int32_t pad;
+};
+
+struct ProgArgs {
+    shmemx_dctx_pub_t c;
+    shmemx_desc_t *ring;          // host memory (device-mapped)
+    uint64_t *ring_seq;           // host memory (device-mapped)
+    uint64_t *ring_done;          // host memory (device-mapped)
+    shmemx_completion_t *comp;    // host memory (device-mapped)
+    uint64_t *stop;               // host memory (device-mapped)
+    Item *items;
+    Parent *parents;
+    uint64_t *claim;              // device: next item ticket for workers
+    uint64_t slots, qsize;
+    uint64_t chunk;
+    uint64_t idle_ticks;
+    int verify;
+};
+
+__device__ __forceinline__ uint64_t ld_sys(const uint64_t *p)
 {
-    return SHMEMX_ERR_UNSUPPORTED;
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+__device__ __forceinline__ void st_sys(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+__device__ __forceinline__ uint64_t ld_dev(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Relaxed coherent loads: records written by another work-group (or by the
+// host) are read through atomic loads, which are served at the coherence
+// point rather than from a possibly stale cached line.
+__device__ __forceinline__ uint64_t ldr_dev(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ldr_sys(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void load_desc(shmemx_desc_t &d, const shmemx_desc_t *src, bool system)
+{
+    uint64_t w[8];
+    const uint64_t *q = (const uint64_t *)src;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = system ? ldr_sys(q + i) : ldr_dev(q + i);
+    memcpy(&d, w, sizeof(d));
+}
+
+// Output checksum: XOR over the output's 8-byte words w_i (last one zero
+// padded) of mix(w_i ^ ((i + 1) * golden)), i counted from the start of the
+// request's output, so it does not depend on where the output was placed.
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ uint64_t hash_range(const uint8_t *out, uint64_t lo, uint64_t hi, uint64_t total)
+{
+    // lo is a multiple of 8 (chunks are multiples of 16); words are indexed from 0.
+    uint64_t h = 0;
+    const uint64_t w0 = lo / 8, w1 = (hi + 7) / 8;
+    const bool aligned = ((uintptr_t)out & 7) == 0;
+    for (uint64_t w = w0 + __lane_id(); w < w1; w += 64) {
+        uint64_t x = 0;
+        const uint64_t b = w * 8;
+        if (aligned && b + 8 <= total) {
+            x = *(const uint64_t *)(out + b);
+        } else {
+            for (int k = 0; k < 8; ++k)
+                if (b + k < total) x |= (uint64_t)out[b + k] << (8 * k);
+        }
+        h ^= mix64(x ^ ((w + 1) * 0x9E3779B97F4A7C15ull));
+    }
+    for (int off = 32; off > 0; off >>= 1) h ^= __shfl_xor(h, off, 64);
+    return h;
+}
+
+__device__ __forceinline__ uint8_t *pe_base(const shmemx_dctx_pub_t &c, int pe) { return c.base + (uint64_t)pe * c.stride; }
+
+// Execute bytes [lo, hi) of a request with one wavefront.
+__device__ void exec_item(const ProgArgs &a, const shmemx_desc_t &d, uint64_t lo, uint64_t hi, uint64_t *hash_acc)
+{
+    const shmemx_dctx_pub_t &c = a.c;
+    uint8_t *out;
+    if (d.op == SHMEMX_OP_AMO_FETCH_ADD) {
+        uint64_t *ctr = (uint64_t *)(pe_base(c, d.target_pe) + d.src);
+        uint64_t *res = (uint64_t *)(pe_base(c, d.issuer_pe) + d.dst);
+        for (uint64_t k = lo / 8 + __lane_id(); k < hi / 8; k += 64)
+            res[k] = __hip_atomic_fetch_add(ctr + k, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        out = (uint8_t *)res;
+    } else {
+        const bool get = d.op == SHMEMX_OP_GET;
+        const int spe = get ? d.target_pe : d.issuer_pe;
+        const int dpe = get ? d.issuer_pe : d.target_pe;
+        out = pe_base(c, dpe) + d.dst;
+        vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(out + lo, pe_base(c, spe) + d.src + lo, hi - lo, __lane_id(),
+                                                             64);
+    }
+    if (a.verify) {
+        vshmem_detail::release_agent();
+        const uint64_t h = hash_range(out, lo, hi, d.nbytes);
+        if (__lane_id() == 0 && h) __hip_atomic_fetch_xor(hash_acc, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ bool valid_request(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d)
+{
+    if (d.issuer_pe < 0 || d.issuer_pe >= c.npes || d.target_pe < 0 || d.target_pe >= c.npes) return false;
+    auto in = [&](uint64_t off, uint64_t n) { return off <= c.user_bytes && n <= c.user_bytes - off; };
+    if (d.op == SHMEMX_OP_PUT || d.op == SHMEMX_OP_GET) return in(d.src, d.nbytes) && in(d.dst, d.nbytes);
+    if (d.op == SHMEMX_OP_AMO_FETCH_ADD)
+        return (d.nbytes & 7) == 0 && (d.src & 7) == 0 && (d.dst & 7) == 0 && in(d.src, d.nbytes) && in(d.dst, d.nbytes);
+    return false;
+}
+
+__device__ void post_completion(const ProgArgs &a, uint32_t slot, Parent &P, int32_t status)
+{
+    shmemx_completion_t *cp = a.comp + slot;
+    cp->ticket = ldr_dev(&P.ticket);
+    cp->t_start = __hip_atomic_load(&P.t_start, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cp->t_end = wall_clock64();
+    cp->hash = __hip_atomic_load(&P.hash, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cp->status = status;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: the record before the done word
+    st_sys(a.ring_done + slot, cp->ticket + 1);
+}
+
+// Front-end: one lane reads the host ring in ticket order and publishes items.
+__device__ void front_end(const ProgArgs &a, uint64_t nworkers)
+{
+    uint64_t next = 0, pub = 0;
+    uint64_t idle0 = wall_clock64();
+    const uint64_t qmask = a.qsize - 1, smask = a.slots - 1;
+    auto publish = [&](uint64_t parent, uint64_t ticket, uint64_t lo, uint64_t hi) -> bool {
+        Item *it = a.items + (pub & qmask);
+        const uint64_t t0 = wall_clock64();
+        while (ld_dev(&it->seq) != pub) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wall_clock64() - t0 > a.idle_ticks) return false;
+        }
+        it->parent = parent;
+        it->ticket = ticket;
+        it->lo = lo;
+        it->hi = hi;
+        st_dev(&it->seq, pub + 1);
+        ++pub;
+        return true;
+    };
+    for (;;) {
+        const uint32_t slot = (uint32_t)(next & smask);
+        if (ld_sys(a.ring_seq + slot) == next + 1) {
+            Parent &P = a.parents[slot];
+            load_desc(P.d, a.ring + slot, true);
+            P.ticket = next;
+            P.t_start = 0;
+            P.hash = 0;
+            if (!valid_request(a.c, P.d)) {
+                P.t_start = wall_clock64();
+                vshmem_detail::latch_error(a.c, 0x2u);
+                post_completion(a, slot, P, -1);
+            } else {
+                const uint64_t n = P.d.nbytes;
+                const uint64_t nitems = n == 0 ? 1 : (n + a.chunk - 1) / a.chunk;
+                P.remaining = nitems;
+                P.status = 0;
+                vshmem_detail::release_agent();
+                bool ok = true;
+                for (uint64_t k = 0; k < nitems && ok; ++k)
+                    ok = publish(slot, next, k * a.chunk, min(n, (k + 1) * a.chunk));
+                if (!ok) break;
+            }
+            ++next;
+            idle0 = wall_clock64();
+            continue;
+        }
+        if (ld_sys(a.stop)) break;
+        if (wall_clock64() - idle0 > a.idle_ticks) {
+            vshmem_detail::latch_error(a.c, 0x4u);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    for (uint64_t w = 0; w < nworkers; ++w)
+        if (!publish(kItemPoison, 0, 0, 0)) break;
+}
+
+__device__ void worker(const ProgArgs &a)
+{
+    const uint64_t qmask = a.qsize - 1;
+    for (;;) {
+        uint64_t t = 0;
+        if (__lane_id() == 0) t = __hip_atomic_fetch_add(a.claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __shfl(t, 0, 64);
+        Item *it = a.items + (t & qmask);
+        bool ready = true;
+        if (__lane_id() == 0) {
+            const uint64_t t0 = wall_clock64();
+            while (ld_dev(&it->seq) != t + 1) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > 2 * a.idle_ticks) {
+                    ready = false;
+                    break;
+                }
+            }
+        }
+        ready = __shfl((int)ready, 0, 64);
+        if (!ready) return;
+        vshmem_detail::acquire_agent();
+        const uint64_t parent = ldr_dev(&it->parent);
+        const uint64_t ticket = ldr_dev(&it->ticket);
+        const uint64_t lo = ldr_dev(&it->lo), hi = ldr_dev(&it->hi);
+        if (__lane_id() == 0) st_dev(&it->seq, t + a.qsize);   // the slot is free again
+        if (parent == kItemPoison) return;
+        Parent &P = a.parents[parent];
+        shmemx_desc_t md;
+        load_desc(md, &P.d, false);
+        if (ldr_dev(&P.ticket) != ticket) {
+            // A record that does not belong to this item: report it, skip it.
+            if (__lane_id() == 0) vshmem_detail::latch_error(a.c, 0x8u);
+            continue;
+        }
+        if (__lane_id() == 0) {
+            uint64_t zero = 0;
+            __hip_atomic_compare_exchange_strong(&P.t_start, &zero, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        exec_item(a, md, lo, hi, &P.hash);
+        vshmem_detail::release_agent();   // this item's stores are complete device-wide
+        if (__lane_id() == 0) {
+            const uint64_t left = __hip_atomic_fetch_sub(&P.remaining, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (left == 1) post_completion(a, parent, P, 0);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_progress(ProgArgs a)
+{
+    const uint64_t waves_per_wg = blockDim.x / 64;
+    const uint64_t nworkers = (uint64_t)gridDim.x * waves_per_wg - 1;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        if (__lane_id() == 0) front_end(a, nworkers);
+        return;
+    }
+    worker(a);
+}
+
+// ------------------------------------------------------------------ host
+struct Progress {
+    bool running = false;
+    uint64_t qsize = 0;
+    hipStream_t stream = nullptr;
+    shmemx_desc_t *ring = nullptr;     // pinned host
+    uint64_t *ring_seq = nullptr;      // pinned host
+    uint64_t *ring_done = nullptr;     // pinned host
+    shmemx_completion_t *comp = nullptr;
+    uint64_t *stop = nullptr;
+    Item *items = nullptr;             // device
+    Parent *parents = nullptr;         // device
+    uint64_t *claim = nullptr;         // device
+    uint64_t slots = 0;
+    std::atomic<uint64_t> head{0};
+};
+
+Progress g_prog;
+
+void release_progress()
+{
+    Progress &p = g_prog;
+    if (p.ring) (void)hipHostFree(p.ring);
+    if (p.ring_seq) (void)hipHostFree(p.ring_seq);
+    if (p.ring_done) (void)hipHostFree(p.ring_done);
+    if (p.comp) (void)hipHostFree(p.comp);
+    if (p.stop) (void)hipHostFree(p.stop);
+    if (p.items) (void)hipFree(p.items);
+    if (p.parents) (void)hipFree(p.parents);
+    if (p.claim) (void)hipFree(p.claim);
+    p.ring = nullptr;
+    p.ring_seq = nullptr;
+    p.ring_done = nullptr;
+    p.comp = nullptr;
+    p.stop = nullptr;
+    p.items = nullptr;
+    p.parents = nullptr;
+    p.claim = nullptr;
+    p.running = false;
+}
+
+template <typename T>
+int host_alloc(T **p, size_t bytes)
+{
+    if (hipHostMalloc((void **)p, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return SHMEMX_ERR_HIP;
+    memset(*p, 0, bytes);
+    return SHMEMX_OK;
+}
+
+template <typename T>
+T *dev_view(T *host)
+{
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, host, 0) != hipSuccess) return nullptr;
+    return (T *)d;
+}
+
+}  // namespace
+
+extern "C" {
+
+}  // extern "C"
+
+namespace vshmem {
+bool progress_running() { return g_prog.running; }
+void progress_release() { release_progress(); }
+}  // namespace vshmem
+
+extern "C" {
+
+int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
+{
+    if (int rc = check_ready()) return rc;
+    Progress &p = g_prog;
+    if (p.running) return SHMEMX_ERR_BUSY;
+    shmemx_progress_cfg_t cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.wg_size == 0) cfg.wg_size = 256;
+    if (cfg.ring_slots == 0) cfg.ring_slots = 4096;
+    if (cfg.chunk_bytes == 0) cfg.chunk_bytes = 256ull << 10;
+    if (cfg.idle_timeout_ms == 0) cfg.idle_timeout_ms = 30000;
+    const State &s = st();
+    if (cfg.nwg == 0) cfg.nwg = s.num_cus;
+    if (!valid_wg_size(cfg.wg_size) || cfg.nwg < 1 || cfg.nwg > 8 * s.num_cus || cfg.ring_slots < 2 ||
+        (cfg.ring_slots & (cfg.ring_slots - 1)) || (cfg.chunk_bytes & 15) || (cfg.nwg == 1 && cfg.wg_size == 64))
+        return SHMEMX_ERR_ARG;
+    const uint64_t slots = (uint64_t)cfg.ring_slots;
+    const uint64_t qsize = 1ull << 16;
+    if (p.ring && p.slots != slots) release_progress();
+    int rc = SHMEMX_OK;
+    if (!p.ring) {
+        rc = host_alloc(&p.ring, slots * sizeof(shmemx_desc_t));
+        if (!rc) rc = host_alloc(&p.ring_seq, slots * sizeof(uint64_t));
+        if (!rc) rc = host_alloc(&p.ring_done, slots * sizeof(uint64_t));
+        if (!rc) rc = host_alloc(&p.comp, slots * sizeof(shmemx_completion_t));
+        if (!rc) rc = host_alloc(&p.stop, 64);
+        if (!rc && hipMalloc((void **)&p.items, qsize * sizeof(Item)) != hipSuccess) rc = SHMEMX_ERR_HIP;
+        if (!rc && hipMalloc((void **)&p.parents, slots * sizeof(Parent)) != hipSuccess) rc = SHMEMX_ERR_HIP;
+        if (!rc && hipMalloc((void **)&p.claim, 256) != hipSuccess) rc = SHMEMX_ERR_HIP;
+    }
+    if (rc || !p.ring_seq || !p.ring_done || !p.comp || !p.stop || !p.items || !p.parents || !p.claim) {
+        if (!rc) rc = SHMEMX_ERR_HIP;
+        release_progress();
+        return rc;
+    }
+    for (uint64_t i = 0; i < slots; ++i) {
+        p.ring_seq[i] = i;
+        p.ring_done[i] = 0;
+    }
+    memset(p.comp, 0, slots * sizeof(shmemx_completion_t));
+    *p.stop = 0;
+    std::vector<Item> init(qsize);
+    for (uint64_t i = 0; i < qsize; ++i) init[i] = Item{i, 0, 0, 0, 0, {0, 0, 0}};
+    hipStream_t hs = (hipStream_t)stream;
+    if (hipMemcpyAsync(p.items, init.data(), qsize * sizeof(Item), hipMemcpyHostToDevice, hs) != hipSuccess ||
+        hipMemsetAsync(p.claim, 0, 256, hs) != hipSuccess || hipMemsetAsync(p.parents, 0, slots * sizeof(Parent), hs) != hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess) {
+        release_progress();
+        return SHMEMX_ERR_HIP;
+    }
+    ProgArgs a{};
+    a.c = pub();
+    a.ring = dev_view(p.ring);
+    a.ring_seq = dev_view(p.ring_seq);
+    a.ring_done = dev_view(p.ring_done);
+    a.comp = dev_view(p.comp);
+    a.stop = dev_view(p.stop);
+    if (!a.ring || !a.ring_seq || !a.ring_done || !a.comp || !a.stop) {
+        release_progress();
+        return SHMEMX_ERR_HIP;
+    }
+    a.items = p.items;
+    a.parents = p.parents;
+    a.claim = p.claim;
+    a.slots = slots;
+    a.qsize = qsize;
+    a.chunk = cfg.chunk_bytes;
+    a.idle_ticks = cfg.idle_timeout_ms * (s.wallclock_hz / 1000);
+    a.verify = cfg.verify;
+    p.slots = slots;
+    p.head.store(0);
+    p.stream = hs;
+    hipLaunchKernelGGL(k_progress, dim3(cfg.nwg), dim3(cfg.wg_size), 0, hs, a);
+    if (hipGetLastError() != hipSuccess) {
+        release_progress();
+        return SHMEMX_ERR_HIP;
+    }
+    p.running = true;
+    return SHMEMX_OK;
+}
+
+int shmemx_progress_submit(const shmemx_desc_t *desc, uint64_t *ticket)
+{
+    Progress &p = g_prog;
+    if (!p.running) return SHMEMX_ERR_STATE;
+    if (!desc || !ticket) return SHMEMX_ERR_ARG;
+    const uint64_t mask = p.slots - 1;
+    uint64_t t = p.head.load(std::memory_order_relaxed);
+    for (;;) {
+        const uint64_t s = __atomic_load_n(p.ring_seq + (t & mask), __ATOMIC_ACQUIRE);
+        if (s == t) {
+            if (p.head.compare_exchange_weak(t, t + 1, std::memory_order_relaxed)) break;
+        } else if (s < t) {
+            return SHMEMX_ERR_BUSY;   // the slot still holds a request in flight: the ring is full
+        } else {
+            t = p.head.load(std::memory_order_relaxed);
+        }
+    }
+    p.ring[t & mask] = *desc;
+    __atomic_store_n(p.ring_seq + (t & mask), t + 1, __ATOMIC_RELEASE);
+    *ticket = t;
+    return SHMEMX_OK;
+}
+
+int shmemx_progress_poll(uint64_t ticket, shmemx_completion_t *out)
+{
+    Progress &p = g_prog;
+    if (!p.ring_seq) return SHMEMX_ERR_STATE;
+    const uint64_t slot = ticket & (p.slots - 1);
+    uint64_t s = __atomic_load_n(p.ring_seq + slot, __ATOMIC_ACQUIRE);
+    if (s > ticket + 1) {               // consumed by an earlier poll: the record is gone
+        if (out) {
+            memset(out, 0, sizeof(*out));
+            out->ticket = ticket;
+        }
+        return 1;
+    }
+    if (s != ticket + 1) return 0;      // not submitted
+    if (__atomic_load_n(p.ring_done + slot, __ATOMIC_ACQUIRE) != ticket + 1) return 0;
+    shmemx_completion_t c = p.comp[slot];
+    // Consume: free the slot for ticket + slots (only one poller wins).
+    if (!__atomic_compare_exchange_n(p.ring_seq + slot, &s, ticket + p.slots, false, __ATOMIC_ACQ_REL,
+                                     __ATOMIC_ACQUIRE)) {
+        memset(&c, 0, sizeof(c));
+        c.ticket = ticket;
+    }
+    if (out) *out = c;
+    return 1;
+}
+
+int shmemx_progress_stop(int timeout_ms)
+{
+    Progress &p = g_prog;
+    if (!p.running) return SHMEMX_ERR_STATE;
+    __atomic_store_n(p.stop, 1ull, __ATOMIC_RELEASE);
+    auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        hipError_t e = hipStreamQuery(p.stream);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) {
+            release_progress();
+            return SHMEMX_ERR_HIP;
+        }
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms)) return SHMEMX_ERR_TIMEOUT;
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+    p.running = false;     // buffers stay allocated for the next start
+    return SHMEMX_OK;
+}
+
+}  // extern "C"

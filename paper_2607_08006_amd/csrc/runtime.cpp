@@ -257,7 +257,9 @@ void shmem_finalize(void)
         set_last_error(SHMEMX_ERR_STATE);
         return;
     }
+    if (progress_running()) (void)shmemx_progress_stop(10000);
     (void)hipDeviceSynchronize();
+    progress_release();
     if (s.d_ctx) (void)hipFree(s.d_ctx);
     if (s.d_err) (void)hipFree(s.d_err);
     if (s.owns_heap && s.base) (void)hipFree(s.base);

@@ -71,6 +71,8 @@ uint64_t sym_offset(const void *p, uint64_t n);
 const shmemx_launch_t &launch_or_default(const shmemx_launch_t *l, shmemx_launch_t &tmp, int def_wgs,
                                          int def_wg, uint64_t def_chunk);
 bool valid_wg_size(int wg);
+bool progress_running();
+void progress_release();
 
 }  // namespace vshmem
 

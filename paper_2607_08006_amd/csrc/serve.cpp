@@ -1,0 +1,215 @@
+// Trace-driven serving on the persistent progress kernel: producer threads
+// replay arrivals, admission reserves destination memory under a heap
+// budget, and a completion thread frees reservations as requests finish so
+// new ones are admitted while others are still on the device.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "runtime.hpp"
+
+using namespace vshmem;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Admission {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<SymAllocator> dst;     // per PE, offsets relative to the region
+    std::vector<uint64_t> ctr_next;    // per PE bump pointer of the counter pool
+    uint64_t ctr_base = 0, ctr_bytes = 0;
+    uint64_t budget = 0, reserved = 0, max_reserved = 0, waits = 0;
+};
+
+struct Slot {
+    std::atomic<int> state{0};          // 0 waiting, 1 submitted, 2 done
+    uint64_t ticket = 0;
+    Clock::time_point arrival;
+    uint64_t dst = 0, ctr = 0, bytes = 0;
+    int dst_pe = 0;
+};
+
+uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+extern "C" int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
+                                uint64_t region_bytes, uint64_t budget_bytes, uint64_t *dst_off_out, uint64_t *latency_ns,
+                                shmemx_completion_t *completions, shmemx_serve_stats_t *stats)
+{
+    if (int rc = check_ready()) return rc;
+    if (!progress_running()) return SHMEMX_ERR_STATE;
+    const State &s = st();
+    if ((!reqs && n) || lanes < 1 || lanes > 64 || !in_user_heap(region_off, region_bytes) || region_bytes < 4096 ||
+        budget_bytes == 0)
+        return SHMEMX_ERR_ARG;
+    for (size_t i = 0; i < n; ++i) {
+        const shmemx_request_t &r = reqs[i];
+        bool ok = r.issuer_pe >= 0 && r.issuer_pe < s.npes && r.target_pe >= 0 && r.target_pe < s.npes && r.lane >= 0 &&
+                  r.lane < lanes && r.arrival_s >= 0 && r.nbytes > 0 &&
+                  (r.op == SHMEMX_OP_PUT || r.op == SHMEMX_OP_GET || r.op == SHMEMX_OP_AMO_FETCH_ADD);
+        if (ok && r.op != SHMEMX_OP_AMO_FETCH_ADD) ok = in_user_heap(r.src_off, r.nbytes);
+        if (ok && r.op == SHMEMX_OP_AMO_FETCH_ADD) ok = (r.nbytes & 7) == 0;
+        if (!ok) return SHMEMX_ERR_ARG;
+    }
+    // Destinations: the lower three quarters of the region, first fit with
+    // reuse.  Counters of fetch_add requests: the top quarter, bump
+    // allocated so every request starts from zeroed counters.
+    Admission adm;
+    const uint64_t dst_bytes = (region_bytes / 4 * 3) & ~255ull;
+    adm.dst.resize(s.npes);
+    for (auto &a : adm.dst) a.reset(dst_bytes);
+    adm.ctr_next.assign(s.npes, 0);
+    adm.ctr_base = region_off + dst_bytes;
+    adm.ctr_bytes = (region_bytes - dst_bytes) & ~255ull;
+    adm.budget = budget_bytes;
+    std::vector<Slot> slots(n);
+    std::atomic<int> failed{0};
+    std::atomic<size_t> ndone{0};
+    const Clock::time_point start = Clock::now() + std::chrono::milliseconds(2);
+
+    auto producer = [&](int lane) {
+        for (size_t i = 0; i < n && !failed.load(); ++i) {
+            const shmemx_request_t &r = reqs[i];
+            if (r.lane != lane) continue;
+            const Clock::time_point due = start + std::chrono::duration_cast<Clock::duration>(
+                                                      std::chrono::duration<double>(r.arrival_s));
+            std::this_thread::sleep_until(due);
+            Slot &sl = slots[i];
+            sl.arrival = due;
+            const uint64_t need = round_up(r.nbytes, 256);
+            const int dpe = r.op == SHMEMX_OP_PUT ? r.target_pe : r.issuer_pe;   // GET and AMO results land on the issuer
+            {
+                std::unique_lock<std::mutex> lk(adm.mu);
+                bool waited = false;
+                for (;;) {
+                    if (failed.load()) return;
+                    const uint64_t extra = need + (r.op == SHMEMX_OP_AMO_FETCH_ADD ? need : 0);
+                    if (extra > adm.budget) {          // could never be admitted
+                        failed.store(SHMEMX_ERR_NOMEM);
+                        adm.cv.notify_all();
+                        return;
+                    }
+                    if (adm.reserved + extra <= adm.budget) {
+                        if (r.op == SHMEMX_OP_AMO_FETCH_ADD &&
+                            adm.ctr_next[r.target_pe] + need > adm.ctr_bytes) {
+                            failed.store(SHMEMX_ERR_NOMEM);
+                            adm.cv.notify_all();
+                            return;
+                        }
+                        const uint64_t off = adm.dst[dpe].alloc(need, 256);
+                        if (off != UINT64_MAX) {
+                            sl.dst = region_off + off;
+                            sl.dst_pe = dpe;
+                            if (r.op == SHMEMX_OP_AMO_FETCH_ADD) {
+                                sl.ctr = adm.ctr_base + adm.ctr_next[r.target_pe];
+                                adm.ctr_next[r.target_pe] += need;
+                            }
+                            sl.bytes = extra;
+                            adm.reserved += extra;
+                            adm.max_reserved = std::max(adm.max_reserved, adm.reserved);
+                            break;
+                        }
+                        if (need > dst_bytes) {
+                            failed.store(SHMEMX_ERR_NOMEM);
+                            adm.cv.notify_all();
+                            return;
+                        }
+                    }
+                    if (!waited) {
+                        adm.waits++;
+                        waited = true;
+                    }
+                    adm.cv.wait_for(lk, std::chrono::milliseconds(5));
+                }
+            }
+            shmemx_desc_t d{};
+            d.op = (uint8_t)r.op;
+            d.scope = SHMEMX_SCOPE_AUTO;
+            d.issuer_pe = r.issuer_pe;
+            d.target_pe = r.target_pe;
+            d.result_idx = SHMEMX_NO_RESULT;
+            d.nbytes = r.nbytes;
+            if (r.op == SHMEMX_OP_AMO_FETCH_ADD) {
+                d.src = sl.ctr;
+                d.dst = sl.dst;
+                d.value = 1;
+            } else {
+                d.src = r.src_off;
+                d.dst = sl.dst;
+            }
+            uint64_t t = 0;
+            int rc;
+            const Clock::time_point t0 = Clock::now();
+            while ((rc = shmemx_progress_submit(&d, &t)) == SHMEMX_ERR_BUSY) {
+                if (Clock::now() - t0 > std::chrono::seconds(30)) break;
+                std::this_thread::yield();
+            }
+            if (rc != SHMEMX_OK) {
+                failed.store(rc);
+                return;
+            }
+            sl.ticket = t;
+            sl.state.store(1, std::memory_order_release);
+        }
+    };
+
+    auto completer = [&]() {
+        size_t lo = 0;
+        Clock::time_point last_progress = Clock::now();
+        while (ndone.load() < n && !failed.load()) {
+            bool any = false;
+            size_t scan_end = n;
+            for (size_t i = lo; i < scan_end; ++i) {
+                Slot &sl = slots[i];
+                const int stt = sl.state.load(std::memory_order_acquire);
+                if (stt != 1) continue;
+                shmemx_completion_t c;
+                if (shmemx_progress_poll(sl.ticket, &c) == 1) {
+                    const Clock::time_point now = Clock::now();
+                    if (latency_ns) latency_ns[i] = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - sl.arrival).count();
+                    if (completions) completions[i] = c;
+                    if (dst_off_out) dst_off_out[i] = sl.dst;
+                    {
+                        std::lock_guard<std::mutex> lk(adm.mu);
+                        adm.dst[sl.dst_pe].free(sl.dst - region_off);
+                        adm.reserved -= sl.bytes;
+                    }
+                    adm.cv.notify_all();
+                    sl.state.store(2, std::memory_order_release);
+                    ndone.fetch_add(1);
+                    any = true;
+                    if (c.status != 0) failed.store(SHMEMX_ERR_DEVICE);
+                }
+            }
+            while (lo < n && slots[lo].state.load(std::memory_order_acquire) == 2) ++lo;
+            if (any) last_progress = Clock::now();
+            else if (Clock::now() - last_progress > std::chrono::seconds(60)) failed.store(SHMEMX_ERR_TIMEOUT);
+            else std::this_thread::yield();
+        }
+    };
+
+    std::vector<std::thread> th;
+    for (int l = 0; l < lanes; ++l) th.emplace_back(producer, l);
+    std::thread ct(completer);
+    for (auto &t : th) t.join();
+    ct.join();
+    const double wall = std::chrono::duration<double>(Clock::now() - start).count();
+    if (stats) {
+        stats->wall_s = wall;
+        stats->bytes = 0;
+        stats->amo_ops = 0;
+        for (size_t i = 0; i < n; ++i) {
+            if (reqs[i].op == SHMEMX_OP_AMO_FETCH_ADD) stats->amo_ops += reqs[i].nbytes / 8;
+            else stats->bytes += reqs[i].nbytes;
+        }
+        stats->max_reserved_bytes = adm.max_reserved;
+        stats->admission_waits = adm.waits;
+    }
+    return failed.load();
+}

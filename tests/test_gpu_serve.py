@@ -1,0 +1,184 @@
+"""GPU: the persistent progress kernel and trace-driven serving.
+
+Every request's output must equal the oracle's, whether the request runs
+alone or among others; admission must never exceed the heap budget; every
+request completes exactly once."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workload as W
+from tests.gpu_helpers import assert_no_device_errors, download, heap, torch, upload
+
+pytestmark = pytest.mark.gpu
+
+GOLD = 0x9E3779B97F4A7C15
+M64 = (1 << 64) - 1
+
+
+def out_hash(b: np.ndarray) -> int:
+    """XOR over 8-byte words w_i (zero padded) of mix(w_i ^ ((i + 1) * golden))."""
+    n = len(b)
+    pad = np.zeros(((n + 7) // 8) * 8, dtype=np.uint8)
+    pad[:n] = b
+    w = pad.view("<u8")
+    idx = np.arange(1, len(w) + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = w ^ (idx * np.uint64(GOLD))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return int(np.bitwise_xor.reduce(z)) if len(z) else 0
+
+
+def _desc(op, issuer, target, src, dst, n, value=0):
+    d = W.descs([(op, W.SCOPE_AUTO, 0, issuer, target, W.NO_RESULT, src, dst, n, value, 0)])
+    from paper_2607_08006_amd import Desc
+    return Desc.from_buffer_copy(d.tobytes())
+
+
+def test_progress_submit_poll_matches_oracle():
+    npes = 8
+    with heap(npes, 8 << 20) as v:
+        t = torch()
+        region = 6 << 20
+        init = W.heap_fill(0xC0FFEE, npes, region)
+        init[:, 5 << 20:] = 0                             # counters start at zero
+        upload(init)
+        side = t.cuda.Stream()
+        v.progress_start(nwg=64, wg_size=256, ring_slots=64, verify=True, chunk_bytes=64 << 10, stream=side)
+        reqs = [
+            (W.OP_PUT, 0, 3, 0, 2 << 20, 100),
+            (W.OP_GET, 5, 1, 4096, (2 << 20) + 4096, 70_000),          # several chunks + ragged tail
+            (W.OP_PUT, 7, 7, 8192, (3 << 20), 1 << 20),                # 16 chunks, self target
+            (W.OP_AMO_FETCH_ADD, 2, 6, 5 << 20, (4 << 20), 4096),      # 512 counters, results on issuer
+            (W.OP_PUT, 1, 2, 13, (2 << 20) + 77, 999),                 # unaligned
+        ]
+        tickets = [v.progress_submit(_desc(*r, value=1 if r[0] == W.OP_AMO_FETCH_ADD else 0)) for r in reqs]
+        comps = {}
+        t0 = time.time()
+        while len(comps) < len(tickets) and time.time() - t0 < 30:
+            for tk in tickets:
+                if tk not in comps:
+                    c = v.progress_poll(tk)
+                    if c is not None:
+                        comps[tk] = c
+        v.progress_stop(10000)
+        side.synchronize()
+        assert len(comps) == len(tickets)
+        got = download(region)
+        ref = init.copy()
+        recs = []
+        for k, (op, i, tg, s, d, n) in enumerate(reqs):
+            if op == W.OP_AMO_FETCH_ADD:
+                for w in range(n // 8):
+                    recs.append((op, 0, 0, i, tg, W.NO_RESULT, s + 8 * w, 0, 8, 1, 0))
+            else:
+                recs.append((op, 0, 0, i, tg, W.NO_RESULT, s, d, n, 0, 0))
+        oracle.run_program(ref, W.descs(recs))
+        # the AMO's fetched values (zeros) land in the issuer's result range
+        op, i, tg, s, d, n = reqs[3]
+        ref[i, d:d + n] = 0
+        assert np.array_equal(got, ref)
+        for tk, (op, i, tg, s, d, n) in zip(tickets, reqs):
+            c = comps[tk]
+            assert c.status == 0 and c.t_end >= c.t_start > 0
+            out_pe = tg if op == W.OP_PUT else i
+            assert c.hash == out_hash(ref[out_pe, d:d + n])
+        assert_no_device_errors()
+
+
+def _trace(npes, n, rate, src_bytes, seed, max_log2=14):
+    rs = W.serve_requests(seed, n, npes, rate_per_s=rate, lanes=8, size_log2_span=max_log2)
+    from paper_2607_08006_amd import Request
+    out = []
+    for r in rs:
+        nb = min(r.nbytes, src_bytes)
+        if r.kind == W.OP_AMO_FETCH_ADD:
+            nb = max(8, nb & ~7)
+        src = 0 if r.kind == W.OP_AMO_FETCH_ADD else int(W.splitmix64(seed, len(out), 1)[0] % np.uint64(src_bytes - nb + 1))
+        out.append(Request(r.kind, r.issuer, r.target, r.lane, nb, src, r.arrival_s))
+    return out
+
+
+def _expected_hashes(reqs, init):
+    hs = []
+    for r in reqs:
+        if r.op == W.OP_AMO_FETCH_ADD:
+            hs.append(out_hash(np.zeros(r.nbytes, dtype=np.uint8)))
+        else:
+            spe = r.issuer_pe if r.op == W.OP_PUT else r.target_pe
+            hs.append(out_hash(init[spe, r.src_off:r.src_off + r.nbytes]))
+    return hs
+
+
+def test_serving_alone_equals_mix_and_budget_holds():
+    npes, n = 16, 400
+    src_bytes = 2 << 20
+    with heap(npes, 40 << 20) as v:
+        t = torch()
+        init = W.heap_fill(0xBEEF, npes, src_bytes)
+        upload(init)
+        region_off, region_bytes = 4 << 20, 32 << 20
+        reqs = _trace(npes, n, rate=2e5, src_bytes=src_bytes, seed=W.SEED_SERVE)
+        want = _expected_hashes(reqs, init)
+        side = t.cuda.Stream()
+
+        def run(trace, budget):
+            h = v.heap_view()
+            h[:, region_off:region_off + region_bytes].zero_()
+            t.cuda.synchronize()
+            v.progress_start(nwg=128, wg_size=256, ring_slots=256, verify=True, chunk_bytes=64 << 10, stream=side)
+            try:
+                dst, lat, comps, stats = v.serve_run(trace, 8, region_off, region_bytes, budget)
+            finally:
+                v.progress_stop(20000)
+                side.synchronize()
+            return dst, lat, comps, stats
+
+        # in the mix: bursty Poisson arrivals, a budget small enough to make requests wait
+        budget = 3 << 20
+        dst, lat, comps, stats = run(reqs, budget)
+        assert stats.max_reserved_bytes <= budget
+        assert stats.admission_waits > 0
+        tickets = [c.ticket for c in comps]
+        assert len(set(tickets)) == n                      # no lost or duplicated completion
+        mix = [c.hash for c in comps]
+        assert all(c.status == 0 for c in comps)
+        assert (lat > 0).all()
+        # alone: one request at a time, far apart
+        from paper_2607_08006_amd import Request
+        alone_trace = [Request(r.op, r.issuer_pe, r.target_pe, 0, r.nbytes, r.src_off, 0.0002 * k)
+                       for k, r in enumerate(reqs)]
+        _, _, comps_a, stats_a = run(alone_trace, 1 << 30)
+        alone = [c.hash for c in comps_a]
+        bad = [(i, reqs[i].op, reqs[i].nbytes, mix[i] == want[i], alone[i] == want[i])
+               for i in range(n) if not (mix[i] == alone[i] == want[i])]
+        assert not bad, bad[:20]
+        assert_no_device_errors()
+
+
+def test_progress_rejects_bad_config_and_busy_ring():
+    with heap(4, 4 << 20) as v:
+        t = torch()
+        with pytest.raises(v.VshmemError):
+            v.progress_start(nwg=1, wg_size=64)                 # no worker wavefronts
+        with pytest.raises(v.VshmemError):
+            v.progress_start(ring_slots=3)                      # not a power of two
+        side = t.cuda.Stream()
+        v.progress_start(nwg=8, wg_size=128, ring_slots=4, stream=side, idle_timeout_ms=5000)
+        with pytest.raises(v.VshmemError):
+            v.progress_start(nwg=8, stream=side)                # already running
+        # invalid request (outside the heap) completes with an error status
+        bad = _desc(W.OP_PUT, 0, 1, v.heap_user_bytes() - 8, 0, 64)
+        tk = v.progress_submit(bad)
+        c = None
+        t0 = time.time()
+        while c is None and time.time() - t0 < 10:
+            c = v.progress_poll(tk)
+        assert c is not None and c.status == -1
+        v.progress_stop(10000)
+        side.synchronize()
+        assert v.device_errors() & v.DEVERR_BAD_DESC
