@@ -55,6 +55,11 @@ def parse():
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="also run one plain copy of this size (counter scaling reference)")
     ap.add_argument("--out", default="", help="also write the JSON line to this file")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the step: the full put/get sweep (8 B - 64 MiB, 3 scopes, 2 patterns)")
+    ap.add_argument("--serve", action="store_true",
+                    help="instead of the step: open-loop Poisson serving on 128 PEs x 512 MiB, 64 GiB budget")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     return ap.parse_args()
 
 
@@ -210,6 +215,41 @@ def batch_latencies(v, B):
     return out
 
 
+def serve_setup(v, torch, L: Layout, npes: int, nreq: int = 1000):
+    """A burst of mixed put/get/fetch_add requests (log-uniform 64 B - 16 MiB)
+    for the persistent progress kernel; sources in A, destinations and
+    counters in B, admission under an 8 GiB budget."""
+    reqs = serve_trace(v, npes, nreq, rate=1e12, src_bytes=L.B - L.A, seed=W.SEED_SERVE)
+    side = torch.cuda.Stream()
+    return dict(reqs=reqs, side=side, region_off=L.B, region_bytes=L.C - L.B, budget=8 << 30,
+                bytes=sum(2 * r.nbytes if r.op != W.OP_AMO_FETCH_ADD else 2 * r.nbytes for r in reqs))
+
+
+def serve_trace(v, npes, n, rate, src_bytes, seed):
+    from paper_2607_08006_amd import Request
+    out = []
+    xs = W.splitmix64(W.subseed(seed, 0x77), 0, n)
+    for i, r in enumerate(W.serve_requests(seed, n, npes, rate_per_s=rate, lanes=8)):
+        nb = min(r.nbytes, src_bytes)
+        src = 0
+        if r.kind == W.OP_AMO_FETCH_ADD:
+            nb = max(8, nb & ~7)
+        else:
+            src = int(xs[i] % np.uint64(src_bytes - nb + 1))
+        out.append(Request(r.kind, r.issuer, r.target, r.lane, nb, src, r.arrival_s))
+    return out
+
+
+def serve_step(v, S):
+    v.progress_start(nwg=0, wg_size=256, ring_slots=4096, verify=False, chunk_bytes=256 << 10, stream=S["side"])
+    try:
+        dst, lat, comps, stats = v.serve_run(S["reqs"], 8, S["region_off"], S["region_bytes"], S["budget"])
+    finally:
+        v.progress_stop(30000)
+        S["side"].synchronize()
+    return lat, comps, stats
+
+
 def percentile(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
 
@@ -293,6 +333,106 @@ def cpu_baseline(seconds: float):
             "seconds": round(tot_t, 2)}
 
 
+def timed_ms(torch, fn, reps):
+    st = torch.cuda.current_stream()
+    ts = []
+    for r in range(reps + 1):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        b.synchronize()
+        if r:
+            ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def run_sweep(v, torch, args):
+    """The put/get bandwidth sweep: 8 B - 64 MiB, thread/wavefront/work-group
+    (and grid for >= 1 MiB) scopes, ring and derangement, put and get; each
+    round is min(2^28 / s, 2^14) messages per PE followed by quiet."""
+    npes = args.npes
+    v.init(npes, args.heap_mib * MiB)
+    A = v.offset(v.malloc(256 * MiB))
+    B = v.offset(v.malloc(256 * MiB))
+    for p in range(npes):
+        pe = v.heap_base() + p * v.heap_stride()
+        v.fill_random(pe + A, 256 * MiB, W.subseed(W.SEED_SWEEP, W.TAG_HEAP + p))
+    torch.cuda.synchronize()
+    tg = {pat: torch.from_numpy(W.pattern_targets(pat, npes).astype(np.int32)).cuda() for pat in ("ring", "perm")}
+    points = []
+    for size in W.sweep_sizes():
+        k = W.msgs_per_pe(size)
+        scopes = [v.SCOPE_THREAD, v.SCOPE_WAVE, v.SCOPE_WG] + ([v.SCOPE_GRID] if size >= MiB else [])
+        for scope in scopes:
+            wgs, wg = (4, 256) if scope == v.SCOPE_THREAD else (16, 512)
+            lc = v.launch_cfg(wgs_per_pe=wgs, wg_size=wg, flags=v.LAUNCH_NONTEMPORAL if size >= 65536 else 0)
+            for pat in ("ring", "perm"):
+                for op in (v.OP_PUT, v.OP_GET):
+                    ms = timed_ms(torch, lambda: v.rma_pattern(op, scope, tg[pat], A, B, size, k, launch=lc),
+                                  1 if (scope == v.SCOPE_THREAD and size >= MiB) else 3)
+                    payload = npes * k * size
+                    points.append({"size": size, "scope": ["thread", "wave", "wg", "grid"][scope], "pattern": pat,
+                                   "op": "put" if op == v.OP_PUT else "get", "msgs_per_pe": k, "ms": round(ms, 4),
+                                   "payload_GB_s": round(payload / ms / 1e6, 2),
+                                   "hbm_GB_s": round(2 * payload / ms / 1e6, 2),
+                                   "hbm_frac": round(2 * payload / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                   "Mops_s": round(npes * k / ms / 1e3, 3)})
+                    log(json.dumps(points[-1]))
+    v.finalize()
+    return {"mode": "sweep", "npes": npes, "heap_bytes_per_pe": args.heap_mib * MiB, "points": points}
+
+
+def run_serve(v, torch, args):
+    """Open-loop serving: saturated burst first, then Poisson arrivals at 50%
+    and 80% of that byte rate, on 128 PEs x 512 MiB with a 64 GiB budget."""
+    npes, heap = 128, 512 * MiB
+    v.init(npes, heap)
+    src = v.offset(v.malloc(128 * MiB))
+    region = v.offset(v.malloc(384 * MiB))
+    for p in range(npes):
+        v.fill_random(v.heap_base() + p * v.heap_stride() + src, 128 * MiB, W.subseed(W.SEED_SERVE, W.TAG_HEAP + p))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    n = args.serve_requests
+    budget = 64 << 30
+
+    def once(reqs):
+        v.heap_view()[:, region + 288 * MiB:region + 384 * MiB].zero_()
+        torch.cuda.synchronize()
+        v.progress_start(nwg=0, wg_size=256, ring_slots=4096, chunk_bytes=256 << 10, stream=side)
+        try:
+            dst, lat, comps, stats = v.serve_run(reqs, 8, region, 384 * MiB, budget)
+        finally:
+            v.progress_stop(60000)
+            side.synchronize()
+        return lat, comps, stats
+
+    burst = serve_trace(v, npes, n, 1e12, 128 * MiB, W.SEED_SERVE)
+    payload = sum(r.nbytes for r in burst)
+    lat, comps, stats = once(burst)
+    b_sat = payload / stats.wall_s
+    mean_size = payload / n
+    out = {"mode": "serve", "npes": npes, "heap_bytes_per_pe": heap, "budget_bytes": budget, "requests": n,
+           "saturated": {"GB_s": round(b_sat / 1e9, 2), "req_s": round(n / stats.wall_s, 1),
+                         "p50_us": round(percentile(lat / 1e3, 50), 1), "p99_us": round(percentile(lat / 1e3, 99), 1),
+                         "max_reserved_bytes": int(stats.max_reserved_bytes)}}
+    warm = n // 20
+    for rho in (0.5, 0.8):
+        lam = rho * b_sat / mean_size
+        reqs = serve_trace(v, npes, n, lam, 128 * MiB, W.SEED_SERVE)
+        lat, comps, stats = once(reqs)
+        l = lat[warm:] / 1e3
+        out[f"rho_{rho}"] = {"offered_GB_s": round(rho * b_sat / 1e9, 2), "GB_s": round(payload / stats.wall_s / 1e9, 2),
+                             "p50_us": round(percentile(l, 50), 1), "p99_us": round(percentile(l, 99), 1),
+                             "admission_waits": int(stats.admission_waits),
+                             "max_reserved_bytes": int(stats.max_reserved_bytes)}
+        log(json.dumps(out[f"rho_{rho}"]))
+    v.finalize()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -305,6 +445,14 @@ def main():
     import paper_2607_08006_amd as v
 
     torch.cuda.set_device(0)
+    if args.sweep or args.serve:
+        rec = run_sweep(v, torch, args) if args.sweep else run_serve(v, torch, args)
+        line = json.dumps(rec)
+        print(line, flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(line + "\n")
+        return
     npes = args.npes
     want = set(r for r in args.rows.split(",") if r)
     log(f"init {npes} PEs x {args.heap_mib} MiB")
@@ -319,6 +467,9 @@ def main():
     if do_batch:
         log("building batch plan")
         B = batch_setup(v, torch, L, npes)
+    do_serve = not want or "serve" in want
+    if do_serve:
+        S = serve_setup(v, torch, L, npes)
     stream = torch.cuda.current_stream()
 
     def one_step(record):
@@ -341,6 +492,12 @@ def main():
             if record:
                 torch.cuda.synchronize()
                 lat = (batch_latencies(v, B), (e0, e1))
+        if do_serve:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            slat, scomps, sstats = serve_step(v, S)
+            if record:
+                lat = (lat, (slat, scomps, sstats, time.perf_counter() - t0))
         return lat
 
     log(f"warmup {args.warmup}")
@@ -351,8 +508,12 @@ def main():
     lats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    serve_recs = []
     for _ in range(args.steps):
         lat = one_step(True)
+        if do_serve:
+            lat, srec = lat
+            serve_recs.append(srec)
         for r in rows:
             r._evs = getattr(r, "_evs", []) + [r._ev]
         lats.append(lat)
@@ -393,6 +554,25 @@ def main():
                           "launch; graph = the fused launch replayed from a hipGraph",
             **forms,
         }
+    serving = None
+    if do_serve:
+        hz = v.wallclock_hz()
+        lat_all = np.concatenate([r[0] for r in serve_recs]) / 1e3
+        svc = np.concatenate([np.array([(c.t_end - c.t_start) for c in r[1]], dtype=np.float64) for r in serve_recs])
+        svc = svc / hz * 1e6
+        wall = float(np.median([r[3] for r in serve_recs]))
+        nbytes = S["bytes"]
+        step_bytes += nbytes
+        st_ = serve_recs[-1][2]
+        out_rows["serve_progress_kernel"] = {"ms": round(wall * 1e3, 3),
+                                             "GB_s": round(nbytes / wall / 1e9, 2),
+                                             "req_s": round(len(S["reqs"]) / wall, 1)}
+        serving = {"requests": len(S["reqs"]), "arrivals": "burst at t=0 over 8 producer lanes",
+                   "sizes": "log-uniform 64 B - 16 MiB; kinds put/get/fetch_add",
+                   "budget_bytes": S["budget"], "max_reserved_bytes": int(st_.max_reserved_bytes),
+                   "admission_waits": int(st_.admission_waits),
+                   "latency_us": {"p50": round(percentile(lat_all, 50), 1), "p99": round(percentile(lat_all, 99), 1)},
+                   "device_service_us": {"p50": round(percentile(svc, 50), 1), "p99": round(percentile(svc, 99), 1)}}
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
     dom = max((r for r in rows if r.bytes), key=lambda r: float(np.sum(r.ms)), default=None)
     roof = None
@@ -417,6 +597,7 @@ def main():
         "amo_Mops_s": gups.get("Mops_s"),
         "rows": out_rows,
         "latency": latency,
+        "serving": serving,
         "roofline": roof,
         "device_errors": errs,
     }

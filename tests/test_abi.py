@@ -88,3 +88,22 @@ def test_calls_before_init_fail_cleanly():
     assert lib.shmemx_init_attach(ctypes.c_void_p(1 << 21), 3 << 20, 2, None) == v.ERR_ARG   # odd split
     assert lib.shmemx_strerror(v.ERR_TIMEOUT).decode() == "timed out"
     assert v.version().startswith("vshmem")
+
+
+def test_tune_table_json_round_trip(tmp_path):
+    _ensure_built()
+    import paper_2607_08006_amd as v
+    t = v.default_tune()
+    assert t.wg_size == 256 and t.scope[3] == v.SCOPE_THREAD and t.scope[12] == v.SCOPE_WAVE
+    assert t.scope[20] == v.SCOPE_WG and t.chunk[21] == 256 << 10
+    t.wg_size = 512
+    t.scope[17] = v.SCOPE_WAVE
+    t.chunk[25] = 1 << 20
+    path = str(tmp_path / "tune.json")
+    v.tune_save(t, path)
+    u = v.tune_load(path)
+    assert u.wg_size == 512 and u.scope[17] == v.SCOPE_WAVE and u.chunk[25] == 1 << 20
+    assert list(u.scope) == list(t.scope) and list(u.chunk) == list(t.chunk)
+    import json
+    d = json.load(open(path))
+    assert d["wg_size"] == 512 and len(d["classes"]) == 40
