@@ -113,19 +113,25 @@ def build_rows(v, torch, L: Layout, npes: int, want):
             rows.append(Row(name, fn, b, ops, kernel))
 
     # ---- put/get (a2, a3): k(s) = min(2^28 / s, 2^14) messages per PE, each PE ends in quiet
-    def rma(op, scope, tgts, size, wgs, wg, nmsg=None):
+    def rma(op, scope, tgts, size, wgs, wg, nmsg=None, flags=0):
         k = nmsg if nmsg is not None else W.msgs_per_pe(size)
         span = L.B - L.A
         while k * size > span:
             k //= 2
-        lc = v.launch_cfg(wgs_per_pe=wgs, wg_size=wg)
+        lc = v.launch_cfg(wgs_per_pe=wgs, wg_size=wg, flags=flags)
         return (lambda: v.rma_pattern(op, scope, tgts, L.A, L.B, size, k, launch=lc)), 2 * npes * k * size
 
+    # Launch shapes from the measured sweep: about one work-group per CU,
+    # nontemporal 8-deep copies for large messages.
     big = int(16 * MiB * min(1.0, scale))
-    f, b = rma(v.OP_PUT, v.SCOPE_WG, ring, big, 16, 512)
-    add("put_wg_16MiB_ring", f, b, kernel="k_rma_pattern<2,true,false>")
-    f, b = rma(v.OP_GET, v.SCOPE_WG, perm, big, 16, 512)
-    add("get_wg_16MiB_perm", f, b, kernel="k_rma_pattern<2,false,false>")
+    deep = v.LAUNCH_NONTEMPORAL | v.LAUNCH_DEEP
+    f, b = rma(v.OP_PUT, v.SCOPE_WG, ring, big, 4, 1024, flags=deep)
+    add("put_wg_16MiB_ring", f, b, kernel="k_rma_pattern<2,true,true,8>")
+    f, b = rma(v.OP_GET, v.SCOPE_WG, perm, big, 4, 1024, flags=deep)
+    add("get_wg_16MiB_perm", f, b, kernel="k_rma_pattern<2,false,true,8>")
+    huge = int(64 * MiB * min(1.0, scale))
+    f, b = rma(v.OP_PUT, v.SCOPE_GRID, perm, huge, 4, 256, flags=deep)
+    add("put_grid_64MiB_perm", f, b, kernel="k_rma_pattern<3,true,true,8>")
     f, b = rma(v.OP_PUT, v.SCOPE_WAVE, perm, 4096, 16, 256)
     add("put_wave_4KiB_perm", f, b)
     f, b = rma(v.OP_GET, v.SCOPE_THREAD, ring, 64, 4, 256)
@@ -153,7 +159,7 @@ def build_rows(v, torch, L: Layout, npes: int, want):
     # ---- collectives (a7-a10)
     blk = int(1 * MiB * min(1.0, scale))
     add("alltoall_1MiB_fp32", lambda: v.alltoallmem(L.addr(L.B), L.addr(L.C), blk), 2 * npes * npes * blk,
-        kernel="k_alltoall<false>")
+        kernel="k_alltoall<true,4>")
     fc = int(4 * MiB * min(1.0, scale))
     add("fcollect_4MiB", lambda: v.fcollectmem(L.addr(L.B), L.addr(L.C), fc), npes * fc + npes * npes * fc)
     bc = L.D - L.C

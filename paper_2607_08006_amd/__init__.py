@@ -31,6 +31,7 @@ DT_INT64, DT_FP32, DT_BF16 = 0, 1, 2
 RED_SUM, RED_MAX = 0, 1
 TEAM_WORLD, TEAM_SHARED, DEVICE_TEAM_WORLD, DEVICE_TEAM_SHARED = 0, 1, 2, 3
 LAUNCH_NONTEMPORAL = 0x1
+LAUNCH_DEEP = 0x2
 NO_RESULT = 0xFFFFFFFF
 
 SCRATCH_BYTES = 64 << 10

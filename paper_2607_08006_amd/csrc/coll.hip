@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(1024) k_fcollect(Geo g)
     shmemx_team_sync_units(ctx, g.team, g.wgs_per_pe);
 }
 
-template <bool NT>
+template <bool NT, int U>
 __global__ void __launch_bounds__(1024) k_alltoall(Geo g)
 {
     shmem_dctx_t ctx;
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(1024) k_alltoall(Geo g)
         const int q = (int)(blk % P);   // source member
         const uint64_t off = (t - blk * nch) * g.chunk;
         const uint64_t len = min(g.chunk, g.n - off);
-        vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, NT>(pe_addr(g, p, g.dst_off + (uint64_t)q * g.n + off),
+        vshmem_detail::copy_bytes<U, NT>(pe_addr(g, p, g.dst_off + (uint64_t)q * g.n + off),
                                                           pe_addr(g, q, g.src_off + (uint64_t)p * g.n + off), len,
                                                           threadIdx.x, blockDim.x);
     }
@@ -331,10 +331,14 @@ template <typename K, typename... Args>
 int launch_team_kernel(K kernel, Geo &g, int wg, hipStream_t s, bool auto_wgs, Args... args)
 {
     if (auto_wgs) {
+        // About one work-group per CU: in measurements on MI355X, streaming
+        // kernels reached higher HBM bandwidth with one wide work-group per
+        // CU than with the grid filled to its occupancy limit.
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, wg, 0) != hipSuccess) return SHMEMX_ERR_HIP;
-        int64_t cap = (int64_t)per_cu * st().num_cus;
-        g.wgs_per_pe = (int)std::max<int64_t>(1, std::min<int64_t>(16, cap / g.team.size));
+        const int64_t cap = (int64_t)per_cu * st().num_cus;
+        const int64_t want = std::max<int64_t>(1, st().num_cus / g.team.size);
+        g.wgs_per_pe = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap / g.team.size));
     }
     const int grid = g.wgs_per_pe * g.team.size;
     int rc = check_coresident(kernel, grid, wg);
@@ -348,11 +352,13 @@ int launch_team_kernel(K kernel, Geo &g, int wg, hipStream_t s, bool auto_wgs, A
 }
 
 int make_geo(shmem_team_t team, const void *dest, const void *src, uint64_t dst_bytes, uint64_t src_bytes,
-             const shmemx_launch_t *launch, int def_wg, Geo &g, shmemx_launch_t &L)
+             const shmemx_launch_t *launch, int def_wg, Geo &g, shmemx_launch_t &L, uint64_t def_chunk = 256ull << 10,
+             int def_flags = 0)
 {
     if (int rc = check_ready()) return rc;
     if (team_get(team, &g.team) != SHMEMX_OK) return SHMEMX_ERR_ARG;
-    launch_or_default(launch, L, 1, def_wg, 256ull << 10);
+    launch_or_default(launch, L, 1, def_wg, def_chunk);
+    if (!launch) L.flags = def_flags;
     if (launch && launch->wgs_per_pe < 0) return SHMEMX_ERR_ARG;
     if (!valid_wg_size(L.wg_size) || (L.chunk_bytes & 15) || (int64_t)L.wgs_per_pe * g.team.size > (1 << 24))
         return SHMEMX_ERR_ARG;
@@ -419,7 +425,9 @@ int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, si
     if (int r0 = check_ready()) return r0;
     int tsize = shmem_team_n_pes(team);
     int rc = tsize <= 0 ? SHMEMX_ERR_ARG : SHMEMX_OK;
-    if (!rc) rc = make_geo(team, dest, src, (uint64_t)n * tsize, (uint64_t)n * tsize, launch, 256, g, L);
+    if (!rc)
+        rc = make_geo(team, dest, src, (uint64_t)n * tsize, (uint64_t)n * tsize, launch, 256, g, L, 1ull << 20,
+                      SHMEMX_LAUNCH_NONTEMPORAL);
     if (!rc && overlap(g.dst_off, (uint64_t)n * tsize, g.src_off, (uint64_t)n * tsize)) rc = SHMEMX_ERR_ARG;
     if (rc) {
         set_last_error(rc);
@@ -427,9 +435,12 @@ int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, si
     }
     g.n = n;
     const bool aw = !launch || launch->wgs_per_pe == 0;
-    if (L.flags & SHMEMX_LAUNCH_NONTEMPORAL)
-        return launch_team_kernel(k_alltoall<true>, g, L.wg_size, (hipStream_t)stream, aw);
-    return launch_team_kernel(k_alltoall<false>, g, L.wg_size, (hipStream_t)stream, aw);
+    const bool nt = (L.flags & SHMEMX_LAUNCH_NONTEMPORAL) != 0, deep = (L.flags & SHMEMX_LAUNCH_DEEP) != 0;
+    hipStream_t hs = (hipStream_t)stream;
+    if (nt && deep) return launch_team_kernel(k_alltoall<true, 8>, g, L.wg_size, hs, aw);
+    if (nt) return launch_team_kernel(k_alltoall<true, 4>, g, L.wg_size, hs, aw);
+    if (deep) return launch_team_kernel(k_alltoall<false, 8>, g, L.wg_size, hs, aw);
+    return launch_team_kernel(k_alltoall<false, 4>, g, L.wg_size, hs, aw);
 }
 
 int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const void *src, size_t nreduce,
@@ -441,7 +452,7 @@ int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const
     int rc = (dtype < SHMEMX_DT_INT64 || dtype > SHMEMX_DT_BF16 || op < SHMEMX_RED_SUM || op > SHMEMX_RED_MAX)
                  ? SHMEMX_ERR_ARG
                  : SHMEMX_OK;
-    shmemx_launch_t L0 = launch ? *launch : shmemx_launch_t{};
+    shmemx_launch_t L0 = launch ? *launch : shmemx_launch_t{0, 256, 16ull << 10, SHMEMX_LAUNCH_NONTEMPORAL, 0};
     if (L0.wg_size == 0) L0.wg_size = 256;
     if (!rc) rc = make_geo(team, dest, src, nreduce * es, nreduce * es, &L0, 256, g, L);
     // In place is allowed; partial overlap is not.

@@ -148,8 +148,7 @@ __device__ void exec_item(const ProgArgs &a, const shmemx_desc_t &d, uint64_t lo
         const int spe = get ? d.target_pe : d.issuer_pe;
         const int dpe = get ? d.issuer_pe : d.target_pe;
         out = pe_base(c, dpe) + d.dst;
-        vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(out + lo, pe_base(c, spe) + d.src + lo, hi - lo, __lane_id(),
-                                                             64);
+        vshmem_detail::copy_bytes<8, true>(out + lo, pe_base(c, spe) + d.src + lo, hi - lo, __lane_id(), 64);
     }
     if (a.verify) {
         vshmem_detail::release_agent();
@@ -180,63 +179,113 @@ __device__ void post_completion(const ProgArgs &a, uint32_t slot, Parent &P, int
     st_sys(a.ring_done + slot, cp->ticket + 1);
 }
 
-// Front-end: one lane reads the host ring in ticket order and publishes items.
+// Front-end: wavefront 0 of work-group 0.  Each round its 64 lanes look at
+// the next 64 tickets and take the published prefix at once: descriptors
+// are read in parallel, item positions come from a wavefront prefix sum,
+// and one release fence publishes the round's records before the items'
+// sequence words are stored.
+__device__ bool wait_item_free(const ProgArgs &a, Item *it, uint64_t pos)
+{
+    const uint64_t t0 = wall_clock64();
+    while (ldr_dev(&it->seq) != pos) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > a.idle_ticks) return false;
+    }
+    return true;
+}
+
 __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
 {
+    const uint64_t qmask = a.qsize - 1, smask = a.slots - 1;
+    const uint32_t lane = __lane_id();
+    const uint32_t window = a.slots < 64 ? (uint32_t)a.slots : 64u;
     uint64_t next = 0, pub = 0;
     uint64_t idle0 = wall_clock64();
-    const uint64_t qmask = a.qsize - 1, smask = a.slots - 1;
-    auto publish = [&](uint64_t parent, uint64_t ticket, uint64_t lo, uint64_t hi) -> bool {
-        Item *it = a.items + (pub & qmask);
-        const uint64_t t0 = wall_clock64();
-        while (ld_dev(&it->seq) != pub) {
-            __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() - t0 > a.idle_ticks) return false;
-        }
-        it->parent = parent;
-        it->ticket = ticket;
-        it->lo = lo;
-        it->hi = hi;
-        st_dev(&it->seq, pub + 1);
-        ++pub;
-        return true;
-    };
+    bool ok = true;
     for (;;) {
-        const uint32_t slot = (uint32_t)(next & smask);
-        if (ld_sys(a.ring_seq + slot) == next + 1) {
-            Parent &P = a.parents[slot];
-            load_desc(P.d, a.ring + slot, true);
-            P.ticket = next;
-            P.t_start = 0;
-            P.hash = 0;
-            if (!valid_request(a.c, P.d)) {
-                P.t_start = wall_clock64();
-                vshmem_detail::latch_error(a.c, 0x2u);
-                post_completion(a, slot, P, -1);
-            } else {
-                const uint64_t n = P.d.nbytes;
-                const uint64_t nitems = n == 0 ? 1 : (n + a.chunk - 1) / a.chunk;
-                P.remaining = nitems;
-                P.status = 0;
-                vshmem_detail::release_agent();
-                bool ok = true;
-                for (uint64_t k = 0; k < nitems && ok; ++k)
-                    ok = publish(slot, next, k * a.chunk, min(n, (k + 1) * a.chunk));
-                if (!ok) break;
+        const uint64_t t = next + lane;
+        const bool published = lane < window && ldr_sys(a.ring_seq + (t & smask)) == t + 1;
+        const uint64_t mask = __ballot(published);
+        const uint32_t c = ~mask == 0 ? 64u : (uint32_t)__builtin_ctzll(~mask);
+        if (c == 0) {
+            bool stop = false;
+            if (lane == 0) stop = ldr_sys(a.stop) != 0;
+            if (__shfl((int)stop, 0, 64)) break;
+            if (wall_clock64() - idle0 > a.idle_ticks) {
+                if (lane == 0) vshmem_detail::latch_error(a.c, 0x4u);
+                break;
             }
-            ++next;
-            idle0 = wall_clock64();
+            __builtin_amdgcn_s_sleep(2);
             continue;
         }
-        if (ld_sys(a.stop)) break;
-        if (wall_clock64() - idle0 > a.idle_ticks) {
-            vshmem_detail::latch_error(a.c, 0x4u);
-            break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // system scope: descriptors after their sequence words
+        const bool mine = lane < c;
+        const uint32_t slot = (uint32_t)(t & smask);
+        shmemx_desc_t d{};
+        bool valid = false;
+        uint64_t nitems = 0;
+        if (mine) {
+            load_desc(d, a.ring + slot, true);
+            valid = valid_request(a.c, d);
+            nitems = valid ? (d.nbytes == 0 ? 1 : (d.nbytes + a.chunk - 1) / a.chunk) : 0;
         }
-        __builtin_amdgcn_s_sleep(2);
+        uint64_t incl = nitems;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t y = __shfl_up(incl, off, 64);
+            if ((int)lane >= off) incl += y;
+        }
+        const uint64_t first = pub + incl - nitems;
+        const uint64_t total = __shfl(incl, 63, 64);
+        if (mine) {
+            Parent &P = a.parents[slot];
+            P.d = d;
+            P.ticket = t;
+            P.t_start = 0;
+            P.hash = 0;
+            P.remaining = nitems;
+            P.status = 0;
+            for (uint64_t k = 0; k < nitems && ok; ++k) {
+                const uint64_t pos = first + k;
+                Item *it = a.items + (pos & qmask);
+                ok = wait_item_free(a, it, pos);
+                it->parent = slot;
+                it->ticket = t;
+                it->lo = k * a.chunk;
+                it->hi = min(d.nbytes, (k + 1) * a.chunk);
+            }
+        }
+        vshmem_detail::release_agent();   // records and items before their sequence words
+        if (mine) {
+            for (uint64_t k = 0; k < nitems; ++k) {
+                const uint64_t pos = first + k;
+                __hip_atomic_store(&a.items[pos & qmask].seq, pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (!valid) {
+                a.parents[slot].t_start = wall_clock64();
+                vshmem_detail::latch_error(a.c, 0x2u);
+                post_completion(a, slot, a.parents[slot], -1);
+            }
+        }
+        next += c;
+        pub += total;
+        idle0 = wall_clock64();
+        if (!__shfl((int)ok, 0, 64) || __ballot(!ok)) break;
     }
-    for (uint64_t w = 0; w < nworkers; ++w)
-        if (!publish(kItemPoison, 0, 0, 0)) break;
+    // One poison item per worker wavefront, lanes in parallel.
+    for (uint64_t w0 = 0; w0 < nworkers; w0 += 64) {
+        const uint64_t w = w0 + lane;
+        bool freed = false;
+        if (w < nworkers) {
+            Item *it = a.items + ((pub + w - w0) & qmask);
+            freed = wait_item_free(a, it, pub + w - w0);
+            if (freed) it->parent = kItemPoison;
+        }
+        vshmem_detail::release_agent();
+        if (freed)
+            __hip_atomic_store(&a.items[(pub + w - w0) & qmask].seq, pub + w - w0 + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        pub += min<uint64_t>(64, nworkers - w0);
+    }
 }
 
 __device__ void worker(const ProgArgs &a)
@@ -250,7 +299,7 @@ __device__ void worker(const ProgArgs &a)
         bool ready = true;
         if (__lane_id() == 0) {
             const uint64_t t0 = wall_clock64();
-            while (ld_dev(&it->seq) != t + 1) {
+            while (ldr_dev(&it->seq) != t + 1) {
                 __builtin_amdgcn_s_sleep(2);
                 if (wall_clock64() - t0 > 2 * a.idle_ticks) {
                     ready = false;
@@ -282,8 +331,11 @@ __device__ void worker(const ProgArgs &a)
         exec_item(a, md, lo, hi, &P.hash);
         vshmem_detail::release_agent();   // this item's stores are complete device-wide
         if (__lane_id() == 0) {
-            const uint64_t left = __hip_atomic_fetch_sub(&P.remaining, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (left == 1) post_completion(a, parent, P, 0);
+            const uint64_t left = __hip_atomic_fetch_sub(&P.remaining, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (left == 1) {
+                vshmem_detail::acquire_agent();
+                post_completion(a, (uint32_t)parent, P, 0);
+            }
         }
     }
 }
@@ -292,8 +344,8 @@ __global__ void __launch_bounds__(1024) k_progress(ProgArgs a)
 {
     const uint64_t waves_per_wg = blockDim.x / 64;
     const uint64_t nworkers = (uint64_t)gridDim.x * waves_per_wg - 1;
-    if (blockIdx.x == 0 && threadIdx.x < 64) {
-        if (__lane_id() == 0) front_end(a, nworkers);
+    if (blockIdx.x == 0 && threadIdx.x < 64) {   // the whole first wavefront is the front-end
+        front_end(a, nworkers);
         return;
     }
     worker(a);

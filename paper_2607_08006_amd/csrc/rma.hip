@@ -9,7 +9,7 @@ namespace {
 
 // Every virtual PE p issues nmsg messages to targets[p] at the given scope,
 // then quiets.  Work-group w acts for PE w / wgs_per_pe.
-template <int SCOPE, bool IS_PUT, bool NT>
+template <int SCOPE, bool IS_PUT, bool NT, int U>
 __global__ void __launch_bounds__(1024) k_rma_pattern(shmemx_dctx_pub_t c, const int32_t *__restrict__ targets,
                                                       uint64_t src_off, uint64_t dst_off, uint64_t msg, uint64_t nmsg,
                                                       uint64_t sstep, uint64_t dstep, int wgs_per_pe)
@@ -26,35 +26,37 @@ __global__ void __launch_bounds__(1024) k_rma_pattern(shmemx_dctx_pub_t c, const
     if constexpr (SCOPE == SHMEMX_SCOPE_THREAD) {
         const uint64_t nl = (uint64_t)wgs_per_pe * blockDim.x;
         for (uint64_t j = (uint64_t)rank * blockDim.x + threadIdx.x; j < nmsg; j += nl)
-            vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, NT>(D + j * dstep, S + j * sstep, msg, 0, 1);
+            vshmem_detail::copy_bytes<U, NT>(D + j * dstep, S + j * sstep, msg, 0, 1);
     } else if constexpr (SCOPE == SHMEMX_SCOPE_WAVE) {
         const uint64_t waves = blockDim.x / 64;
         const uint64_t nw = (uint64_t)wgs_per_pe * waves;
         for (uint64_t j = (uint64_t)rank * waves + threadIdx.x / 64; j < nmsg; j += nw)
-            vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, NT>(D + j * dstep, S + j * sstep, msg, __lane_id(), 64);
+            vshmem_detail::copy_bytes<U, NT>(D + j * dstep, S + j * sstep, msg, __lane_id(), 64);
     } else if constexpr (SCOPE == SHMEMX_SCOPE_WG) {
         for (uint64_t j = rank; j < nmsg; j += wgs_per_pe)
-            vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, NT>(D + j * dstep, S + j * sstep, msg, threadIdx.x,
-                                                              blockDim.x);
+            vshmem_detail::copy_bytes<U, NT>(D + j * dstep, S + j * sstep, msg, threadIdx.x, blockDim.x);
     } else {
         const uint64_t lane = (uint64_t)rank * blockDim.x + threadIdx.x;
         const uint64_t nl = (uint64_t)wgs_per_pe * blockDim.x;
         for (uint64_t j = 0; j < nmsg; ++j)
-            vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, NT>(D + j * dstep, S + j * sstep, msg, lane, nl);
+            vshmem_detail::copy_bytes<U, NT>(D + j * dstep, S + j * sstep, msg, lane, nl);
     }
     vshmem_detail::release_agent();   // quiet
 }
 
 template <int SCOPE, bool IS_PUT>
-void launch_pattern(bool nt, int grid, int wg, hipStream_t s, const shmemx_dctx_pub_t &c, const int32_t *targets,
+void launch_pattern(int flags, int grid, int wg, hipStream_t s, const shmemx_dctx_pub_t &c, const int32_t *targets,
                     uint64_t so, uint64_t d, uint64_t m, uint64_t n, uint64_t ss, uint64_t ds, int wgs)
 {
-    if (nt)
-        hipLaunchKernelGGL((k_rma_pattern<SCOPE, IS_PUT, true>), dim3(grid), dim3(wg), 0, s, c, targets, so, d, m, n, ss,
-                           ds, wgs);
-    else
-        hipLaunchKernelGGL((k_rma_pattern<SCOPE, IS_PUT, false>), dim3(grid), dim3(wg), 0, s, c, targets, so, d, m, n,
-                           ss, ds, wgs);
+    const bool nt = (flags & SHMEMX_LAUNCH_NONTEMPORAL) != 0, deep = (flags & SHMEMX_LAUNCH_DEEP) != 0;
+#define VSHMEM_PAT_K(NT, U)                                                                                      \
+    hipLaunchKernelGGL((k_rma_pattern<SCOPE, IS_PUT, NT, U>), dim3(grid), dim3(wg), 0, s, c, targets, so, d, m, n, ss, \
+                       ds, wgs)
+    if (nt && deep) VSHMEM_PAT_K(true, 8);
+    else if (nt) VSHMEM_PAT_K(true, 4);
+    else if (deep) VSHMEM_PAT_K(false, 8);
+    else VSHMEM_PAT_K(false, 4);
+#undef VSHMEM_PAT_K
 }
 
 // ---------------------------------------------------------------- fill
@@ -151,15 +153,14 @@ int shmemx_rma_pattern(int op, int scope, const int32_t *targets, uint64_t src_o
     }
     if (nmsg == 0 || msg_bytes == 0) return SHMEMX_OK;
     const int grid = L.wgs_per_pe * s.npes;
-    const bool nt = (L.flags & SHMEMX_LAUNCH_NONTEMPORAL) != 0;
     hipStream_t hs = (hipStream_t)stream;
     shmemx_dctx_pub_t c = pub();
 #define VSHMEM_PAT(SC)                                                                                        \
     if (op == SHMEMX_OP_PUT)                                                                                  \
-        launch_pattern<SC, true>(nt, grid, L.wg_size, hs, c, targets, src_off, dst_off, msg_bytes, nmsg, src_step, \
+        launch_pattern<SC, true>(L.flags, grid, L.wg_size, hs, c, targets, src_off, dst_off, msg_bytes, nmsg, src_step, \
                                  dst_step, L.wgs_per_pe);                                                     \
     else                                                                                                      \
-        launch_pattern<SC, false>(nt, grid, L.wg_size, hs, c, targets, src_off, dst_off, msg_bytes, nmsg, src_step, \
+        launch_pattern<SC, false>(L.flags, grid, L.wg_size, hs, c, targets, src_off, dst_off, msg_bytes, nmsg, src_step, \
                                   dst_step, L.wgs_per_pe);
     switch (scope) {
     case SHMEMX_SCOPE_THREAD: VSHMEM_PAT(SHMEMX_SCOPE_THREAD) break;

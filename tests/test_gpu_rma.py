@@ -230,3 +230,25 @@ def test_device_input_generators_match_workload():
     assert np.array_equal(buf[:2 * n].cpu().numpy().view(np.uint16),
                           W.f32_to_bf16_bits(W.uniform_f32(W.splitmix64(44, 0, n))))
     torch_mod.cuda.synchronize()
+
+
+def test_autotune_table_drives_plans_and_stays_exact(tmp_path):
+    wl = W.small_workload(n_rma=300, epoch_ops=100, n_amo=2000)
+    with heap(wl.npes, 8 << 20) as v:
+        t = __import__("torch")
+        scratch = v.offset(v.malloc(4 << 20)) + (2 << 20)      # beyond the workload's 1 MiB window
+        tune = v.autotune(scratch, 2 << 20, 64, 256 << 10, msgs=64, reps=2)
+        assert tune.wg_size in (64, 128, 256, 512, 1024)
+        for c in range(6, 19):
+            assert tune.scope[c] in (v.SCOPE_THREAD, v.SCOPE_WAVE, v.SCOPE_WG)
+        path = str(tmp_path / "tune.json")
+        v.tune_save(tune, path)
+        tune2 = v.tune_load(path)
+        assert list(tune2.scope) == list(tune.scope) and tune2.wg_size == tune.wg_size
+        res = t.zeros(wl.n_amo, dtype=t.int64, device="cuda")
+        plan = v.Plan(wl.descs, tune2)
+        upload(wl.init)
+        plan.launch_fused(results=res)
+        got = download(wl.heap_bytes)
+        _check_small(wl, got, res.cpu().numpy().view(np.uint64).copy())
+        plan.destroy()
