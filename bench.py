@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="instead of the step: open-loop Poisson serving on 128 PEs x 512 MiB, 64 GiB budget")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--summarize-profiles", default="", metavar="DIR",
+                    help="no GPU work: write profiles/ summaries from rocprofv3 CSV output under DIR")
     return ap.parse_args()
 
 
@@ -260,31 +262,113 @@ def percentile(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
 
 
-def source_digest() -> str:
+# Sources each timed kernel is compiled from: a change to any of them makes
+# the committed counter figures stale.
+KERNEL_SOURCES = {
+    "k_rma_pattern": ["paper_2607_08006_amd/csrc/rma.hip"],
+    "k_alltoall": ["paper_2607_08006_amd/csrc/coll.hip"],
+}
+COMMON_SOURCES = ["include/vshmem.h", "include/vshmem_device.hpp", "paper_2607_08006_amd/csrc/runtime.hpp",
+                  "paper_2607_08006_amd/csrc/runtime.cpp"]
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def kernel_digest(kernel: str) -> str:
+    files = KERNEL_SOURCES.get(kernel.split("<")[0])
+    if files is None:
+        return ""
     h = hashlib.sha256()
-    for d in ("paper_2607_08006_amd/csrc", "include"):
-        for fn in sorted(os.listdir(os.path.join(ROOT, d))):
-            with open(os.path.join(ROOT, d, fn), "rb") as f:
-                h.update(fn.encode())
-                h.update(f.read())
+    for fn in files + COMMON_SOURCES:
+        with open(os.path.join(ROOT, fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def pmc_traffic(kernel: str, launches_bytes: int):
-    """HBM traffic of the dominant kernel from the committed counter summary,
-    or None when there is none or the sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when there is none or its sources changed since."""
+    path = os.path.join(PROFILE_DIR, "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
-            d = json.load(f)
-        ent = d.get("kernels", {}).get(kernel)
-        if not ent or d.get("source_digest") != source_digest():
+            ent = json.load(f).get("kernels", {}).get(kernel)
+        if not ent or not ent.get("source_digest") or ent["source_digest"] != kernel_digest(kernel):
             return None
         return int(ent["fetch_bytes"] + ent["write_bytes"])
-    except Exception:
+    except (OSError, ValueError, KeyError, TypeError):
         return None
+
+
+def _csv_rows(pattern):
+    import csv
+    import glob
+    out = []
+    for fn in glob.glob(pattern, recursive=True):
+        with open(fn) as fh:
+            out += list(csv.DictReader(fh))
+    return out
+
+
+def _short_kernel(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(")[0].replace(", ", ",")
+
+
+def summarize_profiles(prof_dir: str, probe_mib: int) -> None:
+    """Turn rocprofv3 CSV output into the committed summaries: a kernel table
+    from `<prof_dir>/trace` and per-launch HBM bytes from the FETCH_SIZE and
+    WRITE_SIZE passes in `<prof_dir>/pmc_<counter>`, each counter scaled by
+    what it reads for the plain copy probe of probe_mib MiB in, probe_mib out."""
+    trace_cmd = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o bench --output-format csv "
+                 "-- python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline")
+    pmc_cmd = ("rocprofv3 --pmc {ctr} -d gpurun_out/prof/pmc_{ctr} -o pmc --output-format csv -- python3 bench.py "
+               "--rows put_wg_16MiB_ring,get_wg_16MiB_perm,alltoall_1MiB_fp32 --steps 2 --warmup 1 "
+               f"--no-cpu-baseline --probe-copy-mib {probe_mib}")
+    stats = _csv_rows(os.path.join(prof_dir, "trace", "**", "*kernel_stats.csv"))
+    if stats:
+        stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        lines = ["# Kernel statistics: bench.py step, 64 virtual PEs x 1 GiB", "",
+                 "Command (from /tmp with TMPDIR=/tmp, then in the repository root):", "",
+                 f"`{trace_cmd}`", "",
+                 "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+        for r in stats[:40]:
+            lines.append("| `%s` | %s | %.3f | %.2f | %.2f | %.2f | %.2f |" % (
+                _short_kernel(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                float(r["Percentage"])))
+        with open(os.path.join(PROFILE_DIR, "bench_step_64pe_kernel_stats.md"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+    per = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        for r in _csv_rows(os.path.join(prof_dir, f"pmc_{ctr}", "**", "*counter_collection.csv")):
+            if r["Counter_Name"] == ctr:
+                per.setdefault((ctr, _short_kernel(r["Kernel_Name"])), []).append(float(r["Counter_Value"]))
+    avg = {k: sum(v) / len(v) for k, v in per.items()}
+    probe = probe_mib * MiB
+    f_scale = probe / (avg[("FETCH_SIZE", "k_probe_copy")] * 1024)
+    w_scale = probe / (avg[("WRITE_SIZE", "k_probe_copy")] * 1024)
+    kernels = {}
+    for (ctr, k), kib in sorted(avg.items()):
+        if ctr != "FETCH_SIZE" or k.split("<")[0] not in KERNEL_SOURCES or ("WRITE_SIZE", k) not in avg:
+            continue
+        kernels[k] = {"fetch_kib_per_launch": round(kib, 1),
+                      "write_kib_per_launch": round(avg[("WRITE_SIZE", k)], 1),
+                      "fetch_bytes": int(kib * 1024 * f_scale), "write_bytes": int(avg[("WRITE_SIZE", k)] * 1024 * w_scale),
+                      "launches": len(per[(ctr, k)]), "source_digest": kernel_digest(k)}
+    out = {"probe": {"bytes_read": probe, "bytes_written": probe,
+                     "fetch_kib": round(avg[("FETCH_SIZE", "k_probe_copy")], 1),
+                     "write_kib": round(avg[("WRITE_SIZE", "k_probe_copy")], 1),
+                     "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)},
+           "kernels": kernels,
+           "commands": [pmc_cmd.format(ctr=c) for c in ("FETCH_SIZE", "WRITE_SIZE")]}
+    with open(os.path.join(PROFILE_DIR, "pmc_traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(seconds: float):
@@ -392,7 +476,9 @@ def run_sweep(v, torch, args):
 
 def run_serve(v, torch, args):
     """Open-loop serving: saturated burst first, then Poisson arrivals at 50%
-    and 80% of that byte rate, on 128 PEs x 512 MiB with a 64 GiB budget."""
+    and 80% of the persistent kernel's saturated byte rate, on 128 PEs x
+    512 MiB with a 64 GiB budget; every trace runs on the persistent progress
+    kernel and on the per-op form (one launch per request)."""
     npes, heap = 128, 512 * MiB
     v.init(npes, heap)
     src = v.offset(v.malloc(128 * MiB))
@@ -404,9 +490,13 @@ def run_serve(v, torch, args):
     n = args.serve_requests
     budget = 64 << 30
 
-    def once(reqs):
+    def once(reqs, per_op=False):
         v.heap_view()[:, region + 288 * MiB:region + 384 * MiB].zero_()
         torch.cuda.synchronize()
+        if per_op:
+            dst, lat, comps, stats = v.serve_run_per_op(reqs, 8, region, 384 * MiB, budget, chunk_bytes=256 << 10)
+            torch.cuda.synchronize()
+            return lat, comps, stats
         v.progress_start(nwg=0, wg_size=256, ring_slots=4096, chunk_bytes=256 << 10, stream=side)
         try:
             dst, lat, comps, stats = v.serve_run(reqs, 8, region, 384 * MiB, budget)
@@ -415,34 +505,42 @@ def run_serve(v, torch, args):
             side.synchronize()
         return lat, comps, stats
 
+    def summary(reqs, lat, stats, warm=0):
+        pay = sum(r.nbytes for r in reqs)
+        l = lat[warm:] / 1e3
+        return {"GB_s": round(pay / stats.wall_s / 1e9, 2), "req_s": round(len(reqs) / stats.wall_s, 1),
+                "p50_us": round(percentile(l, 50), 1), "p99_us": round(percentile(l, 99), 1),
+                "admission_waits": int(stats.admission_waits), "max_reserved_bytes": int(stats.max_reserved_bytes)}
+
     burst = serve_trace(v, npes, n, 1e12, 128 * MiB, W.SEED_SERVE)
     payload = sum(r.nbytes for r in burst)
     lat, comps, stats = once(burst)
     b_sat = payload / stats.wall_s
     mean_size = payload / n
     out = {"mode": "serve", "npes": npes, "heap_bytes_per_pe": heap, "budget_bytes": budget, "requests": n,
-           "saturated": {"GB_s": round(b_sat / 1e9, 2), "req_s": round(n / stats.wall_s, 1),
-                         "p50_us": round(percentile(lat / 1e3, 50), 1), "p99_us": round(percentile(lat / 1e3, 99), 1),
-                         "max_reserved_bytes": int(stats.max_reserved_bytes)}}
+           "persistent": {"saturated": summary(burst, lat, stats)}, "per_op": {}}
+    lat, comps, stats = once(burst, per_op=True)
+    out["per_op"]["saturated"] = summary(burst, lat, stats)
+    log(json.dumps({"saturated": out["persistent"]["saturated"], "per_op": out["per_op"]["saturated"]}))
     warm = n // 20
     for rho in (0.5, 0.8):
         lam = rho * b_sat / mean_size
         reqs = serve_trace(v, npes, n, lam, 128 * MiB, W.SEED_SERVE)
-        lat, comps, stats = once(reqs)
-        l = lat[warm:] / 1e3
-        out[f"rho_{rho}"] = {"offered_GB_s": round(rho * b_sat / 1e9, 2), "GB_s": round(payload / stats.wall_s / 1e9, 2),
-                             "p50_us": round(percentile(l, 50), 1), "p99_us": round(percentile(l, 99), 1),
-                             "admission_waits": int(stats.admission_waits),
-                             "max_reserved_bytes": int(stats.max_reserved_bytes)}
-        log(json.dumps(out[f"rho_{rho}"]))
+        for form in ("persistent", "per_op"):
+            lat, comps, stats = once(reqs, per_op=form == "per_op")
+            out[form][f"rho_{rho}"] = dict(offered_GB_s=round(rho * b_sat / 1e9, 2), **summary(reqs, lat, stats, warm))
+            log(json.dumps({form: {f"rho_{rho}": out[form][f"rho_{rho}"]}}))
     v.finalize()
     return out
 
 
 def main():
     args = parse()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.probe_copy_mib or 1024)
+        return
     if args.gpus != 1:
-        msg = ("this build runs on one GPU: virtual PEs are slices of one device's heap; "
+        msg = ("virtual PEs are slices of one device's symmetric heap, so the benchmark runs on one GPU; "
                "--gpus must be 1")
         print(msg, file=sys.stderr)
         sys.exit(2)

@@ -518,6 +518,26 @@ int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t
                      uint64_t region_bytes, uint64_t budget_bytes, uint64_t *dst_off_out,
                      uint64_t *latency_ns, shmemx_completion_t *completions, shmemx_serve_stats_t *stats);
 
+/* The per-op serving form, for comparison on the same trace: the same
+ * producers, admission, destinations and latency accounting as
+ * shmemx_serve_run, but each request is one kernel launch
+ * (shmemx_launch_request with chunk_bytes / wg_size) on a stream of its
+ * producer lane's own, complete when an event recorded after it is.  The
+ * progress kernel must not be running (SHMEMX_ERR_STATE).  completions[i]
+ * carries only ticket = i (status 0, no hash, no device stamps).  A request's
+ * destination is reused only after it completed, so the final contents of a
+ * destination byte are those of the last request, by completion time
+ * (arrival_s + latency), whose range covers it. */
+int shmemx_serve_run_per_op(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
+                            uint64_t region_bytes, uint64_t budget_bytes, uint64_t chunk_bytes, int wg_size,
+                            uint64_t *dst_off_out, uint64_t *latency_ns, shmemx_completion_t *completions,
+                            shmemx_serve_stats_t *stats);
+
+/* One serving request (PUT, GET, or AMO_FETCH_ADD over nbytes/8 counters with
+ * results to the issuer's dst) executed by a launch of its own: work-group
+ * b moves bytes [b*chunk_bytes, (b+1)*chunk_bytes).  Asynchronous on stream. */
+int shmemx_launch_request(const shmemx_desc_t *desc, uint64_t chunk_bytes, int wg_size, void *stream);
+
 /* ------------------------------------------------------------ utilities */
 /* Fill device memory with bytes [word_offset*8, ...) of the SplitMix64
  * stream `seed` (little-endian words): the seeded synthetic payload. */

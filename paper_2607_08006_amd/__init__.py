@@ -404,5 +404,24 @@ def serve_run(reqs: Sequence[Request], lanes: int, region_off: int, region_bytes
     return dst, lat, comps, stats
 
 
+def serve_run_per_op(reqs: Sequence[Request], lanes: int, region_off: int, region_bytes: int, budget_bytes: int,
+                     chunk_bytes: int = 256 << 10, wg_size: int = 256):
+    """The same trace and admission as serve_run, one kernel launch per request."""
+    n = len(reqs)
+    arr = (Request * n)(*reqs)
+    dst = np.zeros(n, dtype=np.uint64)
+    lat = np.zeros(n, dtype=np.uint64)
+    comps = (Completion * n)()
+    stats = ServeStats()
+    _check(lib.shmemx_serve_run_per_op(arr, n, lanes, region_off, region_bytes, budget_bytes, chunk_bytes, wg_size,
+                                       dst.ctypes.data, lat.ctypes.data, comps, C.byref(stats)),
+           "shmemx_serve_run_per_op")
+    return dst, lat, comps, stats
+
+
+def launch_request(desc: Desc, chunk_bytes: int = 256 << 10, wg_size: int = 256, stream=None) -> None:
+    _check(lib.shmemx_launch_request(C.byref(desc), chunk_bytes, wg_size, _stream(stream)), "shmemx_launch_request")
+
+
 def version() -> str:
     return lib.shmemx_version().decode()

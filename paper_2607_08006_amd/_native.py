@@ -114,6 +114,9 @@ SIGNATURES = {
     "shmemx_progress_poll": (i32, [u64, P(Completion)]),
     "shmemx_progress_stop": (i32, [i32]),
     "shmemx_serve_run": (i32, [P(Request), sz, i32, u64, u64, u64, vp, vp, P(Completion), P(ServeStats)]),
+    "shmemx_serve_run_per_op": (i32, [P(Request), sz, i32, u64, u64, u64, u64, i32, vp, vp, P(Completion),
+                                       P(ServeStats)]),
+    "shmemx_launch_request": (i32, [P(Desc), u64, i32, vp]),
     "shmemx_fill_random": (i32, [vp, u64, u64, u64, vp]),
     "shmemx_fill_typed": (i32, [vp, u64, i32, u64, u64, vp]),
     "shmemx_probe_copy": (i32, [vp, vp, u64, i32, i32, vp]),

@@ -351,6 +351,40 @@ __global__ void __launch_bounds__(1024) k_progress(ProgArgs a)
     worker(a);
 }
 
+// One request executed by a launch of its own (the per-op serving form):
+// work-group b handles bytes [b*chunk, (b+1)*chunk) of the request.
+__global__ void __launch_bounds__(1024) k_request(shmemx_dctx_pub_t c, shmemx_desc_t d, uint64_t chunk)
+{
+    const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+    const uint64_t hi = min(d.nbytes, lo + chunk);
+    if (lo < hi) {
+        if (d.op == SHMEMX_OP_AMO_FETCH_ADD) {
+            uint64_t *ctr = (uint64_t *)(pe_base(c, d.target_pe) + d.src);
+            uint64_t *res = (uint64_t *)(pe_base(c, d.issuer_pe) + d.dst);
+            for (uint64_t k = lo / 8 + threadIdx.x; k < hi / 8; k += blockDim.x)
+                res[k] = __hip_atomic_fetch_add(ctr + k, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const bool get = d.op == SHMEMX_OP_GET;
+            const int spe = get ? d.target_pe : d.issuer_pe;
+            const int dpe = get ? d.issuer_pe : d.target_pe;
+            vshmem_detail::copy_bytes<8, true>(pe_base(c, dpe) + d.dst + lo, pe_base(c, spe) + d.src + lo, hi - lo,
+                                               threadIdx.x, blockDim.x);
+        }
+    }
+    vshmem_detail::release_agent();
+}
+
+bool valid_request_host(const shmemx_desc_t &d)
+{
+    const State &s = st();
+    if (d.issuer_pe < 0 || d.issuer_pe >= s.npes || d.target_pe < 0 || d.target_pe >= s.npes) return false;
+    if (d.op == SHMEMX_OP_PUT || d.op == SHMEMX_OP_GET) return in_user_heap(d.src, d.nbytes) && in_user_heap(d.dst, d.nbytes);
+    if (d.op == SHMEMX_OP_AMO_FETCH_ADD)
+        return (d.nbytes & 7) == 0 && (d.src & 7) == 0 && (d.dst & 7) == 0 && in_user_heap(d.src, d.nbytes) &&
+               in_user_heap(d.dst, d.nbytes);
+    return false;
+}
+
 // ------------------------------------------------------------------ host
 struct Progress {
     bool running = false;
@@ -409,10 +443,6 @@ T *dev_view(T *host)
 }
 
 }  // namespace
-
-extern "C" {
-
-}  // extern "C"
 
 namespace vshmem {
 bool progress_running() { return g_prog.running; }
@@ -499,6 +529,18 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
         return SHMEMX_ERR_HIP;
     }
     p.running = true;
+    return SHMEMX_OK;
+}
+
+int shmemx_launch_request(const shmemx_desc_t *desc, uint64_t chunk_bytes, int wg_size, void *stream)
+{
+    if (int rc = check_ready()) return rc;
+    if (!desc || !valid_request_host(*desc) || chunk_bytes == 0 || (chunk_bytes & 15) || !valid_wg_size(wg_size))
+        return SHMEMX_ERR_ARG;
+    const uint64_t nb = desc->nbytes ? (desc->nbytes + chunk_bytes - 1) / chunk_bytes : 1;
+    if (nb > (1u << 30)) return SHMEMX_ERR_ARG;
+    hipLaunchKernelGGL(k_request, dim3((unsigned)nb), dim3(wg_size), 0, (hipStream_t)stream, pub(), *desc, chunk_bytes);
+    VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
 }
 

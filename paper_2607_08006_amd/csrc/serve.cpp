@@ -36,14 +36,95 @@ struct Slot {
 
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-}  // namespace
+// How admitted requests reach the device and how their completion is seen.
+struct Backend {
+    virtual ~Backend() = default;
+    // Issue request `index` from producer `lane`; on success *ticket names it.
+    virtual int submit(const shmemx_desc_t &d, size_t index, int lane, uint64_t *ticket) = 0;
+    // 1 and *out filled when finished, 0 when not yet, < 0 on error.
+    virtual int poll(uint64_t ticket, shmemx_completion_t *out) = 0;
+};
 
-extern "C" int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
-                                uint64_t region_bytes, uint64_t budget_bytes, uint64_t *dst_off_out, uint64_t *latency_ns,
-                                shmemx_completion_t *completions, shmemx_serve_stats_t *stats)
+// The persistent progress kernel: requests go through its host ring.
+struct ProgressBackend final : Backend {
+    int submit(const shmemx_desc_t &d, size_t, int, uint64_t *ticket) override
+    {
+        int rc;
+        const Clock::time_point t0 = Clock::now();
+        while ((rc = shmemx_progress_submit(&d, ticket)) == SHMEMX_ERR_BUSY) {
+            if (Clock::now() - t0 > std::chrono::seconds(30)) break;
+            std::this_thread::yield();
+        }
+        return rc;
+    }
+    int poll(uint64_t ticket, shmemx_completion_t *out) override { return shmemx_progress_poll(ticket, out); }
+};
+
+// One kernel launch per request on the producer lane's own stream; an event
+// recorded after the launch marks completion.  Events come from a pool that
+// grows to the peak number of requests in flight.
+struct PerOpBackend final : Backend {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> by_request;
+    std::vector<hipEvent_t> pool, all;
+    std::mutex mu;
+    uint64_t chunk;
+    int wg;
+
+    PerOpBackend(size_t n, uint64_t chunk_bytes, int wg_size) : by_request(n, nullptr), chunk(chunk_bytes), wg(wg_size) {}
+    ~PerOpBackend() override
+    {
+        for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
+        for (hipEvent_t e : all) (void)hipEventDestroy(e);
+        for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+    }
+    int init(int lanes)
+    {
+        for (int l = 0; l < lanes; ++l) {
+            hipStream_t s = nullptr;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SHMEMX_ERR_HIP;
+            streams.push_back(s);
+        }
+        return SHMEMX_OK;
+    }
+    int submit(const shmemx_desc_t &d, size_t index, int lane, uint64_t *ticket) override
+    {
+        hipEvent_t e = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (!pool.empty()) {
+                e = pool.back();
+                pool.pop_back();
+            } else {
+                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SHMEMX_ERR_HIP;
+                all.push_back(e);
+            }
+        }
+        if (int rc = shmemx_launch_request(&d, chunk, wg, streams[lane])) return rc;
+        if (hipEventRecord(e, streams[lane]) != hipSuccess) return SHMEMX_ERR_HIP;
+        by_request[index] = e;
+        *ticket = index;
+        return SHMEMX_OK;
+    }
+    int poll(uint64_t ticket, shmemx_completion_t *out) override
+    {
+        const hipError_t q = hipEventQuery(by_request[ticket]);
+        if (q == hipErrorNotReady) return 0;
+        if (q != hipSuccess) return SHMEMX_ERR_HIP;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            pool.push_back(by_request[ticket]);
+        }
+        *out = shmemx_completion_t{};
+        out->ticket = ticket;
+        return 1;
+    }
+};
+
+int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
+                 uint64_t region_bytes, uint64_t budget_bytes, uint64_t *dst_off_out, uint64_t *latency_ns,
+                 shmemx_completion_t *completions, shmemx_serve_stats_t *stats)
 {
-    if (int rc = check_ready()) return rc;
-    if (!progress_running()) return SHMEMX_ERR_STATE;
     const State &s = st();
     if ((!reqs && n) || lanes < 1 || lanes > 64 || !in_user_heap(region_off, region_bytes) || region_bytes < 4096 ||
         budget_bytes == 0)
@@ -144,12 +225,7 @@ extern "C" int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lane
                 d.dst = sl.dst;
             }
             uint64_t t = 0;
-            int rc;
-            const Clock::time_point t0 = Clock::now();
-            while ((rc = shmemx_progress_submit(&d, &t)) == SHMEMX_ERR_BUSY) {
-                if (Clock::now() - t0 > std::chrono::seconds(30)) break;
-                std::this_thread::yield();
-            }
+            const int rc = be.submit(d, i, lane, &t);
             if (rc != SHMEMX_OK) {
                 failed.store(rc);
                 return;
@@ -170,7 +246,12 @@ extern "C" int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lane
                 const int stt = sl.state.load(std::memory_order_acquire);
                 if (stt != 1) continue;
                 shmemx_completion_t c;
-                if (shmemx_progress_poll(sl.ticket, &c) == 1) {
+                const int pr = be.poll(sl.ticket, &c);
+                if (pr < 0) {
+                    failed.store(pr);
+                    break;
+                }
+                if (pr == 1) {
                     const Clock::time_point now = Clock::now();
                     if (latency_ns) latency_ns[i] = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - sl.arrival).count();
                     if (completions) completions[i] = c;
@@ -212,4 +293,32 @@ extern "C" int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lane
         stats->admission_waits = adm.waits;
     }
     return failed.load();
+}
+
+}  // namespace
+
+extern "C" int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
+                                uint64_t region_bytes, uint64_t budget_bytes, uint64_t *dst_off_out, uint64_t *latency_ns,
+                                shmemx_completion_t *completions, shmemx_serve_stats_t *stats)
+{
+    if (int rc = check_ready()) return rc;
+    if (!progress_running()) return SHMEMX_ERR_STATE;
+    ProgressBackend be;
+    return serve_common(be, reqs, n, lanes, region_off, region_bytes, budget_bytes, dst_off_out, latency_ns,
+                        completions, stats);
+}
+
+extern "C" int shmemx_serve_run_per_op(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
+                                       uint64_t region_bytes, uint64_t budget_bytes, uint64_t chunk_bytes, int wg_size,
+                                       uint64_t *dst_off_out, uint64_t *latency_ns, shmemx_completion_t *completions,
+                                       shmemx_serve_stats_t *stats)
+{
+    if (int rc = check_ready()) return rc;
+    if (progress_running()) return SHMEMX_ERR_STATE;
+    if (lanes < 1 || lanes > 64 || chunk_bytes == 0 || (chunk_bytes & 15) || !valid_wg_size(wg_size))
+        return SHMEMX_ERR_ARG;
+    PerOpBackend be(n, chunk_bytes, wg_size);
+    if (int rc = be.init(lanes)) return rc;
+    return serve_common(be, reqs, n, lanes, region_off, region_bytes, budget_bytes, dst_off_out, latency_ns,
+                        completions, stats);
 }

@@ -182,3 +182,85 @@ def test_progress_rejects_bad_config_and_busy_ring():
         v.progress_stop(10000)
         side.synchronize()
         assert v.device_errors() & v.DEVERR_BAD_DESC
+
+
+def test_launch_request_matches_oracle():
+    npes = 8
+    with heap(npes, 8 << 20) as v:
+        t = torch()
+        region = 6 << 20
+        init = W.heap_fill(0xFACE, npes, region)
+        init[:, 5 << 20:] = 0
+        upload(init)
+        reqs = [
+            (W.OP_PUT, 0, 3, 0, 2 << 20, 100),
+            (W.OP_GET, 5, 1, 4096, (2 << 20) + 4096, 70_000),          # 5 chunks of 16 KiB, ragged tail
+            (W.OP_PUT, 7, 7, 8192, 3 << 20, 1 << 20),
+            (W.OP_AMO_FETCH_ADD, 2, 6, 5 << 20, 4 << 20, 4096),
+            (W.OP_PUT, 1, 2, 13, (2 << 20) + 77, 999),                  # unaligned
+            (W.OP_GET, 4, 4, 0, (4 << 20) + 8192, 0),                   # empty
+        ]
+        for r in reqs:
+            v.launch_request(_desc(*r, value=1 if r[0] == W.OP_AMO_FETCH_ADD else 0), chunk_bytes=16 << 10, wg_size=128)
+        t.cuda.synchronize()
+        got = download(region)
+        ref = init.copy()
+        recs = []
+        for op, i, tg, s, d, n in reqs:
+            if op == W.OP_AMO_FETCH_ADD:
+                recs += [(op, 0, 0, i, tg, W.NO_RESULT, s + 8 * w, 0, 8, 1, 0) for w in range(n // 8)]
+            elif n:
+                recs.append((op, 0, 0, i, tg, W.NO_RESULT, s, d, n, 0, 0))
+        oracle.run_program(ref, W.descs(recs))
+        op, i, tg, s, d, n = reqs[3]
+        ref[i, d:d + n] = 0                                   # fetched values of fresh counters
+        assert np.array_equal(got, ref)
+        with pytest.raises(v.VshmemError):
+            v.launch_request(_desc(W.OP_PUT, 0, npes, 0, 0, 64))          # target PE out of range
+        with pytest.raises(v.VshmemError):
+            v.launch_request(_desc(W.OP_PUT, 0, 1, 0, 0, 64), chunk_bytes=24)
+        assert_no_device_errors()
+
+
+def test_serving_per_op_final_state_and_budget():
+    npes, n = 16, 300
+    src_bytes = 2 << 20
+    with heap(npes, 40 << 20) as v:
+        t = torch()
+        init = W.heap_fill(0xD00D, npes, src_bytes)
+        upload(init)
+        region_off, region_bytes = 4 << 20, 32 << 20
+        reqs = _trace(npes, n, rate=2e5, src_bytes=src_bytes, seed=W.SEED_SERVE + 1)
+        h = v.heap_view()
+        h[:, region_off:region_off + region_bytes].zero_()
+        t.cuda.synchronize()
+        budget = 3 << 20
+        dst, lat, comps, stats = v.serve_run_per_op(reqs, 8, region_off, region_bytes, budget,
+                                                    chunk_bytes=64 << 10, wg_size=256)
+        t.cuda.synchronize()
+        assert stats.max_reserved_bytes <= budget
+        assert sorted(c.ticket for c in comps) == list(range(n))
+        assert (lat > 0).all()
+        got = download(region_off + region_bytes)
+        # replay destinations in completion order: the last writer of each byte wins
+        want = np.zeros_like(got)
+        written = np.zeros(got.shape, dtype=bool)
+        done_at = np.array([r.arrival_s * 1e9 for r in reqs]) + lat.astype(np.float64)
+        for k in np.argsort(done_at, kind="stable"):
+            r, d = reqs[k], int(dst[k])
+            if r.op == W.OP_AMO_FETCH_ADD:
+                payload = np.zeros(r.nbytes, dtype=np.uint8)
+                pe = r.issuer_pe
+            else:
+                spe = r.issuer_pe if r.op == W.OP_PUT else r.target_pe
+                payload = init[spe, r.src_off:r.src_off + r.nbytes]
+                pe = r.target_pe if r.op == W.OP_PUT else r.issuer_pe
+            want[pe, d:d + r.nbytes] = payload
+            written[pe, d:d + r.nbytes] = True
+        assert np.array_equal(got[written], want[written])
+        # fetch_add counters are bump allocated: every one was incremented exactly once
+        n_ctr = sum(r.nbytes // 8 for r in reqs if r.op == W.OP_AMO_FETCH_ADD)
+        ctr_base = region_off + ((region_bytes // 4 * 3) & ~255)
+        ctr = got[:, ctr_base:].copy().view("<u8")
+        assert int(ctr.sum()) == n_ctr and int(ctr.max()) <= 1
+        assert_no_device_errors()
