@@ -251,6 +251,12 @@ void shmem_team_destroy(shmem_team_t team);
 /* Error reporting. */
 const char *shmemx_strerror(int code);
 int shmemx_last_error(void);
+/* Detail of the most recent SHMEMX_ERR_HIP: returns the hipError_t code of
+ * the HIP runtime call that failed (0 when the library itself refused, e.g.
+ * a kernel that cannot be resident) and, when buf is not NULL, writes a
+ * description into buf (truncated to len): "<name> (<code>) at
+ * <source>:<line>: <call>" for a failed call. */
+int shmemx_last_hip_error(char *buf, size_t len);
 /* Read and clear the device error word (SHMEMX_DEVERR_* bits); waits for
  * the device.  Returns the bits, or a negative code if not initialised. */
 int shmemx_device_errors(void);
@@ -370,6 +376,10 @@ int shmemx_barrier_launch(shmem_team_t team, int iters, uint64_t tokens_off, uin
  *              SUM or MAX with max(a, b) = (b > a) ? b : a.
  * Every member's work-groups must be co-resident: the launch fails with
  * SHMEMX_ERR_ARG if team size * wgs_per_pe work-groups cannot be.
+ * launch may be NULL; zero fields take the defaults: wgs_per_pe about one
+ * work-group per CU in total, work-groups of 1024 threads (256 for the
+ * reductions, which accept at most 256), chunk 256 KiB (alltoall 1 MiB,
+ * reductions 16 KiB), nontemporal copies for alltoall and the reductions.
  */
 #define SHMEMX_DT_INT64 0
 #define SHMEMX_DT_FP32 1
@@ -409,7 +419,10 @@ typedef struct shmemx_plan shmemx_plan_t;
 void shmemx_tune_default(shmemx_tune_t *tune);
 /* Build a plan from HOST descriptors (copied).  tune may be NULL.
  * Validates every descriptor (ranges inside the user heap, PEs, op codes,
- * equal barrier counts) and returns SHMEMX_ERR_ARG with no plan otherwise. */
+ * equal barrier counts) and returns SHMEMX_ERR_ARG with no plan otherwise.
+ * Returns SHMEMX_ERR_UNSUPPORTED when no work-group of tune->wg_size threads
+ * of the fused kernel can be resident on a CU (shmemx_last_hip_error says
+ * why). */
 int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t *tune, shmemx_plan_t **plan);
 /* One fused launch of the whole plan.  results: DEVICE uint64 array with
  * room for every result index used, or NULL if none. */

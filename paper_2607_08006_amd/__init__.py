@@ -20,7 +20,7 @@ lib = _native.load()
 
 OK = 0
 ERR_ARG, ERR_NOMEM, ERR_STATE, ERR_HIP, ERR_BUSY, ERR_TIMEOUT, ERR_DEVICE, ERR_UNSUPPORTED = range(-1, -9, -1)
-DEVERR_WAIT_TIMEOUT, DEVERR_BAD_DESC, DEVERR_PROGRESS_IDLE = 0x1, 0x2, 0x4
+DEVERR_WAIT_TIMEOUT, DEVERR_BAD_DESC, DEVERR_PROGRESS_IDLE, DEVERR_PROGRESS_STATE = 0x1, 0x2, 0x4, 0x8
 
 OP_NOP, OP_PUT, OP_GET, OP_PUT_SIGNAL = 0, 1, 2, 3
 OP_AMO_FETCH_ADD, OP_AMO_FETCH_XOR, OP_AMO_COMPARE_SWAP, OP_AMO_ADD, OP_AMO_XOR = 4, 5, 6, 7, 8
@@ -41,6 +41,10 @@ SLICE_ALIGN = 2 << 20
 class VshmemError(RuntimeError):
     def __init__(self, code: int, what: str):
         msg = lib.shmemx_strerror(code).decode()
+        buf = C.create_string_buffer(512)
+        lib.shmemx_last_hip_error(buf, len(buf))
+        if buf.value:
+            msg += ": " + buf.value.decode(errors="replace")
         super().__init__(f"{what}: {msg} ({code})")
         self.code = code
 

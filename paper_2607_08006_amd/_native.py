@@ -124,6 +124,7 @@ SIGNATURES = {
     "shmemx_probe_xcd": (i32, [vp, i32, vp]),
     "shmemx_probe_empty": (i32, [vp]),
     "shmemx_version": (C.c_char_p, []),
+    "shmemx_last_hip_error": (i32, [C.c_char_p, sz]),
 }
 
 _lib = None

@@ -405,10 +405,18 @@ int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t
     uint64_t widest = 1;
     for (size_t p = 0; p + 1 < phase.size(); ++p) widest = std::max<uint64_t>(widest, phase[p + 1] - phase[p]);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_fused, plan->wg, 0) != hipSuccess || per_cu <= 0) {
+    if (int rc = blocks_per_cu(k_plan_fused, plan->wg, &per_cu)) {
         delete plan;
-        set_last_error(SHMEMX_ERR_HIP);
-        return SHMEMX_ERR_HIP;
+        return rc;
+    }
+    if (per_cu <= 0) {
+        hipFuncAttributes fa{};
+        (void)hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_plan_fused));
+        set_error_detail(SHMEMX_ERR_UNSUPPORTED,
+                         "k_plan_fused: no work-group of %d threads can be resident (occupancy %d; %d registers, "
+                         "at most %d threads per block)", plan->wg, per_cu, fa.numRegs, fa.maxThreadsPerBlock);
+        delete plan;
+        return SHMEMX_ERR_UNSUPPORTED;
     }
     uint64_t cap = (uint64_t)per_cu * s.num_cus;
     if (tune.grid_wgs > 0) cap = std::min<uint64_t>(cap, (uint64_t)tune.grid_wgs);
@@ -472,11 +480,11 @@ int shmemx_plan_graph_build(shmemx_plan_t *plan, int form, uint64_t *results, vo
     hipStream_t cap;
     VSHMEM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     int rc = SHMEMX_OK;
-    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = SHMEMX_ERR_HIP;
+    if (VSHMEM_HIP_FAILED(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal))) rc = SHMEMX_ERR_HIP;
     if (!rc) rc = form == 0 ? shmemx_plan_launch_per_op(plan, results, cap) : shmemx_plan_launch_fused(plan, results, cap);
     hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(cap, &g) != hipSuccess && !rc) rc = SHMEMX_ERR_HIP;
-    if (!rc && hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0) != hipSuccess) rc = SHMEMX_ERR_HIP;
+    if (VSHMEM_HIP_FAILED(hipStreamEndCapture(cap, &g)) && !rc) rc = SHMEMX_ERR_HIP;
+    if (!rc && VSHMEM_HIP_FAILED(hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0))) rc = SHMEMX_ERR_HIP;
     plan->graph = g;
     (void)hipStreamDestroy(cap);
     (void)stream;

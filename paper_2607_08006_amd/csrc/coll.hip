@@ -32,9 +32,15 @@ __device__ __forceinline__ void enter(const Geo &g, shmem_dctx_t &ctx)
     shmemx_team_sync_units(ctx, g.team, g.wgs_per_pe);
 }
 
-// Copy one source range to `ndst` destinations that are the same offset on
-// consecutive team members (member stride in bytes = pstride): each 16-byte
-// vector is read once and written ndst times.
+// Copy one source range to the same offset on every team member (member
+// stride in bytes = pstride).  Aligned ranges go through a register tile:
+// each lane loads kMcastTile 16-byte vectors once, then the whole tile is
+// written to one member after another, starting at a member that depends on
+// the work-group so that concurrent work-groups spread over the members.
+// Long contiguous writes per member page measured about 10% faster on
+// MI355X than writing every vector to all members in turn.
+constexpr int kMcastTile = 16;
+
 template <bool NT>
 __device__ __forceinline__ void multicast(const Geo &g, const uint8_t *src, uint64_t dst_off, uint64_t len)
 {
@@ -43,11 +49,20 @@ __device__ __forceinline__ void multicast(const Geo &g, const uint8_t *src, uint
     uint8_t *d0 = pe_addr(g, 0, dst_off);
     if ((((uintptr_t)src | (uintptr_t)d0 | len) & 15) == 0) {
         const v4u *s = (const v4u *)src;
-        const uint64_t nv = len / 16;
-        for (uint64_t i = threadIdx.x; i < nv; i += blockDim.x) {
-            const v4u v = vshmem_detail::ld<NT>(s + i);
-            uint8_t *d = d0 + i * 16;
-            for (int p = 0; p < P; ++p, d += pstride) vshmem_detail::st<NT>((v4u *)d, v);
+        const uint64_t nv = len / 16, bd = blockDim.x;
+        for (uint64_t i0 = threadIdx.x; i0 < nv; i0 += kMcastTile * bd) {
+            v4u r[kMcastTile];
+#pragma unroll
+            for (int u = 0; u < kMcastTile; ++u)
+                if (i0 + u * bd < nv) r[u] = vshmem_detail::ld<true>(s + i0 + u * bd);
+            int p = (int)(blockIdx.x % (unsigned)P);
+            for (int k = 0; k < P; ++k) {
+                v4u *d = (v4u *)(d0 + (uint64_t)p * pstride);
+#pragma unroll
+                for (int u = 0; u < kMcastTile; ++u)
+                    if (i0 + u * bd < nv) vshmem_detail::st<NT>(d + i0 + u * bd, r[u]);
+                if (++p == P) p = 0;
+            }
         }
     } else {
         for (int p = 0; p < P; ++p)
@@ -314,11 +329,11 @@ template <typename K>
 int check_coresident(K kernel, int grid, int wg)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, wg, 0) != hipSuccess) return SHMEMX_ERR_HIP;
+    if (int rc = blocks_per_cu(kernel, wg, &per_cu)) return rc;
     if ((int64_t)per_cu * st().num_cus < grid) {
-        if (st().debug)
-            fprintf(stderr, "vshmem: %d work-groups of %d threads cannot be co-resident (%d per CU x %d CUs)\n", grid,
-                    wg, per_cu, st().num_cus);
+        set_error_detail(SHMEMX_ERR_ARG, "%d work-groups of %d threads cannot be co-resident (%d per CU x %d CUs)", grid,
+                         wg, per_cu, st().num_cus);
+        if (st().debug) fprintf(stderr, "vshmem: %s\n", "collective work-groups cannot be co-resident");
         return SHMEMX_ERR_ARG;
     }
     return SHMEMX_OK;
@@ -335,17 +350,13 @@ int launch_team_kernel(K kernel, Geo &g, int wg, hipStream_t s, bool auto_wgs, A
         // kernels reached higher HBM bandwidth with one wide work-group per
         // CU than with the grid filled to its occupancy limit.
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, wg, 0) != hipSuccess) return SHMEMX_ERR_HIP;
+        if (int rc = blocks_per_cu(kernel, wg, &per_cu)) return rc;
         const int64_t cap = (int64_t)per_cu * st().num_cus;
         const int64_t want = std::max<int64_t>(1, st().num_cus / g.team.size);
         g.wgs_per_pe = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap / g.team.size));
     }
     const int grid = g.wgs_per_pe * g.team.size;
-    int rc = check_coresident(kernel, grid, wg);
-    if (rc) {
-        set_last_error(rc);
-        return rc;
-    }
+    if (int rc = check_coresident(kernel, grid, wg)) return rc;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wg), 0, s, g, args...);
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
@@ -382,7 +393,7 @@ int shmemx_broadcastmem_launch(shmem_team_t team, void *dest, const void *src, s
 {
     Geo g{};
     shmemx_launch_t L;
-    int rc = make_geo(team, dest, src, n, n, launch, 256, g, L);
+    int rc = make_geo(team, dest, src, n, n, launch, 1024, g, L);
     if (!rc && (root < 0 || root >= g.team.size || overlap(g.dst_off, n, g.src_off, n))) rc = SHMEMX_ERR_ARG;
     if (rc) {
         set_last_error(rc);
@@ -404,7 +415,7 @@ int shmemx_fcollectmem_launch(shmem_team_t team, void *dest, const void *src, si
     if (int r0 = check_ready()) return r0;
     int tsize = shmem_team_n_pes(team);
     if (tsize <= 0) rc = SHMEMX_ERR_ARG;
-    if (!rc) rc = make_geo(team, dest, src, (uint64_t)n * tsize, n, launch, 256, g, L);
+    if (!rc) rc = make_geo(team, dest, src, (uint64_t)n * tsize, n, launch, 1024, g, L);
     if (!rc && overlap(g.dst_off, (uint64_t)n * tsize, g.src_off, n)) rc = SHMEMX_ERR_ARG;
     if (rc) {
         set_last_error(rc);

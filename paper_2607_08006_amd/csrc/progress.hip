@@ -429,7 +429,7 @@ void release_progress()
 template <typename T>
 int host_alloc(T **p, size_t bytes)
 {
-    if (hipHostMalloc((void **)p, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return SHMEMX_ERR_HIP;
+    if (VSHMEM_HIP_FAILED(hipHostMalloc((void **)p, bytes, hipHostMallocMapped | hipHostMallocCoherent))) return SHMEMX_ERR_HIP;
     memset(*p, 0, bytes);
     return SHMEMX_OK;
 }
@@ -438,7 +438,7 @@ template <typename T>
 T *dev_view(T *host)
 {
     void *d = nullptr;
-    if (hipHostGetDevicePointer(&d, host, 0) != hipSuccess) return nullptr;
+    if (VSHMEM_HIP_FAILED(hipHostGetDevicePointer(&d, host, 0))) return nullptr;
     return (T *)d;
 }
 
@@ -477,9 +477,9 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
         if (!rc) rc = host_alloc(&p.ring_done, slots * sizeof(uint64_t));
         if (!rc) rc = host_alloc(&p.comp, slots * sizeof(shmemx_completion_t));
         if (!rc) rc = host_alloc(&p.stop, 64);
-        if (!rc && hipMalloc((void **)&p.items, qsize * sizeof(Item)) != hipSuccess) rc = SHMEMX_ERR_HIP;
-        if (!rc && hipMalloc((void **)&p.parents, slots * sizeof(Parent)) != hipSuccess) rc = SHMEMX_ERR_HIP;
-        if (!rc && hipMalloc((void **)&p.claim, 256) != hipSuccess) rc = SHMEMX_ERR_HIP;
+        if (!rc && VSHMEM_HIP_FAILED(hipMalloc((void **)&p.items, qsize * sizeof(Item)))) rc = SHMEMX_ERR_HIP;
+        if (!rc && VSHMEM_HIP_FAILED(hipMalloc((void **)&p.parents, slots * sizeof(Parent)))) rc = SHMEMX_ERR_HIP;
+        if (!rc && VSHMEM_HIP_FAILED(hipMalloc((void **)&p.claim, 256))) rc = SHMEMX_ERR_HIP;
     }
     if (rc || !p.ring_seq || !p.ring_done || !p.comp || !p.stop || !p.items || !p.parents || !p.claim) {
         if (!rc) rc = SHMEMX_ERR_HIP;
@@ -495,9 +495,9 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     std::vector<Item> init(qsize);
     for (uint64_t i = 0; i < qsize; ++i) init[i] = Item{i, 0, 0, 0, 0, {0, 0, 0}};
     hipStream_t hs = (hipStream_t)stream;
-    if (hipMemcpyAsync(p.items, init.data(), qsize * sizeof(Item), hipMemcpyHostToDevice, hs) != hipSuccess ||
-        hipMemsetAsync(p.claim, 0, 256, hs) != hipSuccess || hipMemsetAsync(p.parents, 0, slots * sizeof(Parent), hs) != hipSuccess ||
-        hipStreamSynchronize(hs) != hipSuccess) {
+    if (VSHMEM_HIP_FAILED(hipMemcpyAsync(p.items, init.data(), qsize * sizeof(Item), hipMemcpyHostToDevice, hs)) ||
+        VSHMEM_HIP_FAILED(hipMemsetAsync(p.claim, 0, 256, hs)) || VSHMEM_HIP_FAILED(hipMemsetAsync(p.parents, 0, slots * sizeof(Parent), hs)) ||
+        VSHMEM_HIP_FAILED(hipStreamSynchronize(hs))) {
         release_progress();
         return SHMEMX_ERR_HIP;
     }
@@ -524,7 +524,7 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     p.head.store(0);
     p.stream = hs;
     hipLaunchKernelGGL(k_progress, dim3(cfg.nwg), dim3(cfg.wg_size), 0, hs, a);
-    if (hipGetLastError() != hipSuccess) {
+    if (VSHMEM_HIP_FAILED(hipGetLastError())) {
         release_progress();
         return SHMEMX_ERR_HIP;
     }

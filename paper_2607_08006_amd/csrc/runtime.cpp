@@ -1,5 +1,10 @@
 // Host runtime: symmetric heap, allocator, published device context, teams,
 // capability query and error reporting.
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+
 #include "runtime.hpp"
 
 #include <cctype>
@@ -13,7 +18,48 @@ static State g_state;
 static thread_local int g_last_error = SHMEMX_OK;
 
 State &st() { return g_state; }
-void set_last_error(int code) { g_last_error = code; }
+void clear_error_detail();
+void set_last_error(int code)
+{
+    clear_error_detail();
+    g_last_error = code;
+}
+
+namespace {
+std::mutex g_detail_mu;
+int g_hip_code = 0;
+char g_detail[384] = "";
+}  // namespace
+
+void set_hip_error(hipError_t e, const char *site)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_detail_mu);
+        g_hip_code = (int)e;
+        snprintf(g_detail, sizeof g_detail, "%s (%d) at %s", hipGetErrorName(e), (int)e, site);
+    }
+    g_last_error = SHMEMX_ERR_HIP;
+}
+
+void clear_error_detail()
+{
+    std::lock_guard<std::mutex> lk(g_detail_mu);
+    g_hip_code = 0;
+    g_detail[0] = 0;
+}
+
+void set_error_detail(int code, const char *fmt, ...)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_detail_mu);
+        g_hip_code = 0;
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(g_detail, sizeof g_detail, fmt, ap);
+        va_end(ap);
+    }
+    g_last_error = code;
+}
 
 int check_ready()
 {
@@ -188,7 +234,7 @@ static int finish_init(void *heap, size_t heap_bytes, int npes, hipStream_t stre
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         s.initialised = false;
-        set_last_error(SHMEMX_ERR_HIP);
+        set_hip_error(e, "publishing the device context");
         return SHMEMX_ERR_HIP;
     }
     return SHMEMX_OK;
@@ -239,7 +285,7 @@ void shmem_init(void)
     }
     uint64_t stride = (user + VSHMEM_SCRATCH_BYTES + kSliceAlign - 1) & ~(kSliceAlign - 1);
     void *heap = nullptr;
-    if (hipMalloc(&heap, stride * (uint64_t)npes) != hipSuccess) {
+    if (VSHMEM_HIP_FAILED(hipMalloc(&heap, stride * (uint64_t)npes))) {
         set_last_error(SHMEMX_ERR_NOMEM);
         return;
     }
@@ -298,14 +344,12 @@ void *shmem_calloc(size_t count, size_t size)
     if (!p) return nullptr;
     State &s = st();
     for (int pe = 0; pe < s.npes; ++pe) {
-        if (hipMemsetAsync((uint8_t *)p + (uint64_t)pe * s.stride, 0, count * size, nullptr) != hipSuccess) {
-            set_last_error(SHMEMX_ERR_HIP);
+        if (VSHMEM_HIP_FAILED(hipMemsetAsync((uint8_t *)p + (uint64_t)pe * s.stride, 0, count * size, nullptr))) {
             shmem_free(p);
             return nullptr;
         }
     }
-    if (hipStreamSynchronize(nullptr) != hipSuccess) {
-        set_last_error(SHMEMX_ERR_HIP);
+    if (VSHMEM_HIP_FAILED(hipStreamSynchronize(nullptr))) {
         shmem_free(p);
         return nullptr;
     }
@@ -410,9 +454,8 @@ int shmem_team_split_strided(shmem_team_t parent, int start, int stride, int siz
     // Clear the new team's barrier words in its first member's scratch.
     uint64_t *slot = (uint64_t *)(s.base + (uint64_t)t.start * s.stride + s.user_bytes +
                                   (uint64_t)t.slot * VSHMEM_SYNC_SLOT_BYTES);
-    if (hipMemset(slot, 0, VSHMEM_SYNC_SLOT_BYTES) != hipSuccess) {
+    if (VSHMEM_HIP_FAILED(hipMemset(slot, 0, VSHMEM_SYNC_SLOT_BYTES))) {
         t.live = false;
-        set_last_error(SHMEMX_ERR_HIP);
         return SHMEMX_ERR_HIP;
     }
     *new_team = idx;
@@ -484,5 +527,12 @@ int shmemx_set_wait_timeout_ns(uint64_t ns)
 }
 
 const char *shmemx_version(void) { return "vshmem 0.1 (gfx950)"; }
+
+int shmemx_last_hip_error(char *buf, size_t len)
+{
+    std::lock_guard<std::mutex> lk(g_detail_mu);
+    if (buf && len) snprintf(buf, len, "%s", g_detail);
+    return g_hip_code;
+}
 
 }  // extern "C"

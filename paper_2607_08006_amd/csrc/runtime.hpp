@@ -1,9 +1,9 @@
 // Internal host-side state shared by the library's translation units.
 #pragma once
-
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -62,6 +62,18 @@ struct State {
 
 State &st();
 void set_last_error(int code);
+// Record a failed HIP runtime call (its code and where it was made) and set
+// the last error to SHMEMX_ERR_HIP.
+void set_hip_error(hipError_t e, const char *site);
+// Set the last error to `code` with a printf-style explanation that
+// shmemx_last_hip_error() reports.
+void set_error_detail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+inline bool hip_failed(hipError_t e, const char *site)
+{
+    if (e == hipSuccess) return false;
+    set_hip_error(e, site);
+    return true;
+}
 int check_ready();
 shmemx_dctx_pub_t pub();
 int team_get(shmem_team_t t, shmemx_dteam_t *out);
@@ -71,16 +83,42 @@ uint64_t sym_offset(const void *p, uint64_t n);
 const shmemx_launch_t &launch_or_default(const shmemx_launch_t *l, shmemx_launch_t &tmp, int def_wgs,
                                          int def_wg, uint64_t def_chunk);
 bool valid_wg_size(int wg);
+// Work-groups of `wg` threads of `kernel` that can be resident on one CU.
+// The occupancy query has answered 0 for kernels that do launch at that
+// size on MI355X; a work-group no larger than the kernel's own per-block
+// limit (derived from its registers) fits on an idle CU, so count one then.
+template <typename K>
+int blocks_per_cu(K kernel, int wg, int *per_cu)
+{
+    if (hip_failed(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, wg, 0),
+                   "blocks_per_cu: hipOccupancyMaxActiveBlocksPerMultiprocessor"))
+        return SHMEMX_ERR_HIP;
+    if (*per_cu <= 0) {
+        hipFuncAttributes fa{};
+        if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kernel)) == hipSuccess && wg <= fa.maxThreadsPerBlock)
+            *per_cu = 1;
+        if (st().debug)
+            fprintf(stderr, "vshmem: occupancy query gave 0 blocks of %d threads; kernel limit %d threads, %d registers\n",
+                    wg, fa.maxThreadsPerBlock, fa.numRegs);
+    }
+    return SHMEMX_OK;
+}
+
 bool progress_running();
 void progress_release();
 
 }  // namespace vshmem
 
+#define VSHMEM_STR2(x) #x
+#define VSHMEM_STR(x) VSHMEM_STR2(x)
+// True when the call failed; the failure is recorded as by VSHMEM_HIP.
+#define VSHMEM_HIP_FAILED(call) \
+    vshmem::hip_failed((call), __FILE__ ":" VSHMEM_STR(__LINE__) ": " #call)
 #define VSHMEM_HIP(call)                                                                                  \
     do {                                                                                                  \
         hipError_t e_ = (call);                                                                           \
         if (e_ != hipSuccess) {                                                                           \
-            vshmem::set_last_error(SHMEMX_ERR_HIP);                                                       \
+            vshmem::set_hip_error(e_, __FILE__ ":" VSHMEM_STR(__LINE__) ": " #call);                      \
             return SHMEMX_ERR_HIP;                                                                        \
         }                                                                                                 \
     } while (0)

@@ -82,7 +82,7 @@ struct PerOpBackend final : Backend {
     {
         for (int l = 0; l < lanes; ++l) {
             hipStream_t s = nullptr;
-            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SHMEMX_ERR_HIP;
+            if (VSHMEM_HIP_FAILED(hipStreamCreateWithFlags(&s, hipStreamNonBlocking))) return SHMEMX_ERR_HIP;
             streams.push_back(s);
         }
         return SHMEMX_OK;
@@ -96,12 +96,12 @@ struct PerOpBackend final : Backend {
                 e = pool.back();
                 pool.pop_back();
             } else {
-                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SHMEMX_ERR_HIP;
+                if (VSHMEM_HIP_FAILED(hipEventCreateWithFlags(&e, hipEventDisableTiming))) return SHMEMX_ERR_HIP;
                 all.push_back(e);
             }
         }
         if (int rc = shmemx_launch_request(&d, chunk, wg, streams[lane])) return rc;
-        if (hipEventRecord(e, streams[lane]) != hipSuccess) return SHMEMX_ERR_HIP;
+        if (VSHMEM_HIP_FAILED(hipEventRecord(e, streams[lane]))) return SHMEMX_ERR_HIP;
         by_request[index] = e;
         *ticket = index;
         return SHMEMX_OK;
@@ -110,7 +110,10 @@ struct PerOpBackend final : Backend {
     {
         const hipError_t q = hipEventQuery(by_request[ticket]);
         if (q == hipErrorNotReady) return 0;
-        if (q != hipSuccess) return SHMEMX_ERR_HIP;
+        if (q != hipSuccess) {
+            set_hip_error(q, "serve per-op: hipEventQuery");
+            return SHMEMX_ERR_HIP;
+        }
         {
             std::lock_guard<std::mutex> lk(mu);
             pool.push_back(by_request[ticket]);

@@ -61,7 +61,7 @@ int time_candidate(const Cand &c, uint64_t off, uint64_t span, uint64_t bytes, i
         (void)hipEventRecord(e0, s);
         rc = shmemx_plan_launch_fused(plan, nullptr, s);
         (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) rc = SHMEMX_ERR_HIP;
+        if (VSHMEM_HIP_FAILED(hipEventSynchronize(e1))) rc = SHMEMX_ERR_HIP;
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (r > 0) ts.push_back(ms);   // first launch is a warm-up
@@ -90,7 +90,6 @@ int shmemx_autotune(uint64_t scratch_off, uint64_t scratch_bytes, uint64_t min_b
     hipStream_t s = (hipStream_t)stream;
     const int wgs[] = {64, 128, 256, 512, 1024};
     const uint64_t chunks[] = {0, 64ull << 10, 256ull << 10, 1ull << 20};
-    float best_wg_ms = 1e30f;
     for (uint64_t b = min_bytes; b <= max_bytes; b *= 2) {
         int cls = 0;
         while (cls + 1 < SHMEMX_TUNE_CLASSES && (2ull << cls) <= b) ++cls;
@@ -104,6 +103,7 @@ int shmemx_autotune(uint64_t scratch_off, uint64_t scratch_bytes, uint64_t min_b
                     Cand c{sc, wg, ch};
                     float ms = 0;
                     int rc = time_candidate(c, scratch_off, scratch_bytes, b, msgs, reps, s, &ms);
+                    if (rc == SHMEMX_ERR_UNSUPPORTED) continue;   // this work-group size cannot be resident
                     if (rc) return rc;
                     if (ms < best) {
                         best = ms;
@@ -117,7 +117,6 @@ int shmemx_autotune(uint64_t scratch_off, uint64_t scratch_bytes, uint64_t min_b
         // One work-group size serves the whole fused kernel: keep the one
         // that won the largest class.
         tune->wg_size = pick.wg;
-        (void)best_wg_ms;
         if (b > max_bytes / 2) break;
     }
     return SHMEMX_OK;
