@@ -32,6 +32,14 @@ if ROOT not in sys.path:
 import workload as W  # noqa: E402
 
 MiB = 1 << 20
+# Progress kernel launch shape for the serving rows, from measurements on
+# MI355X: whole work-groups execute chunks, and 1024-thread work-groups with
+# 256 KiB chunks gave the best tail latency under load (1 MiB chunks: about
+# 8% more saturated throughput, twice the p99).  The per-op form is fastest
+# with 256 KiB per work-group as well.
+PROGRESS_WG = 1024
+PROGRESS_CHUNK = 256 << 10
+PER_OP_CHUNK = 256 << 10
 GiB = 1 << 30
 HBM_PEAK_GBS = 8000.0
 METRIC = "put/get/alltoall GB/s vs HBM peak; AMO Mops/s; p50/p99 op latency batched vs per-op"
@@ -60,6 +68,8 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="instead of the step: open-loop Poisson serving on 128 PEs x 512 MiB, 64 GiB budget")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-wg", type=int, default=PROGRESS_WG, help="progress kernel work-group size")
+    ap.add_argument("--serve-chunk-kib", type=int, default=PROGRESS_CHUNK >> 10, help="progress kernel chunk size")
     ap.add_argument("--summarize-profiles", default="", metavar="DIR",
                     help="no GPU work: write profiles/ summaries from rocprofv3 CSV output under DIR")
     return ap.parse_args()
@@ -249,7 +259,8 @@ def serve_trace(v, npes, n, rate, src_bytes, seed):
 
 
 def serve_step(v, S):
-    v.progress_start(nwg=0, wg_size=256, ring_slots=4096, verify=False, chunk_bytes=256 << 10, stream=S["side"])
+    v.progress_start(nwg=0, wg_size=PROGRESS_WG, ring_slots=4096, verify=False, chunk_bytes=PROGRESS_CHUNK,
+                     stream=S["side"])
     try:
         dst, lat, comps, stats = v.serve_run(S["reqs"], 8, S["region_off"], S["region_bytes"], S["budget"])
     finally:
@@ -494,10 +505,11 @@ def run_serve(v, torch, args):
         v.heap_view()[:, region + 288 * MiB:region + 384 * MiB].zero_()
         torch.cuda.synchronize()
         if per_op:
-            dst, lat, comps, stats = v.serve_run_per_op(reqs, 8, region, 384 * MiB, budget, chunk_bytes=256 << 10)
+            dst, lat, comps, stats = v.serve_run_per_op(reqs, 8, region, 384 * MiB, budget, chunk_bytes=PER_OP_CHUNK)
             torch.cuda.synchronize()
             return lat, comps, stats
-        v.progress_start(nwg=0, wg_size=256, ring_slots=4096, chunk_bytes=256 << 10, stream=side)
+        v.progress_start(nwg=0, wg_size=args.serve_wg, ring_slots=4096, chunk_bytes=args.serve_chunk_kib << 10,
+                         stream=side)
         try:
             dst, lat, comps, stats = v.serve_run(reqs, 8, region, 384 * MiB, budget)
         finally:

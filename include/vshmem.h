@@ -462,27 +462,31 @@ int shmemx_tune_load(shmemx_tune_t *tune, const char *path);
  * Persistent progress kernel (long-lived kernels, Section 3; GPU-driven
  * progress, Section 6.4 and Section 7).  Host threads submit descriptors
  * (PUT, GET, AMO_FETCH_ADD with nbytes/8 counters) into a ring in pinned
- * host memory; resident work-groups claim requests, split large ones into
- * chunks that several work-groups share, execute them, quiet, and post a
- * completion record.  The kernel exits when stopped or after
- * idle_timeout_ms without work.
+ * host memory.  Work-group 0's first wavefront is the front-end: it takes
+ * published requests in ticket order and splits each into chunks of at most
+ * chunk_bytes; every other work-group is a worker that claims one chunk at
+ * a time and executes it with all its threads.  The worker finishing a
+ * request's last chunk quiets and posts the completion record.  The kernel
+ * exits when stopped or after idle_timeout_ms without work.
  */
 typedef struct shmemx_progress_cfg {
-    int32_t nwg;              /* resident work-groups (0 = one per CU) */
-    int32_t wg_size;          /* threads per work-group */
+    int32_t nwg;              /* work-groups, >= 2 (0 = one per CU) */
+    int32_t wg_size;          /* threads per work-group (0 = 1024) */
     int32_t ring_slots;       /* power of two */
     int32_t verify;           /* 1: completion carries a hash of the output */
-    uint64_t chunk_bytes;     /* split unit for large requests */
+    uint64_t chunk_bytes;     /* split unit for large requests, multiple of 16 (0 = 256 KiB) */
     uint64_t idle_timeout_ms; /* 0 = 30000 */
 } shmemx_progress_cfg_t;
 
 typedef struct shmemx_completion {
     uint64_t ticket;
-    uint64_t t_start;         /* device wall clock when first claimed */
+    uint64_t t_start;         /* device wall clock when a worker first claimed it */
     uint64_t t_end;           /* device wall clock at completion */
     uint64_t hash;            /* output hash when verify is on */
     int32_t status;           /* 0 ok */
     int32_t reserved;
+    uint64_t t_queued;        /* device wall clock when the front-end took it from the ring */
+    uint64_t submit_ns;       /* serving runs: host ns from arrival to ring publish; else 0 */
 } shmemx_completion_t;
 
 int shmemx_progress_start(const shmemx_progress_cfg_t *cfg, void *stream);
@@ -525,6 +529,7 @@ typedef struct shmemx_serve_stats {
     uint64_t amo_ops;
     uint64_t max_reserved_bytes;
     uint64_t admission_waits;
+    uint64_t ring_full_retries;   /* submissions refused because the ring was full */
 } shmemx_serve_stats_t;
 
 int shmemx_serve_run(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,

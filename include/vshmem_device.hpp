@@ -98,6 +98,17 @@ __device__ __forceinline__ void latch_error(const shmemx_dctx_pub_t &c, uint32_t
 }
 
 __device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+/* Wait until this thread's earlier vector memory operations have completed
+ * (stores acknowledged by L2): vmcnt(0), with the export and LDS counters
+ * left alone.  Followed by a work-group barrier and one agent-scope release
+ * by a single thread, it gives the whole work-group's stores agent-scope
+ * visibility with one L2 write-back instead of one per wavefront. */
+__device__ __forceinline__ void wait_vm_complete()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 __device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 template <bool NT, typename T>

@@ -372,7 +372,7 @@ def tune_load(path: str) -> Tune:
 
 
 # --------------------------------------------------------------- serving
-def progress_start(nwg: int = 0, wg_size: int = 256, ring_slots: int = 4096, verify: bool = False,
+def progress_start(nwg: int = 0, wg_size: int = 0, ring_slots: int = 4096, verify: bool = False,
                    chunk_bytes: int = 256 << 10, idle_timeout_ms: int = 30000, stream=None) -> None:
     cfg = ProgressCfg(nwg, wg_size, ring_slots, 1 if verify else 0, chunk_bytes, idle_timeout_ms)
     _check(lib.shmemx_progress_start(C.byref(cfg), _stream(stream)), "shmemx_progress_start")

@@ -44,7 +44,7 @@ class ProgressCfg(C.Structure):
 
 class Completion(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("t_start", C.c_uint64), ("t_end", C.c_uint64), ("hash", C.c_uint64),
-                ("status", C.c_int32), ("reserved", C.c_int32)]
+                ("status", C.c_int32), ("reserved", C.c_int32), ("t_queued", C.c_uint64), ("submit_ns", C.c_uint64)]
 
 
 class Request(C.Structure):
@@ -54,7 +54,8 @@ class Request(C.Structure):
 
 class ServeStats(C.Structure):
     _fields_ = [("wall_s", C.c_double), ("bytes", C.c_uint64), ("amo_ops", C.c_uint64),
-                ("max_reserved_bytes", C.c_uint64), ("admission_waits", C.c_uint64)]
+                ("max_reserved_bytes", C.c_uint64), ("admission_waits", C.c_uint64),
+                ("ring_full_retries", C.c_uint64)]
 
 
 vp, i32, u64, sz = C.c_void_p, C.c_int, C.c_uint64, C.c_size_t

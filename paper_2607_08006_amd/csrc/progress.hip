@@ -43,6 +43,7 @@ struct alignas(128) Parent {   // device memory, one per ring slot, own cache li
     uint64_t remaining;    // items not yet finished
     uint64_t t_start;
     uint64_t hash;
+    uint64_t t_queued;     // front-end pickup
     int32_t status;
     int32_t pad;
 };
@@ -109,13 +110,15 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+// This thread's share of the hash of words [lo/8, (hi+7)/8), reduced over its
+// wavefront (lane 0 holds the wavefront's share).
 __device__ uint64_t hash_range(const uint8_t *out, uint64_t lo, uint64_t hi, uint64_t total)
 {
     // lo is a multiple of 8 (chunks are multiples of 16); words are indexed from 0.
     uint64_t h = 0;
     const uint64_t w0 = lo / 8, w1 = (hi + 7) / 8;
     const bool aligned = ((uintptr_t)out & 7) == 0;
-    for (uint64_t w = w0 + __lane_id(); w < w1; w += 64) {
+    for (uint64_t w = w0 + threadIdx.x; w < w1; w += blockDim.x) {
         uint64_t x = 0;
         const uint64_t b = w * 8;
         if (aligned && b + 8 <= total) {
@@ -132,7 +135,7 @@ __device__ uint64_t hash_range(const uint8_t *out, uint64_t lo, uint64_t hi, uin
 
 __device__ __forceinline__ uint8_t *pe_base(const shmemx_dctx_pub_t &c, int pe) { return c.base + (uint64_t)pe * c.stride; }
 
-// Execute bytes [lo, hi) of a request with one wavefront.
+// Execute bytes [lo, hi) of a request with all threads of the work-group.
 __device__ void exec_item(const ProgArgs &a, const shmemx_desc_t &d, uint64_t lo, uint64_t hi, uint64_t *hash_acc)
 {
     const shmemx_dctx_pub_t &c = a.c;
@@ -140,7 +143,7 @@ __device__ void exec_item(const ProgArgs &a, const shmemx_desc_t &d, uint64_t lo
     if (d.op == SHMEMX_OP_AMO_FETCH_ADD) {
         uint64_t *ctr = (uint64_t *)(pe_base(c, d.target_pe) + d.src);
         uint64_t *res = (uint64_t *)(pe_base(c, d.issuer_pe) + d.dst);
-        for (uint64_t k = lo / 8 + __lane_id(); k < hi / 8; k += 64)
+        for (uint64_t k = lo / 8 + threadIdx.x; k < hi / 8; k += blockDim.x)
             res[k] = __hip_atomic_fetch_add(ctr + k, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         out = (uint8_t *)res;
     } else {
@@ -148,10 +151,13 @@ __device__ void exec_item(const ProgArgs &a, const shmemx_desc_t &d, uint64_t lo
         const int spe = get ? d.target_pe : d.issuer_pe;
         const int dpe = get ? d.issuer_pe : d.target_pe;
         out = pe_base(c, dpe) + d.dst;
-        vshmem_detail::copy_bytes<8, true>(out + lo, pe_base(c, spe) + d.src + lo, hi - lo, __lane_id(), 64);
+        vshmem_detail::copy_bytes<8, true>(out + lo, pe_base(c, spe) + d.src + lo, hi - lo, threadIdx.x, blockDim.x);
     }
     if (a.verify) {
+        // Every thread's stores complete before any thread reads the output.
         vshmem_detail::release_agent();
+        __syncthreads();
+        vshmem_detail::acquire_agent();
         const uint64_t h = hash_range(out, lo, hi, d.nbytes);
         if (__lane_id() == 0 && h) __hip_atomic_fetch_xor(hash_acc, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -174,16 +180,19 @@ __device__ void post_completion(const ProgArgs &a, uint32_t slot, Parent &P, int
     cp->t_start = __hip_atomic_load(&P.t_start, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     cp->t_end = wall_clock64();
     cp->hash = __hip_atomic_load(&P.hash, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cp->t_queued = ldr_dev(&P.t_queued);
+    cp->submit_ns = 0;
     cp->status = status;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: the record before the done word
     st_sys(a.ring_done + slot, cp->ticket + 1);
 }
 
 // Front-end: wavefront 0 of work-group 0.  Each round its 64 lanes look at
-// the next 64 tickets and take the published prefix at once: descriptors
-// are read in parallel, item positions come from a wavefront prefix sum,
-// and one release fence publishes the round's records before the items'
-// sequence words are stored.
+// up to the next 256 tickets and take the published prefix at once, under
+// one acquire and one release: descriptors are read in parallel, item
+// positions come from wavefront prefix sums, the items are written by all
+// lanes evenly, and the release publishes the round's records before the
+// items' sequence words are stored.
 __device__ bool wait_item_free(const ProgArgs &a, Item *it, uint64_t pos)
 {
     const uint64_t t0 = wall_clock64();
@@ -194,20 +203,29 @@ __device__ bool wait_item_free(const ProgArgs &a, Item *it, uint64_t pos)
     return true;
 }
 
+constexpr int kFrontBatches = 4;   // a round takes up to 4 x 64 published tickets
+
 __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
 {
     const uint64_t qmask = a.qsize - 1, smask = a.slots - 1;
     const uint32_t lane = __lane_id();
-    const uint32_t window = a.slots < 64 ? (uint32_t)a.slots : 64u;
+    const uint64_t window = a.slots < 64ull * kFrontBatches ? a.slots : 64ull * kFrontBatches;
     uint64_t next = 0, pub = 0;
     uint64_t idle0 = wall_clock64();
     bool ok = true;
     for (;;) {
-        const uint64_t t = next + lane;
-        const bool published = lane < window && ldr_sys(a.ring_seq + (t & smask)) == t + 1;
-        const uint64_t mask = __ballot(published);
-        const uint32_t c = ~mask == 0 ? 64u : (uint32_t)__builtin_ctzll(~mask);
-        if (c == 0) {
+        // The published prefix of the next `window` tickets, 64 at a time.
+        uint64_t c_total = 0;
+        for (int r = 0; r < kFrontBatches; ++r) {
+            const uint64_t idx = (uint64_t)r * 64 + lane;
+            const uint64_t t = next + idx;
+            const bool published = idx < window && ldr_sys(a.ring_seq + (t & smask)) == t + 1;
+            const uint64_t mask = __ballot(published);
+            const uint32_t c = ~mask == 0 ? 64u : (uint32_t)__builtin_ctzll(~mask);
+            c_total += c;
+            if (c < 64) break;
+        }
+        if (c_total == 0) {
             bool stop = false;
             if (lane == 0) stop = ldr_sys(a.stop) != 0;
             if (__shfl((int)stop, 0, 64)) break;
@@ -219,59 +237,103 @@ __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
             continue;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // system scope: descriptors after their sequence words
-        const bool mine = lane < c;
-        const uint32_t slot = (uint32_t)(t & smask);
-        shmemx_desc_t d{};
-        bool valid = false;
-        uint64_t nitems = 0;
-        if (mine) {
-            load_desc(d, a.ring + slot, true);
-            valid = valid_request(a.c, d);
-            nitems = valid ? (d.nbytes == 0 ? 1 : (d.nbytes + a.chunk - 1) / a.chunk) : 0;
-        }
-        uint64_t incl = nitems;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint64_t y = __shfl_up(incl, off, 64);
-            if ((int)lane >= off) incl += y;
-        }
-        const uint64_t first = pub + incl - nitems;
-        const uint64_t total = __shfl(incl, 63, 64);
-        if (mine) {
-            Parent &P = a.parents[slot];
-            P.d = d;
-            P.ticket = t;
-            P.t_start = 0;
-            P.hash = 0;
-            P.remaining = nitems;
-            P.status = 0;
-            for (uint64_t k = 0; k < nitems && ok; ++k) {
-                const uint64_t pos = first + k;
-                Item *it = a.items + (pos & qmask);
-                ok = wait_item_free(a, it, pos);
-                it->parent = slot;
-                it->ticket = t;
-                it->lo = k * a.chunk;
-                it->hi = min(d.nbytes, (k + 1) * a.chunk);
+        uint64_t pos0 = pub;                            // next free item position
+        uint64_t invalid = 0;                           // bit r: this lane's request of batch r is invalid
+        for (int r = 0; r * 64ull < c_total; ++r) {
+            const uint64_t t = next + (uint64_t)r * 64 + lane;
+            const bool mine = (uint64_t)r * 64 + lane < c_total;
+            const uint32_t slot = (uint32_t)(t & smask);
+            shmemx_desc_t d{};
+            bool valid = false;
+            uint64_t nitems = 0;
+            if (mine) {
+                // After the acquire, plain 16-byte loads: the four loads of a
+                // lane share one host cache line, fetched over PCIe once.
+                const vshmem_detail::v4u *q = (const vshmem_detail::v4u *)(a.ring + slot);
+                vshmem_detail::v4u w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[i] = q[i];
+                memcpy(&d, w, sizeof(d));
+                valid = valid_request(a.c, d);
+                nitems = valid ? (d.nbytes == 0 ? 1 : (d.nbytes + a.chunk - 1) / a.chunk) : 0;
+                if (!valid) invalid |= 1ull << r;
             }
+            uint64_t incl = nitems;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint64_t y = __shfl_up(incl, off, 64);
+                if ((int)lane >= off) incl += y;
+            }
+            const uint64_t first = incl - nitems;      // this lane's first item, relative to pos0
+            const uint64_t total = __shfl(incl, 63, 64);
+            if (mine) {
+                Parent &P = a.parents[slot];
+                P.d = d;
+                P.ticket = t;
+                P.t_start = 0;
+                P.hash = 0;
+                P.t_queued = wall_clock64();
+                P.remaining = nitems;
+                P.status = 0;
+            }
+            // The batch's items are spread over all lanes: item j belongs to
+            // the last lane whose first item is <= j (lanes without items
+            // share the next lane's first, so the last such lane owns it).
+            for (uint64_t j0 = 0; j0 < total; j0 += 64) {
+                if (pos0 + j0 + 64 - pub > a.qsize) {
+                    // The queue holds qsize items: publish the ones written so
+                    // far so that workers can free slots for the rest.
+                    if (__ballot(!ok)) break;
+                    vshmem_detail::release_agent();
+                    for (uint64_t pos = pub + lane; pos < pos0 + j0; pos += 64)
+                        __hip_atomic_store(&a.items[pos & qmask].seq, pos + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    pub = pos0 + j0;
+                }
+                const uint64_t j = j0 + lane;
+                uint32_t lo = 0, hi = 63;
+#pragma unroll
+                for (int step = 0; step < 6; ++step) {
+                    const uint32_t mid = (lo + hi + 1) / 2;
+                    const uint64_t f = __shfl(first, (int)mid, 64);
+                    if (f <= j) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint64_t o_first = __shfl(first, (int)lo, 64);
+                const uint64_t o_ticket = __shfl(t, (int)lo, 64);
+                const uint64_t o_bytes = __shfl(d.nbytes, (int)lo, 64);
+                const uint32_t o_slot = (uint32_t)__shfl((int)slot, (int)lo, 64);
+                if (j < total && ok) {
+                    const uint64_t k = j - o_first;
+                    const uint64_t pos = pos0 + j;
+                    Item *it = a.items + (pos & qmask);
+                    ok = wait_item_free(a, it, pos);
+                    if (ok) {
+                        it->parent = o_slot;
+                        it->ticket = o_ticket;
+                        it->lo = k * a.chunk;
+                        it->hi = min(o_bytes, (k + 1) * a.chunk);
+                    }
+                }
+            }
+            pos0 += total;
         }
+        if (__ballot(!ok)) break;            // an item slot never came free: shut down
         vshmem_detail::release_agent();   // records and items before their sequence words
-        if (mine) {
-            for (uint64_t k = 0; k < nitems; ++k) {
-                const uint64_t pos = first + k;
-                __hip_atomic_store(&a.items[pos & qmask].seq, pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (!valid) {
+        for (uint64_t pos = pub + lane; pos < pos0; pos += 64)
+            __hip_atomic_store(&a.items[pos & qmask].seq, pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int r = 0; invalid >> r; ++r) {
+            if ((invalid >> r) & 1) {
+                const uint32_t slot = (uint32_t)((next + (uint64_t)r * 64 + lane) & smask);
                 a.parents[slot].t_start = wall_clock64();
                 vshmem_detail::latch_error(a.c, 0x2u);
                 post_completion(a, slot, a.parents[slot], -1);
             }
         }
-        next += c;
-        pub += total;
+        next += c_total;
+        pub = pos0;
         idle0 = wall_clock64();
-        if (!__shfl((int)ok, 0, 64) || __ballot(!ok)) break;
     }
-    // One poison item per worker wavefront, lanes in parallel.
+    // One poison item per worker work-group, lanes in parallel.
     for (uint64_t w0 = 0; w0 < nworkers; w0 += 64) {
         const uint64_t w = w0 + lane;
         bool freed = false;
@@ -288,64 +350,113 @@ __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
     }
 }
 
-__device__ void worker(const ProgArgs &a)
+// A worker work-group: thread 0 claims the next item ticket, waits for the
+// item, and shares it through LDS; the whole work-group executes it (wide,
+// contiguous streams keep HBM busy); the last item of a request posts its
+// completion.
+struct ClaimedItem {
+    shmemx_desc_t d;
+    uint64_t parent, lo, hi;
+    int state;   // 0 run, 1 stop, 2 skip
+};
+
+// Thread 0 of the work-group: claim the next item and fill `ci`.
+__device__ void claim_item(const ProgArgs &a, ClaimedItem &ci)
 {
     const uint64_t qmask = a.qsize - 1;
+    const uint64_t t = __hip_atomic_fetch_add(a.claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Item *it = a.items + (t & qmask);
+    const uint64_t t0 = wall_clock64();
+    bool ready = true;
+    while (ldr_dev(&it->seq) != t + 1) {
+        __builtin_amdgcn_s_sleep(2);
+        if (wall_clock64() - t0 > 2 * a.idle_ticks) {
+            ready = false;
+            break;
+        }
+    }
+    ci.state = 1;
+    if (!ready) return;
+    vshmem_detail::acquire_agent();
+    const uint64_t parent = ldr_dev(&it->parent);
+    const uint64_t ticket = ldr_dev(&it->ticket);
+    ci.lo = ldr_dev(&it->lo);
+    ci.hi = ldr_dev(&it->hi);
+    st_dev(&it->seq, t + a.qsize);   // the slot is free again
+    if (parent == kItemPoison) return;
+    Parent &P = a.parents[parent];
+    load_desc(ci.d, &P.d, false);
+    ci.parent = parent;
+    if (ldr_dev(&P.ticket) != ticket) {
+        // A record that does not belong to this item: report it, skip it.
+        vshmem_detail::latch_error(a.c, 0x8u);
+        ci.state = 2;
+        return;
+    }
+    uint64_t zero = 0;
+    __hip_atomic_compare_exchange_strong(&P.t_start, &zero, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ci.state = 0;
+}
+
+// Values every thread reads from LDS, made visibly uniform (scalar registers).
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ void uniform_copy(void *dst, const void *src, size_t bytes)
+{
+    uint32_t *d = (uint32_t *)dst;
+    const uint32_t *q = (const uint32_t *)src;
+    for (size_t i = 0; i < bytes / 4; ++i) d[i] = __builtin_amdgcn_readfirstlane(q[i]);
+}
+
+// Every branch around a barrier below is uniform across the work-group and
+// visibly so to the compiler (wavefront index and item state go through
+// readfirstlane): a loop whose exit the compiler must treat as divergent
+// can be restructured so that some lanes cycle through the barriers while
+// thread 0, which claims the next item, stays masked off.
+__device__ void worker(const ProgArgs &a)
+{
+    __shared__ ClaimedItem ci;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     for (;;) {
-        uint64_t t = 0;
-        if (__lane_id() == 0) t = __hip_atomic_fetch_add(a.claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __shfl(t, 0, 64);
-        Item *it = a.items + (t & qmask);
-        bool ready = true;
-        if (__lane_id() == 0) {
-            const uint64_t t0 = wall_clock64();
-            while (ldr_dev(&it->seq) != t + 1) {
-                __builtin_amdgcn_s_sleep(2);
-                if (wall_clock64() - t0 > 2 * a.idle_ticks) {
-                    ready = false;
-                    break;
+        if (wave == 0) {
+            if (__lane_id() == 0) claim_item(a, ci);
+        }
+        __syncthreads();
+        const int state = __builtin_amdgcn_readfirstlane(ci.state);
+        if (state == 1) break;
+        if (state == 0) {
+            shmemx_desc_t d;
+            uniform_copy(&d, &ci.d, sizeof(d));
+            const uint64_t parent = uniform_u64(ci.parent), lo = uniform_u64(ci.lo), hi = uniform_u64(ci.hi);
+            Parent &P = a.parents[parent];
+            exec_item(a, d, lo, hi, &P.hash);
+            vshmem_detail::wait_vm_complete();   // this thread's stores of the item reached L2
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                vshmem_detail::release_agent();   // the work-group's stores are visible device-wide
+                const uint64_t left = __hip_atomic_fetch_sub(&P.remaining, 1ull, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                if (left == 1) {
+                    vshmem_detail::acquire_agent();
+                    post_completion(a, (uint32_t)parent, P, 0);
                 }
             }
         }
-        ready = __shfl((int)ready, 0, 64);
-        if (!ready) return;
-        vshmem_detail::acquire_agent();
-        const uint64_t parent = ldr_dev(&it->parent);
-        const uint64_t ticket = ldr_dev(&it->ticket);
-        const uint64_t lo = ldr_dev(&it->lo), hi = ldr_dev(&it->hi);
-        if (__lane_id() == 0) st_dev(&it->seq, t + a.qsize);   // the slot is free again
-        if (parent == kItemPoison) return;
-        Parent &P = a.parents[parent];
-        shmemx_desc_t md;
-        load_desc(md, &P.d, false);
-        if (ldr_dev(&P.ticket) != ticket) {
-            // A record that does not belong to this item: report it, skip it.
-            if (__lane_id() == 0) vshmem_detail::latch_error(a.c, 0x8u);
-            continue;
-        }
-        if (__lane_id() == 0) {
-            uint64_t zero = 0;
-            __hip_atomic_compare_exchange_strong(&P.t_start, &zero, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        exec_item(a, md, lo, hi, &P.hash);
-        vshmem_detail::release_agent();   // this item's stores are complete device-wide
-        if (__lane_id() == 0) {
-            const uint64_t left = __hip_atomic_fetch_sub(&P.remaining, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (left == 1) {
-                vshmem_detail::acquire_agent();
-                post_completion(a, (uint32_t)parent, P, 0);
-            }
-        }
+        __syncthreads();   // every thread is done with `ci` before the next claim
     }
 }
 
 __global__ void __launch_bounds__(1024) k_progress(ProgArgs a)
 {
-    const uint64_t waves_per_wg = blockDim.x / 64;
-    const uint64_t nworkers = (uint64_t)gridDim.x * waves_per_wg - 1;
-    if (blockIdx.x == 0 && threadIdx.x < 64) {   // the whole first wavefront is the front-end
-        front_end(a, nworkers);
+    // Work-group 0: its first wavefront is the front-end, its other
+    // wavefronts idle.  Every other work-group is one worker.
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 64) front_end(a, (uint64_t)gridDim.x - 1);
         return;
     }
     worker(a);
@@ -458,14 +569,14 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     if (p.running) return SHMEMX_ERR_BUSY;
     shmemx_progress_cfg_t cfg{};
     if (cfg_in) cfg = *cfg_in;
-    if (cfg.wg_size == 0) cfg.wg_size = 256;
+    if (cfg.wg_size == 0) cfg.wg_size = 1024;
     if (cfg.ring_slots == 0) cfg.ring_slots = 4096;
     if (cfg.chunk_bytes == 0) cfg.chunk_bytes = 256ull << 10;
     if (cfg.idle_timeout_ms == 0) cfg.idle_timeout_ms = 30000;
     const State &s = st();
     if (cfg.nwg == 0) cfg.nwg = s.num_cus;
-    if (!valid_wg_size(cfg.wg_size) || cfg.nwg < 1 || cfg.nwg > 8 * s.num_cus || cfg.ring_slots < 2 ||
-        (cfg.ring_slots & (cfg.ring_slots - 1)) || (cfg.chunk_bytes & 15) || (cfg.nwg == 1 && cfg.wg_size == 64))
+    if (!valid_wg_size(cfg.wg_size) || cfg.nwg < 2 || cfg.nwg > 8 * s.num_cus || cfg.ring_slots < 2 ||
+        (cfg.ring_slots & (cfg.ring_slots - 1)) || (cfg.chunk_bytes & 15))
         return SHMEMX_ERR_ARG;
     const uint64_t slots = (uint64_t)cfg.ring_slots;
     const uint64_t qsize = 1ull << 16;

@@ -29,7 +29,7 @@ struct Admission {
 struct Slot {
     std::atomic<int> state{0};          // 0 waiting, 1 submitted, 2 done
     uint64_t ticket = 0;
-    Clock::time_point arrival;
+    Clock::time_point arrival, submitted;
     uint64_t dst = 0, ctr = 0, bytes = 0;
     int dst_pe = 0;
 };
@@ -41,23 +41,42 @@ struct Backend {
     virtual ~Backend() = default;
     // Issue request `index` from producer `lane`; on success *ticket names it.
     virtual int submit(const shmemx_desc_t &d, size_t index, int lane, uint64_t *ticket) = 0;
+    std::atomic<uint64_t> busy_retries{0};
     // 1 and *out filled when finished, 0 when not yet, < 0 on error.
     virtual int poll(uint64_t ticket, shmemx_completion_t *out) = 0;
+    // Called by the completion thread after a pass that freed ring slots.
+    virtual void slots_freed() {}
 };
 
 // The persistent progress kernel: requests go through its host ring.
+// A producer that finds the ring full sleeps until the completion thread
+// has freed slots (a generation count) instead of spinning on the ring's
+// cache lines, which starved the completion thread itself.
 struct ProgressBackend final : Backend {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::atomic<uint64_t> gen{0};
+
     int submit(const shmemx_desc_t &d, size_t, int, uint64_t *ticket) override
     {
-        int rc;
         const Clock::time_point t0 = Clock::now();
-        while ((rc = shmemx_progress_submit(&d, ticket)) == SHMEMX_ERR_BUSY) {
-            if (Clock::now() - t0 > std::chrono::seconds(30)) break;
-            std::this_thread::yield();
+        for (;;) {
+            const uint64_t seen = gen.load(std::memory_order_acquire);
+            const int rc = shmemx_progress_submit(&d, ticket);
+            if (rc != SHMEMX_ERR_BUSY) return rc;
+            busy_retries.fetch_add(1, std::memory_order_relaxed);
+            if (Clock::now() - t0 > std::chrono::seconds(30)) return rc;
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait_for(lk, std::chrono::milliseconds(1), [&] { return gen.load(std::memory_order_acquire) != seen; });
         }
-        return rc;
     }
     int poll(uint64_t ticket, shmemx_completion_t *out) override { return shmemx_progress_poll(ticket, out); }
+    void slots_freed() override
+    {
+        gen.fetch_add(1, std::memory_order_release);
+        { std::lock_guard<std::mutex> lk(mu); }
+        cv.notify_all();
+    }
 };
 
 // One kernel launch per request on the producer lane's own stream; an event
@@ -234,6 +253,7 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
                 return;
             }
             sl.ticket = t;
+            sl.submitted = Clock::now();
             sl.state.store(1, std::memory_order_release);
         }
     };
@@ -257,6 +277,7 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
                 if (pr == 1) {
                     const Clock::time_point now = Clock::now();
                     if (latency_ns) latency_ns[i] = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - sl.arrival).count();
+                    c.submit_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(sl.submitted - sl.arrival).count();
                     if (completions) completions[i] = c;
                     if (dst_off_out) dst_off_out[i] = sl.dst;
                     {
@@ -272,6 +293,7 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
                 }
             }
             while (lo < n && slots[lo].state.load(std::memory_order_acquire) == 2) ++lo;
+            if (any) be.slots_freed();
             if (any) last_progress = Clock::now();
             else if (Clock::now() - last_progress > std::chrono::seconds(60)) failed.store(SHMEMX_ERR_TIMEOUT);
             else std::this_thread::yield();
@@ -294,6 +316,7 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
         }
         stats->max_reserved_bytes = adm.max_reserved;
         stats->admission_waits = adm.waits;
+        stats->ring_full_retries = be.busy_retries.load();
     }
     return failed.load();
 }

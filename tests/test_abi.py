@@ -59,11 +59,37 @@ def test_binding_declares_exactly_the_header():
     assert sorted(_native.SIGNATURES) == declared_functions()
 
 
-def test_struct_sizes_match_header():
+STRUCTS = {"Desc": "shmemx_desc_t", "Caps": "shmemx_caps_t", "Launch": "shmemx_launch_t", "Tune": "shmemx_tune_t",
+           "ProgressCfg": "shmemx_progress_cfg_t", "Completion": "shmemx_completion_t", "Request": "shmemx_request_t",
+           "ServeStats": "shmemx_serve_stats_t"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes record has the size and field offsets the C compiler
+    gives the header's struct of the same name."""
+    from paper_2607_08006_amd import _native
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vshmem.h"', "int main(void) {"]
+    for py, c in STRUCTS.items():
+        lines.append(f'  printf("{py} size %zu\\n", sizeof({c}));')
+        for f, _ in getattr(_native, py)._fields_:
+            lines.append(f'  printf("{py} {f} %zu\\n", offsetof({c}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(x.split()[:2]): int(x.split()[2]) for x in out if x}
+    for py in STRUCTS:
+        cls = getattr(_native, py)
+        assert got[(py, "size")] == ctypes.sizeof(cls), py
+        for f, _ in cls._fields_:
+            assert got[(py, f)] == getattr(cls, f).offset, (py, f)
+
+
+def test_desc_record_matches_workload_dtype():
     from paper_2607_08006_amd import _native
     assert ctypes.sizeof(_native.Desc) == 64
-    assert ctypes.sizeof(_native.Launch) == 24
-    assert ctypes.sizeof(_native.Completion) == 40
     import workload
     assert workload.DESC_DTYPE.itemsize == ctypes.sizeof(_native.Desc)
     for f, _ in _native.Desc._fields_:

@@ -264,3 +264,39 @@ def test_serving_per_op_final_state_and_budget():
         ctr = got[:, ctr_base:].copy().view("<u8")
         assert int(ctr.sum()) == n_ctr and int(ctr.max()) <= 1
         assert_no_device_errors()
+
+
+def test_progress_request_larger_than_item_queue():
+    """A request split into more items than the device queue holds (2 MiB in
+    16-byte items = 131072 items, queue 65536) is published in parts and
+    still completes with the right bytes; a small request behind it too."""
+    npes = 4
+    with heap(npes, 8 << 20) as v:
+        t = torch()
+        region = 6 << 20
+        init = W.heap_fill(0xA11CE, npes, region)
+        upload(init)
+        side = t.cuda.Stream()
+        v.progress_start(nwg=64, wg_size=256, ring_slots=16, verify=True, chunk_bytes=16, stream=side)
+        reqs = [(W.OP_PUT, 0, 1, 0, 3 << 20, 2 << 20), (W.OP_GET, 2, 3, 4096, (5 << 20) + 16, 1000)]
+        tickets = [v.progress_submit(_desc(*r)) for r in reqs]
+        comps = {}
+        t0 = time.time()
+        while len(comps) < len(tickets) and time.time() - t0 < 60:
+            for tk in tickets:
+                if tk not in comps:
+                    c = v.progress_poll(tk)
+                    if c is not None:
+                        comps[tk] = c
+        v.progress_stop(20000)
+        side.synchronize()
+        assert len(comps) == len(tickets)
+        got = download(region)
+        ref = init.copy()
+        oracle.run_program(ref, W.descs([(op, 0, 0, i, tg, W.NO_RESULT, s, d, n, 0, 0) for op, i, tg, s, d, n in reqs]))
+        assert np.array_equal(got, ref)
+        for tk, (op, i, tg, s, d, n) in zip(tickets, reqs):
+            out_pe = tg if op == W.OP_PUT else i
+            assert comps[tk].status == 0 and comps[tk].hash == out_hash(ref[out_pe, d:d + n])
+            assert comps[tk].t_queued > 0 and comps[tk].t_end >= comps[tk].t_start >= comps[tk].t_queued
+        assert_no_device_errors()
