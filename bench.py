@@ -144,11 +144,11 @@ def build_rows(v, torch, L: Layout, npes: int, want):
     huge = int(64 * MiB * min(1.0, scale))
     f, b = rma(v.OP_PUT, v.SCOPE_GRID, perm, huge, 4, 256, flags=deep)
     add("put_grid_64MiB_perm", f, b, kernel="k_rma_pattern<3,true,true,8>")
-    f, b = rma(v.OP_PUT, v.SCOPE_WAVE, perm, 4096, 16, 256)
+    f, b = rma(v.OP_PUT, v.SCOPE_WAVE, perm, 4096, 4, 256, flags=v.LAUNCH_NONTEMPORAL)
     add("put_wave_4KiB_perm", f, b)
     f, b = rma(v.OP_GET, v.SCOPE_THREAD, ring, 64, 4, 256)
     add("get_thread_64B_ring", f, b)
-    f, b = rma(v.OP_PUT, v.SCOPE_THREAD, perm, 8, 4, 256)
+    f, b = rma(v.OP_PUT, v.SCOPE_THREAD, perm, 8, 4, 1024)
     add("put_thread_8B_perm", f, b)
 
     # ---- atomics (a4): 2^26 random fetch_xor / fetch_add updates on a 2^27-entry table

@@ -109,6 +109,24 @@ __device__ __forceinline__ void wait_vm_complete()
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
+
+/* Agent-scope release of everything the work-group stored, with one L2
+ * write-back: every thread waits for its own operations, the work-group
+ * synchronises, thread 0 releases.  Every thread of the work-group must
+ * call it.  An agent release per wavefront costs one write-back each, and
+ * those serialise in the L2s (thousands of wavefronts: hundreds of us). */
+__device__ __forceinline__ void release_wg_at_exit()
+{
+    wait_vm_complete();
+    __syncthreads();
+    if (threadIdx.x == 0) release_agent();
+}
+/* As above, and no thread returns before the release is done. */
+__device__ __forceinline__ void release_wg()
+{
+    release_wg_at_exit();
+    __syncthreads();
+}
 __device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 template <bool NT, typename T>
@@ -225,7 +243,11 @@ __device__ __forceinline__ uint64_t *sync_slot(const shmemx_dctx_pub_t &c, int p
 
 /* Sense-reversing counter barrier among `units` arriving work-groups; one
  * thread per work-group calls it.  Release before arriving, acquire after
- * leaving, so it also completes (quiets) the arrivals' stores. */
+ * leaving (in both the last arrival and the waiters), so it also completes
+ * (quiets) the arrivals' stores.  Called after the work-group's threads
+ * waited for their own operations and synchronised, the release and
+ * acquire of this one thread cover the whole work-group: they write back
+ * and invalidate the caches the work-group's wavefronts share. */
 __device__ __forceinline__ void counter_barrier(const shmemx_dctx_pub_t &c, uint64_t *slot, uint64_t units)
 {
     uint64_t *cnt = slot;
@@ -234,6 +256,7 @@ __device__ __forceinline__ void counter_barrier(const shmemx_dctx_pub_t &c, uint
     uint64_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t old = __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == units - 1) {
+        acquire_agent();   // the other arrivals' releases
         __hip_atomic_store(cnt, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
@@ -336,11 +359,7 @@ __device__ __forceinline__ void shmem_quiet_wave(const shmem_dctx_t &) { vshmem_
 __device__ __forceinline__ void shmem_fence_wave(const shmem_dctx_t &) { vshmem_detail::release_agent(); }
 /* Every lane completes its own stores, then the work-group synchronises:
  * all of the work-group's earlier operations are complete on return. */
-__device__ __forceinline__ void shmem_quiet_wg(const shmem_dctx_t &)
-{
-    vshmem_detail::release_agent();
-    __syncthreads();
-}
+__device__ __forceinline__ void shmem_quiet_wg(const shmem_dctx_t &) { vshmem_detail::release_wg(); }
 __device__ __forceinline__ void shmem_fence_wg(const shmem_dctx_t &ctx) { shmem_quiet_wg(ctx); }
 
 /* --------------------------------------------------------------- atomics */
@@ -425,8 +444,7 @@ __device__ __forceinline__ void shmem_putmem_signal_wg(const shmem_dctx_t &ctx, 
                                                        uint64_t *sig, uint64_t sigval, int sig_op, int pe)
 {
     shmem_putmem_nbi_wg(ctx, dest, src, n, pe);
-    vshmem_detail::release_agent();
-    __syncthreads();
+    vshmem_detail::release_wg_at_exit();
     if (threadIdx.x == 0) vshmemx_signal_update(ctx, sig, sigval, sig_op, pe);
     __syncthreads();
 }
@@ -465,15 +483,15 @@ __device__ __forceinline__ uint64_t shmem_signal_wait_until_wg(const shmem_dctx_
 __device__ __forceinline__ void shmemx_team_sync_units(const shmem_dctx_t &ctx, const shmemx_dteam_t &team,
                                                        uint64_t units_per_pe)
 {
-    // Every wavefront completes its own stores before the work-group arrives.
-    vshmem_detail::release_agent();
+    // Every thread's operations complete before the work-group arrives;
+    // thread 0's release and acquire inside the barrier then cover them all.
+    vshmem_detail::wait_vm_complete();
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t *slot = vshmem_detail::sync_slot(ctx.c, team.start, team.slot);
         vshmem_detail::counter_barrier(ctx.c, slot, (uint64_t)team.size * units_per_pe);
     }
     __syncthreads();
-    vshmem_detail::acquire_agent();
 }
 
 /* barrier_all with one work-group per PE (rocSHMEM-style _wg routine). */

@@ -138,9 +138,8 @@ __device__ __forceinline__ void exec_wg(const shmemx_dctx_pub_t &c, const shmemx
         if (threadIdx.x == 0) exec_amo(c, d, results);
     } else if (d.op == SHMEMX_OP_PUT || d.op == SHMEMX_OP_GET || d.op == SHMEMX_OP_PUT_SIGNAL) {
         exec_copy(c, d, lo, hi, threadIdx.x, blockDim.x);
-        if (d.op == SHMEMX_OP_PUT_SIGNAL) {
-            vshmem_detail::release_agent();
-            __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(d.op) == SHMEMX_OP_PUT_SIGNAL) {   // uniform: a barrier follows
+            vshmem_detail::release_wg_at_exit();
             if (threadIdx.x == 0) signal_of(c, d);
         }
     }
@@ -190,24 +189,32 @@ __global__ void __launch_bounds__(1024) k_plan_fused(shmemx_dctx_pub_t c, const 
                                                      const PlanTask *__restrict__ T, const uint32_t *__restrict__ phase,
                                                      int nphases, uint64_t *results, uint64_t *stamps)
 {
+    // Loop bounds and task fields go through readfirstlane: the task loop
+    // holds work-group barriers, and the compiler must see its exits (and
+    // the branches around the barriers) as uniform.
     for (int ph = 0; ph < nphases; ++ph) {
-        const uint32_t t1 = phase[ph + 1];
-        for (uint32_t t = phase[ph] + blockIdx.x; t < t1; t += gridDim.x) {
-            const PlanTask task = T[t];
+        const uint32_t t1 = __builtin_amdgcn_readfirstlane(phase[ph + 1]);
+        const uint32_t t0 = __builtin_amdgcn_readfirstlane(phase[ph]);
+        for (uint32_t t = t0 + blockIdx.x; t < t1; t += gridDim.x) {
+            PlanTask task;
+            const uint32_t *q = (const uint32_t *)(T + t);
+            uint32_t *w = (uint32_t *)&task;
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(PlanTask) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(q[i]);
             run_task(c, D, task, results, stamps);
         }
         if (ph + 1 < nphases) {
             // Ordering point: every work-group's earlier operations complete
-            // before any later operation starts.
-            vshmem_detail::release_agent();
+            // before any later operation starts (thread 0's release and
+            // acquire in the barrier cover its work-group).
+            vshmem_detail::wait_vm_complete();
             __syncthreads();
             if (threadIdx.x == 0)
                 vshmem_detail::counter_barrier(c, vshmem_detail::sync_slot(c, 0, kTeamSlotPlan), gridDim.x);
             __syncthreads();
-            vshmem_detail::acquire_agent();
         }
     }
-    vshmem_detail::release_agent();   // quiet
+    vshmem_detail::release_wg_at_exit();   // quiet
 }
 
 // Per-operation form: the kernel receives its descriptor by value.
@@ -223,11 +230,8 @@ __global__ void __launch_bounds__(1024) k_plan_one(shmemx_dctx_pub_t c, shmemx_d
         const uint64_t hi = lo + chunk < d.nbytes ? lo + chunk : d.nbytes;
         if (lo < hi || (blockIdx.x == 0 && d.nbytes == 0)) exec_wg(c, d, lo, hi, results);
     }
-    vshmem_detail::release_agent();
-    if (stamps) {
-        __syncthreads();
-        if (threadIdx.x == 0) stamp(stamps, d.reserved);
-    }
+    vshmem_detail::release_wg_at_exit();   // quiet
+    if (stamps && threadIdx.x == 0) stamp(stamps, d.reserved);
 }
 
 __global__ void k_stamp(uint64_t *dst) { if (threadIdx.x == 0) *dst = wall_clock64(); }

@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(1024) k_request(shmemx_dctx_pub_t c, shmemx_de
                                                threadIdx.x, blockDim.x);
         }
     }
-    vshmem_detail::release_agent();
+    vshmem_detail::release_wg_at_exit();   // quiet
 }
 
 bool valid_request_host(const shmemx_desc_t &d)

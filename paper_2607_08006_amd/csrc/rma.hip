@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(1024) k_rma_pattern(shmemx_dctx_pub_t c, const
         for (uint64_t j = 0; j < nmsg; ++j)
             vshmem_detail::copy_bytes<U, NT>(D + j * dstep, S + j * sstep, msg, lane, nl);
     }
-    vshmem_detail::release_agent();   // quiet
+    vshmem_detail::release_wg_at_exit();   // quiet
 }
 
 template <int SCOPE, bool IS_PUT>

@@ -92,7 +92,8 @@ def test_reductions_bit_exact(dt, rop):
             for nreduce in (1, 7, 1000, nmax):
                 init = np.zeros((npes, region), dtype=np.uint8)
                 init[:, so:so + nreduce * es] = _red_inputs(dt, npes, nreduce, 1000 * npes + nreduce)
-                for L in (dict(wgs_per_pe=2, wg_size=256, chunk_bytes=4096), dict(wgs_per_pe=1, wg_size=64)):
+                for L in (dict(wgs_per_pe=2, wg_size=256, chunk_bytes=4096), dict(wgs_per_pe=1, wg_size=64),
+                          dict(wgs_per_pe=3, wg_size=128, chunk_bytes=16384, flags=v.LAUNCH_NONTEMPORAL)):
                     upload(init)
                     v.reduce(dt, rop, dst, src, nreduce, launch=v.launch_cfg(**L))
                     got = download(region)
@@ -109,6 +110,29 @@ def test_reductions_bit_exact(dt, rop):
             oracle.reduce(ref, dt, rop, so, so, 999)
             assert np.array_equal(got, ref)
             assert_no_device_errors()
+
+
+@pytest.mark.parametrize("dt", [oracle.DT_INT64, oracle.DT_FP32, oracle.DT_BF16])
+def test_reduction_team_of_130(dt):
+    """A team of 130 members needs 8 TREE levels; 130 is not a power of
+    two, so odd carries occur at several levels."""
+    es = {oracle.DT_INT64: 8, oracle.DT_FP32: 4, oracle.DT_BF16: 2}[dt]
+    npes, nreduce = 130, 5003
+    with heap(npes, 2 << 20) as v:
+        src = v.malloc(nreduce * es)
+        dst = v.malloc(nreduce * es)
+        so, do = v.offset(src), v.offset(dst)
+        region = do + nreduce * es
+        init = np.zeros((npes, region), dtype=np.uint8)
+        init[:, so:so + nreduce * es] = _red_inputs(dt, npes, nreduce, 4242)
+        for rop in (oracle.RO_SUM, oracle.RO_MAX):
+            upload(init)
+            v.reduce(dt, rop, dst, src, nreduce)
+            got = download(region)
+            ref = init.copy()
+            oracle.reduce(ref, dt, rop, do, so, nreduce)
+            assert np.array_equal(got, ref), (dt, rop)
+        assert_no_device_errors()
 
 
 def test_strided_team_collectives():
