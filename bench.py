@@ -40,6 +40,7 @@ MiB = 1 << 20
 PROGRESS_WG = 1024
 PROGRESS_CHUNK = 256 << 10
 PER_OP_CHUNK = 256 << 10
+WINDOW_US = 20.0   # arrival window of the batched serving forms
 GiB = 1 << 30
 HBM_PEAK_GBS = 8000.0
 METRIC = "put/get/alltoall GB/s vs HBM peak; AMO Mops/s; p50/p99 op latency batched vs per-op"
@@ -382,6 +383,59 @@ def summarize_profiles(prof_dir: str, probe_mib: int) -> None:
     print(json.dumps(out, indent=1))
 
 
+def measure_ceilings(v, torch, L: Layout, npes: int):
+    """Measured ceilings the rows are compared with (outside the timed
+    steps): the achievable copy rate (the copy probe, 4 GiB), agent-scope
+    random atomics on a 4 MiB and a 1 GiB table, and signal ping-pong
+    one-way latency for one pair and for all pairs, with the two sides of a
+    pair on one XCD or on two."""
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps=5):
+        ts = []
+        for r in range(reps + 1):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    out = {}
+    n = 4 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ms = timed(lambda: v.probe_copy(b, a, n))
+    out["copy_GB_s"] = round(2 * n / (ms * 1e-3) / 1e9, 1)
+    del a, b
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nupd = 1 << 26
+    for tag, lg in (("table_4MiB", 19), ("table_1GiB", 27)):
+        table = torch.zeros(1 << lg, dtype=torch.int64, device="cuda")
+        ms = timed(lambda: v.probe_atomics(table, 1 << lg, nupd, 0x5EED0003, acc))
+        out.setdefault("atomics_G_updates_s", {})[tag] = round(nupd / (ms * 1e-3) / 1e9, 2)
+        del table
+    torch.cuda.empty_cache()
+    hz = v.wallclock_hz()
+    rounds = 1000
+    npairs_all = npes // 2
+    pairs = torch.arange(2 * npairs_all, dtype=torch.int32, device="cuda")
+    lat = {}
+    for tag, np_, same in (("one_pair_cross_xcd", 1, False), ("one_pair_same_xcd", 1, True),
+                           (f"{npairs_all}_pairs_cross_xcd", npairs_all, False),
+                           (f"{npairs_all}_pairs_same_xcd", npairs_all, True)):
+        rtt = torch.zeros(np_ * rounds, dtype=torch.int64, device="cuda")
+        v.pingpong(L.H, L.H + 64, pairs, np_, rounds, 8, same, rtt)
+        torch.cuda.synchronize()
+        ns = rtt.cpu().numpy().astype(np.float64) / hz * 1e9 / 2
+        lat[tag] = {"p50": round(percentile(ns, 50), 1), "p99": round(percentile(ns, 99), 1)}
+    out["pingpong_one_way_ns"] = lat
+    return out
+
+
 def cpu_baseline(seconds: float):
     """Time the CPU oracle (single thread, as written) on bounded samples of
     the step's rows and report algorithmic GB/s."""
@@ -488,8 +542,9 @@ def run_sweep(v, torch, args):
 def run_serve(v, torch, args):
     """Open-loop serving: saturated burst first, then Poisson arrivals at 50%
     and 80% of the persistent kernel's saturated byte rate, on 128 PEs x
-    512 MiB with a 64 GiB budget; every trace runs on the persistent progress
-    kernel and on the per-op form (one launch per request)."""
+    512 MiB with a 64 GiB budget; every trace runs in four forms: the
+    persistent progress kernel, windowed batches replayed from a graph or
+    launched fused, and one launch per request."""
     npes, heap = 128, 512 * MiB
     v.init(npes, heap)
     src = v.offset(v.malloc(128 * MiB))
@@ -501,11 +556,17 @@ def run_serve(v, torch, args):
     n = args.serve_requests
     budget = 64 << 30
 
-    def once(reqs, per_op=False):
+    def once(reqs, form="persistent"):
         v.heap_view()[:, region + 288 * MiB:region + 384 * MiB].zero_()
         torch.cuda.synchronize()
-        if per_op:
+        if form == "per_op":
             dst, lat, comps, stats = v.serve_run_per_op(reqs, 8, region, 384 * MiB, budget, chunk_bytes=PER_OP_CHUNK)
+            torch.cuda.synchronize()
+            return lat, comps, stats
+        if form in ("batched_fused", "batched_graph"):
+            dst, lat, comps, stats = v.serve_run_batched(reqs, 8, region, 384 * MiB, budget, window_us=WINDOW_US,
+                                                         use_graph=form == "batched_graph",
+                                                         chunk_bytes=PROGRESS_CHUNK, wg_size=PROGRESS_WG)
             torch.cuda.synchronize()
             return lat, comps, stats
         v.progress_start(nwg=0, wg_size=args.serve_wg, ring_slots=4096, chunk_bytes=args.serve_chunk_kib << 10,
@@ -529,17 +590,19 @@ def run_serve(v, torch, args):
     lat, comps, stats = once(burst)
     b_sat = payload / stats.wall_s
     mean_size = payload / n
+    forms = ("persistent", "batched_graph", "batched_fused", "per_op")
     out = {"mode": "serve", "npes": npes, "heap_bytes_per_pe": heap, "budget_bytes": budget, "requests": n,
-           "persistent": {"saturated": summary(burst, lat, stats)}, "per_op": {}}
-    lat, comps, stats = once(burst, per_op=True)
-    out["per_op"]["saturated"] = summary(burst, lat, stats)
-    log(json.dumps({"saturated": out["persistent"]["saturated"], "per_op": out["per_op"]["saturated"]}))
+           "batch_window_us": WINDOW_US, "persistent": {"saturated": summary(burst, lat, stats)}}
+    for form in forms[1:]:
+        lat, comps, stats = once(burst, form)
+        out[form] = {"saturated": summary(burst, lat, stats)}
+    log(json.dumps({f: out[f]["saturated"] for f in forms}))
     warm = n // 20
     for rho in (0.5, 0.8):
         lam = rho * b_sat / mean_size
         reqs = serve_trace(v, npes, n, lam, 128 * MiB, W.SEED_SERVE)
-        for form in ("persistent", "per_op"):
-            lat, comps, stats = once(reqs, per_op=form == "per_op")
+        for form in forms:
+            lat, comps, stats = once(reqs, form)
             out[form][f"rho_{rho}"] = dict(offered_GB_s=round(rho * b_sat / 1e9, 2), **summary(reqs, lat, stats, warm))
             log(json.dumps({form: {f"rho_{rho}": out[form][f"rho_{rho}"]}}))
     v.finalize()
@@ -717,6 +780,18 @@ def main():
         "roofline": roof,
         "device_errors": errs,
     }
+    if not want:
+        log("ceilings")
+        ceil = measure_ceilings(v, torch, L, npes)
+        rec["ceilings"] = ceil
+        for name, r in out_rows.items():
+            if "hbm_frac" in r and r["GB_s"] > 1000:
+                r["frac_of_copy_ceiling"] = round(r["GB_s"] / ceil["copy_GB_s"], 4)
+        if "gups_fetch_xor_add" in out_rows:
+            g = out_rows["gups_fetch_xor_add"]["Mops_s"] / 1e3
+            out_rows["gups_fetch_xor_add"]["frac_of_atomic_ceiling_1GiB"] = round(
+                g / ceil["atomics_G_updates_s"]["table_1GiB"], 4)
+        rec["errors_after_ceilings"] = v.device_errors()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
@@ -724,7 +799,7 @@ def main():
         n = args.probe_copy_mib * MiB
         a = torch.empty(n, dtype=torch.uint8, device="cuda")
         b = torch.empty(n, dtype=torch.uint8, device="cuda")
-        v.probe_copy(b, a, n, nwg=4096, wg_size=256)
+        v.probe_copy(b, a, n)
         torch.cuda.synchronize()
         rec["probe_copy_bytes"] = n
     line = json.dumps(rec)

@@ -551,6 +551,21 @@ int shmemx_serve_run_per_op(const shmemx_request_t *reqs, size_t n, int lanes, u
                             uint64_t *dst_off_out, uint64_t *latency_ns, shmemx_completion_t *completions,
                             shmemx_serve_stats_t *stats);
 
+/* Windowed batch serving forms on the same trace, admission and accounting
+ * as shmemx_serve_run: a dispatcher thread gathers the requests submitted
+ * while the oldest one waits window_ns (or up to 4096 of them), and launches
+ * them as one batch: a kernel stages the batch from pinned host memory to
+ * device memory, and a second, with one work-group of wg_size threads per CU,
+ * executes every chunk of chunk_bytes of every request.  use_graph = 0
+ * launches the two kernels directly (fused form); 1 replays a graph captured
+ * once for each of the 4 batch slots (graph form).  Up to 4 batches are in
+ * flight; a request completes with its batch.  The progress kernel must not
+ * be running.  completions[i] carries only ticket = i. */
+int shmemx_serve_run_batched(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
+                             uint64_t region_bytes, uint64_t budget_bytes, uint64_t window_ns, int use_graph,
+                             uint64_t chunk_bytes, int wg_size, uint64_t *dst_off_out, uint64_t *latency_ns,
+                             shmemx_completion_t *completions, shmemx_serve_stats_t *stats);
+
 /* One serving request (PUT, GET, or AMO_FETCH_ADD over nbytes/8 counters with
  * results to the issuer's dst) executed by a launch of its own: work-group
  * b moves bytes [b*chunk_bytes, (b+1)*chunk_bytes).  Asynchronous on stream. */
@@ -567,7 +582,10 @@ int shmemx_fill_random(void *dst, uint64_t nbytes, uint64_t seed, uint64_t word_
  * aligned to the element size. */
 int shmemx_fill_typed(void *dst, uint64_t count, int dtype, uint64_t seed, uint64_t index0, void *stream);
 /* Plain device-to-device copy kernel of nbytes (16-byte aligned) used as
- * the achievable-bandwidth probe and as the counter-scaling reference. */
+ * the achievable-bandwidth probe and as the counter-scaling reference:
+ * nwg work-groups of wg_size threads stream 16 MiB chunks (dealt round
+ * robin) with nontemporal 16-byte loads and stores, 8 in flight per lane
+ * (256 x 1024 was the fastest shape measured on MI355X). */
 int shmemx_probe_copy(void *dst, const void *src, uint64_t nbytes, int nwg, int wg_size, void *stream);
 /* Agent-scope int64 fetch_add to random words of a DEVICE table of nwords
  * (a power of two): atomic-throughput probe. */

@@ -281,7 +281,7 @@ def fill_typed(dst, count: int, dtype: int, seed: int, index0: int = 0, stream=N
     _check(lib.shmemx_fill_typed(_ptr(dst), count, dtype, seed, index0, _stream(stream)), "shmemx_fill_typed")
 
 
-def probe_copy(dst, src, nbytes: int, nwg: int = 4096, wg_size: int = 256, stream=None) -> None:
+def probe_copy(dst, src, nbytes: int, nwg: int = 256, wg_size: int = 1024, stream=None) -> None:
     _check(lib.shmemx_probe_copy(_ptr(dst), _ptr(src), nbytes, nwg, wg_size, _stream(stream)), "shmemx_probe_copy")
 
 
@@ -420,6 +420,23 @@ def serve_run_per_op(reqs: Sequence[Request], lanes: int, region_off: int, regio
     _check(lib.shmemx_serve_run_per_op(arr, n, lanes, region_off, region_bytes, budget_bytes, chunk_bytes, wg_size,
                                        dst.ctypes.data, lat.ctypes.data, comps, C.byref(stats)),
            "shmemx_serve_run_per_op")
+    return dst, lat, comps, stats
+
+
+def serve_run_batched(reqs: Sequence[Request], lanes: int, region_off: int, region_bytes: int, budget_bytes: int,
+                      window_us: float = 20.0, use_graph: bool = False, chunk_bytes: int = 256 << 10,
+                      wg_size: int = 1024):
+    """The same trace and admission as serve_run, in windowed batches (fused
+    launches, or graph replays with use_graph)."""
+    n = len(reqs)
+    arr = (Request * n)(*reqs)
+    dst = np.zeros(n, dtype=np.uint64)
+    lat = np.zeros(n, dtype=np.uint64)
+    comps = (Completion * n)()
+    stats = ServeStats()
+    _check(lib.shmemx_serve_run_batched(arr, n, lanes, region_off, region_bytes, budget_bytes, int(window_us * 1000),
+                                        1 if use_graph else 0, chunk_bytes, wg_size, dst.ctypes.data, lat.ctypes.data,
+                                        comps, C.byref(stats)), "shmemx_serve_run_batched")
     return dst, lat, comps, stats
 
 

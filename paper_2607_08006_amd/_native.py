@@ -118,6 +118,8 @@ SIGNATURES = {
     "shmemx_serve_run_per_op": (i32, [P(Request), sz, i32, u64, u64, u64, u64, i32, vp, vp, P(Completion),
                                        P(ServeStats)]),
     "shmemx_launch_request": (i32, [P(Desc), u64, i32, vp]),
+    "shmemx_serve_run_batched": (i32, [P(Request), sz, i32, u64, u64, u64, u64, i32, u64, i32, vp, vp,
+                                        P(Completion), P(ServeStats)]),
     "shmemx_fill_random": (i32, [vp, u64, u64, u64, vp]),
     "shmemx_fill_typed": (i32, [vp, u64, i32, u64, u64, vp]),
     "shmemx_probe_copy": (i32, [vp, vp, u64, i32, i32, vp]),

@@ -21,7 +21,7 @@
 #include <cstring>
 #include <thread>
 
-#include "runtime.hpp"
+#include "serving.hpp"
 
 using namespace vshmem;
 
@@ -133,26 +133,11 @@ __device__ uint64_t hash_range(const uint8_t *out, uint64_t lo, uint64_t hi, uin
     return h;
 }
 
-__device__ __forceinline__ uint8_t *pe_base(const shmemx_dctx_pub_t &c, int pe) { return c.base + (uint64_t)pe * c.stride; }
 
 // Execute bytes [lo, hi) of a request with all threads of the work-group.
 __device__ void exec_item(const ProgArgs &a, const shmemx_desc_t &d, uint64_t lo, uint64_t hi, uint64_t *hash_acc)
 {
-    const shmemx_dctx_pub_t &c = a.c;
-    uint8_t *out;
-    if (d.op == SHMEMX_OP_AMO_FETCH_ADD) {
-        uint64_t *ctr = (uint64_t *)(pe_base(c, d.target_pe) + d.src);
-        uint64_t *res = (uint64_t *)(pe_base(c, d.issuer_pe) + d.dst);
-        for (uint64_t k = lo / 8 + threadIdx.x; k < hi / 8; k += blockDim.x)
-            res[k] = __hip_atomic_fetch_add(ctr + k, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        out = (uint8_t *)res;
-    } else {
-        const bool get = d.op == SHMEMX_OP_GET;
-        const int spe = get ? d.target_pe : d.issuer_pe;
-        const int dpe = get ? d.issuer_pe : d.target_pe;
-        out = pe_base(c, dpe) + d.dst;
-        vshmem_detail::copy_bytes<8, true>(out + lo, pe_base(c, spe) + d.src + lo, hi - lo, threadIdx.x, blockDim.x);
-    }
+    uint8_t *out = exec_request_range(a.c, d, lo, hi, threadIdx.x, blockDim.x);
     if (a.verify) {
         // Every thread's stores complete before any thread reads the output.
         vshmem_detail::release_agent();
@@ -468,23 +453,13 @@ __global__ void __launch_bounds__(1024) k_request(shmemx_dctx_pub_t c, shmemx_de
 {
     const uint64_t lo = (uint64_t)blockIdx.x * chunk;
     const uint64_t hi = min(d.nbytes, lo + chunk);
-    if (lo < hi) {
-        if (d.op == SHMEMX_OP_AMO_FETCH_ADD) {
-            uint64_t *ctr = (uint64_t *)(pe_base(c, d.target_pe) + d.src);
-            uint64_t *res = (uint64_t *)(pe_base(c, d.issuer_pe) + d.dst);
-            for (uint64_t k = lo / 8 + threadIdx.x; k < hi / 8; k += blockDim.x)
-                res[k] = __hip_atomic_fetch_add(ctr + k, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const bool get = d.op == SHMEMX_OP_GET;
-            const int spe = get ? d.target_pe : d.issuer_pe;
-            const int dpe = get ? d.issuer_pe : d.target_pe;
-            vshmem_detail::copy_bytes<8, true>(pe_base(c, dpe) + d.dst + lo, pe_base(c, spe) + d.src + lo, hi - lo,
-                                               threadIdx.x, blockDim.x);
-        }
-    }
+    if (lo < hi) exec_request_range(c, d, lo, hi, threadIdx.x, blockDim.x);
     vshmem_detail::release_wg_at_exit();   // quiet
 }
 
+}  // namespace
+
+namespace vshmem {
 bool valid_request_host(const shmemx_desc_t &d)
 {
     const State &s = st();
@@ -495,6 +470,9 @@ bool valid_request_host(const shmemx_desc_t &d)
                in_user_heap(d.dst, d.nbytes);
     return false;
 }
+}  // namespace vshmem
+
+namespace {
 
 // ------------------------------------------------------------------ host
 struct Progress {

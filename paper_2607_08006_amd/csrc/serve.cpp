@@ -10,7 +10,7 @@
 #include <thread>
 #include <vector>
 
-#include "runtime.hpp"
+#include "serving.hpp"
 
 using namespace vshmem;
 using Clock = std::chrono::steady_clock;
@@ -136,6 +136,127 @@ struct PerOpBackend final : Backend {
         {
             std::lock_guard<std::mutex> lk(mu);
             pool.push_back(by_request[ticket]);
+        }
+        *out = shmemx_completion_t{};
+        out->ticket = ticket;
+        return 1;
+    }
+};
+
+// Windowed batches: submit() queues the request; a dispatcher thread takes
+// everything queued once the oldest request has waited `window` (or a full
+// batch is queued) and launches it as one batch from a free slot (the slot's
+// previous batch must have completed).  A request completes when its
+// batch's event does.
+struct WindowBackend final : Backend {
+    WindowBatcher *wb = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<std::pair<shmemx_desc_t, size_t>> pending;
+    Clock::time_point oldest;
+    std::vector<std::atomic<int64_t>> batch_of;   // request -> batch, -1 before launch
+    std::vector<hipEvent_t> batch_done;           // batch -> event (grows; guarded by events_mu)
+    std::mutex events_mu;
+    std::chrono::nanoseconds window;
+    std::atomic<bool> stop{false};
+    std::atomic<int> error{0};
+    std::thread dispatcher;
+    size_t batches = 0;
+
+    WindowBackend(size_t n, uint64_t window_ns) : batch_of(n), window(window_ns)
+    {
+        for (auto &b : batch_of) b.store(-1);
+    }
+    int init(bool graph, uint64_t chunk, int nwg, int wg, hipStream_t stream)
+    {
+        int rc = SHMEMX_OK;
+        wb = window_batcher_create(graph, chunk, nwg, wg, stream, &rc);
+        if (rc) return rc;
+        dispatcher = std::thread([this] { run(); });
+        return SHMEMX_OK;
+    }
+    ~WindowBackend() override
+    {
+        stop.store(true);
+        cv.notify_all();
+        if (dispatcher.joinable()) dispatcher.join();
+        window_batcher_destroy(wb);
+        for (hipEvent_t e : batch_done) (void)hipEventDestroy(e);
+    }
+    void run()
+    {
+        std::vector<shmemx_desc_t> d;
+        std::vector<size_t> idx;
+        hipEvent_t slot_event[kWindowSlots] = {};
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stop.load() || !pending.empty(); });
+                if (pending.empty()) return;   // stopped
+                // Wait out the window of the oldest request unless a batch is full.
+                while (!stop.load() && pending.size() < kWindowBatchMax && Clock::now() < oldest + window)
+                    cv.wait_until(lk, oldest + window);
+                const size_t take = std::min(pending.size(), kWindowBatchMax);
+                d.clear();
+                idx.clear();
+                for (size_t i = 0; i < take; ++i) {
+                    d.push_back(pending[i].first);
+                    idx.push_back(pending[i].second);
+                }
+                pending.erase(pending.begin(), pending.begin() + (ptrdiff_t)take);
+                if (!pending.empty()) oldest = Clock::now();
+            }
+            const int slot = (int)(batches % kWindowSlots);
+            if (slot_event[slot] && VSHMEM_HIP_FAILED(hipEventSynchronize(slot_event[slot]))) {
+                error.store(SHMEMX_ERR_HIP);
+                return;
+            }
+            hipEvent_t e = nullptr;
+            if (VSHMEM_HIP_FAILED(hipEventCreateWithFlags(&e, hipEventDisableTiming))) {
+                error.store(SHMEMX_ERR_HIP);
+                return;
+            }
+            if (int rc = window_batcher_launch(wb, slot, d.data(), d.size(), e)) {
+                (void)hipEventDestroy(e);
+                error.store(rc);
+                return;
+            }
+            slot_event[slot] = e;
+            {
+                std::lock_guard<std::mutex> lk(events_mu);
+                batch_done.push_back(e);
+            }
+            for (size_t i : idx) batch_of[i].store((int64_t)batches, std::memory_order_release);
+            ++batches;
+        }
+    }
+    int submit(const shmemx_desc_t &d, size_t index, int, uint64_t *ticket) override
+    {
+        if (int rc = error.load()) return rc;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (pending.empty()) oldest = Clock::now();
+            pending.emplace_back(d, index);
+        }
+        cv.notify_all();
+        *ticket = index;
+        return SHMEMX_OK;
+    }
+    int poll(uint64_t ticket, shmemx_completion_t *out) override
+    {
+        if (int rc = error.load()) return rc;
+        const int64_t b = batch_of[ticket].load(std::memory_order_acquire);
+        if (b < 0) return 0;
+        hipEvent_t e;
+        {
+            std::lock_guard<std::mutex> lk(events_mu);
+            e = batch_done[(size_t)b];
+        }
+        const hipError_t q = hipEventQuery(e);
+        if (q == hipErrorNotReady) return 0;
+        if (q != hipSuccess) {
+            set_hip_error(q, "serve windowed: hipEventQuery");
+            return SHMEMX_ERR_HIP;
         }
         *out = shmemx_completion_t{};
         out->ticket = ticket;
@@ -347,4 +468,29 @@ extern "C" int shmemx_serve_run_per_op(const shmemx_request_t *reqs, size_t n, i
     if (int rc = be.init(lanes)) return rc;
     return serve_common(be, reqs, n, lanes, region_off, region_bytes, budget_bytes, dst_off_out, latency_ns,
                         completions, stats);
+}
+
+extern "C" int shmemx_serve_run_batched(const shmemx_request_t *reqs, size_t n, int lanes, uint64_t region_off,
+                                        uint64_t region_bytes, uint64_t budget_bytes, uint64_t window_ns, int use_graph,
+                                        uint64_t chunk_bytes, int wg_size, uint64_t *dst_off_out, uint64_t *latency_ns,
+                                        shmemx_completion_t *completions, shmemx_serve_stats_t *stats)
+{
+    if (int rc = check_ready()) return rc;
+    if (progress_running()) return SHMEMX_ERR_STATE;
+    if (lanes < 1 || lanes > 64 || chunk_bytes == 0 || (chunk_bytes & 15) || !valid_wg_size(wg_size) ||
+        window_ns > 1000000000ull)
+        return SHMEMX_ERR_ARG;
+    hipStream_t stream = nullptr;
+    if (VSHMEM_HIP_FAILED(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking))) return SHMEMX_ERR_HIP;
+    int rc;
+    {
+        WindowBackend be(n, window_ns);
+        rc = be.init(use_graph != 0, chunk_bytes, st().num_cus, wg_size, stream);
+        if (!rc)
+            rc = serve_common(be, reqs, n, lanes, region_off, region_bytes, budget_bytes, dst_off_out, latency_ns,
+                              completions, stats);
+    }
+    (void)hipStreamSynchronize(stream);
+    (void)hipStreamDestroy(stream);
+    return rc;
 }

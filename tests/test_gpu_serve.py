@@ -222,7 +222,13 @@ def test_launch_request_matches_oracle():
         assert_no_device_errors()
 
 
-def test_serving_per_op_final_state_and_budget():
+@pytest.mark.parametrize("form", ["per_op", "batched_fused", "batched_graph"])
+def test_serving_other_forms_final_state_and_budget(form):
+    """The per-op and windowed-batch forms on a trace: every request completes
+    once, the budget holds, and the final heap equals replaying the requests
+    in completion order (a destination is reused only after its request
+    completed, so the last writer of each byte is the one that finished
+    last)."""
     npes, n = 16, 300
     src_bytes = 2 << 20
     with heap(npes, 40 << 20) as v:
@@ -235,14 +241,18 @@ def test_serving_per_op_final_state_and_budget():
         h[:, region_off:region_off + region_bytes].zero_()
         t.cuda.synchronize()
         budget = 3 << 20
-        dst, lat, comps, stats = v.serve_run_per_op(reqs, 8, region_off, region_bytes, budget,
-                                                    chunk_bytes=64 << 10, wg_size=256)
+        if form == "per_op":
+            dst, lat, comps, stats = v.serve_run_per_op(reqs, 8, region_off, region_bytes, budget,
+                                                        chunk_bytes=64 << 10, wg_size=256)
+        else:
+            dst, lat, comps, stats = v.serve_run_batched(reqs, 8, region_off, region_bytes, budget, window_us=30.0,
+                                                         use_graph=form == "batched_graph", chunk_bytes=64 << 10,
+                                                         wg_size=256)
         t.cuda.synchronize()
         assert stats.max_reserved_bytes <= budget
         assert sorted(c.ticket for c in comps) == list(range(n))
         assert (lat > 0).all()
         got = download(region_off + region_bytes)
-        # replay destinations in completion order: the last writer of each byte wins
         want = np.zeros_like(got)
         written = np.zeros(got.shape, dtype=bool)
         done_at = np.array([r.arrival_s * 1e9 for r in reqs]) + lat.astype(np.float64)
