@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-wg", type=int, default=PROGRESS_WG, help="progress kernel work-group size")
     ap.add_argument("--serve-chunk-kib", type=int, default=PROGRESS_CHUNK >> 10, help="progress kernel chunk size")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="instead of the step: only the small-program and 256-PE ping-pong sections")
     ap.add_argument("--summarize-profiles", default="", metavar="DIR",
                     help="no GPU work: write profiles/ summaries from rocprofv3 CSV output under DIR")
     return ap.parse_args()
@@ -436,6 +438,91 @@ def measure_ceilings(v, torch, L: Layout, npes: int):
     return out
 
 
+def run_config_sections(v, torch):
+    """Measurements at the small configurations' own shapes, each on a heap
+    of its own: the 4-PE x 1 MiB mixed program (1000 put/get of 8 B - 4 KiB
+    and 10^4 fetch_add on 64 counters) at each scope and with the autotuned
+    table, in per-op, fused and graph forms; and signal ping-pong with 128
+    pairs of 256 PEs."""
+    out = {}
+    hz = v.wallclock_hz()
+    # ---- small mixed program
+    v.init(4, 4 * MiB)
+    wl = W.small_workload(W.SEED_SMALL)
+    res = torch.zeros(wl.n_amo, dtype=torch.int64, device="cuda")
+    ops = wl.descs["op"]
+    is_op = (ops == W.OP_PUT) | (ops == W.OP_GET) | (ops == W.OP_AMO_FETCH_ADD)
+    n_amo = int((ops == W.OP_AMO_FETCH_ADD).sum())
+    tune_auto = v.autotune(v.offset(v.malloc(3 * MiB)) + MiB, 2 * MiB, 8, 4096, msgs=1024, reps=5)
+    stamps = torch.zeros(len(wl.descs), dtype=torch.int64, device="cuda")
+    t0 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    small = {}
+    for label, scope in (("thread", v.SCOPE_THREAD), ("wave", v.SCOPE_WAVE), ("wg", v.SCOPE_WG),
+                         ("default_table", "default"), ("autotuned", None)):
+        if scope is None:
+            tune = tune_auto
+        elif scope == "default":
+            tune = v.default_tune()
+        else:
+            tune = v.default_tune()
+            for c in range(len(tune.scope)):
+                tune.scope[c] = scope
+        plan = v.Plan(wl.descs, tune)
+        graph = v.Plan(wl.descs, tune)
+        graph.set_stamps(stamps)
+        graph.graph_build(1, results=res)
+        forms = {}
+        for form in ("per_op", "fused", "graph"):
+            lat_all, bursts = [], []
+            for rep in range(6):
+                upload = torch.from_numpy(wl.init).cuda()
+                v.heap_view()[:, :wl.heap_bytes].copy_(upload)
+                stamps.zero_()
+                torch.cuda.synchronize()
+                v.stamp(t0)
+                if form == "graph":
+                    graph.graph_launch()
+                else:
+                    plan.set_stamps(stamps)
+                    (plan.launch_fused if form == "fused" else plan.launch_per_op)(results=res)
+                torch.cuda.synchronize()
+                if rep == 0:
+                    continue
+                st_ = stamps.cpu().numpy()[is_op]
+                lat = (st_ - int(t0.cpu().numpy()[0])) / hz * 1e6
+                lat_all.append(lat)
+                bursts.append(float(lat.max()))
+            lat = np.concatenate(lat_all)
+            burst = float(np.median(bursts))
+            forms[form] = {"p50_us": round(percentile(lat, 50), 2), "p99_us": round(percentile(lat, 99), 2),
+                           "burst_us": round(burst, 2), "ops_s": round(int(is_op.sum()) / (burst * 1e-6), 0),
+                           "amo_Mops_s": round(n_amo / (burst * 1e-6) / 1e6, 2)}
+        plan.destroy()
+        graph.destroy()
+        small[label] = forms
+    out["small_program_4pe"] = {"ops": int(is_op.sum()), "fetch_add": n_amo, "heap": "4 PEs x 1 MiB",
+                                "autotuned_scopes_log2_3_to_12": [int(tune_auto.scope[c]) for c in range(3, 13)],
+                                "autotuned_wg_size": int(tune_auto.wg_size), **small}
+    v.finalize()
+    # ---- ping-pong, 128 pairs of 256 PEs
+    v.init(256, 4 * MiB)
+    base = v.offset(v.malloc(4096))
+    pairs = torch.arange(256, dtype=torch.int32, device="cuda")
+    pp = {}
+    for tag, np_, same, rounds in (("one_pair_cross_xcd", 1, False, 100000), ("one_pair_same_xcd", 1, True, 100000),
+                                   ("128_pairs_cross_xcd", 128, False, 20000), ("128_pairs_same_xcd", 128, True, 20000)):
+        rtt = torch.zeros(np_ * rounds, dtype=torch.int64, device="cuda")
+        v.pingpong(base, base + 64, pairs, np_, rounds, 8, same, rtt)
+        torch.cuda.synchronize()
+        ns = rtt.cpu().numpy().astype(np.float64) / hz * 1e9 / 2
+        pp[tag] = {"rounds": rounds, "one_way_p50_ns": round(percentile(ns, 50), 1),
+                   "one_way_p99_ns": round(percentile(ns, 99), 1)}
+    out["pingpong_256pe"] = pp
+    out["device_errors"] = v.device_errors()
+    v.finalize()
+    return out
+
+
 def cpu_baseline(seconds: float):
     """Time the CPU oracle (single thread, as written) on bounded samples of
     the step's rows and report algorithmic GB/s."""
@@ -624,8 +711,11 @@ def main():
     import paper_2607_08006_amd as v
 
     torch.cuda.set_device(0)
-    if args.sweep or args.serve:
-        rec = run_sweep(v, torch, args) if args.sweep else run_serve(v, torch, args)
+    if args.sweep or args.serve or args.configs_only:
+        if args.configs_only:
+            rec = {"mode": "configs", "configs": run_config_sections(v, torch)}
+        else:
+            rec = run_sweep(v, torch, args) if args.sweep else run_serve(v, torch, args)
         line = json.dumps(rec)
         print(line, flush=True)
         if args.out:
@@ -802,12 +892,15 @@ def main():
         v.probe_copy(b, a, n)
         torch.cuda.synchronize()
         rec["probe_copy_bytes"] = n
+    v.finalize()
+    if not want:
+        log("configuration sections")
+        rec["configs"] = run_config_sections(v, torch)
     line = json.dumps(rec)
     print(line, flush=True)
     if args.out:
         with open(args.out, "w") as f:
             f.write(line + "\n")
-    v.finalize()
 
 
 if __name__ == "__main__":

@@ -297,9 +297,11 @@ void shmemx_tune_default(shmemx_tune_t *t)
     t->wg_size = 256;
     t->grid_wgs = 0;
     for (int c = 0; c < SHMEMX_TUNE_CLASSES; ++c) {
-        // below 1 KiB one lane per message; up to 16 KiB a wavefront; above, a
-        // work-group, with messages past 1 MiB split into 256 KiB tasks.
-        t->scope[c] = c < 10 ? SHMEMX_SCOPE_THREAD : (c < 14 ? SHMEMX_SCOPE_WAVE : SHMEMX_SCOPE_WG);
+        // below 64 B one lane per message; up to 16 KiB a wavefront; above, a
+        // work-group, with messages past 1 MiB split into 256 KiB tasks.  (On
+        // the 4-PE mixed program of 8 B - 4 KiB messages, wavefront scope
+        // finished the burst 6x sooner than one lane per message.)
+        t->scope[c] = c < 6 ? SHMEMX_SCOPE_THREAD : (c < 14 ? SHMEMX_SCOPE_WAVE : SHMEMX_SCOPE_WG);
         t->chunk[c] = c >= 20 ? (256ull << 10) : 0;
     }
 }
