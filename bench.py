@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--heap-mib", type=int, default=1024)
     ap.add_argument("--rows", default="", help="comma-separated subset of rows (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the ceilings and the configuration sections (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="also run one plain copy of this size (counter scaling reference)")
@@ -174,7 +176,7 @@ def build_rows(v, torch, L: Layout, npes: int, want):
     # ---- collectives (a7-a10)
     blk = int(1 * MiB * min(1.0, scale))
     add("alltoall_1MiB_fp32", lambda: v.alltoallmem(L.addr(L.B), L.addr(L.C), blk), 2 * npes * npes * blk,
-        kernel="k_alltoall<true,4>")
+        kernel="k_alltoall<true,8>")
     fc = int(4 * MiB * min(1.0, scale))
     add("fcollect_4MiB", lambda: v.fcollectmem(L.addr(L.B), L.addr(L.C), fc), npes * fc + npes * npes * fc)
     bc = L.D - L.C
@@ -338,7 +340,7 @@ def summarize_profiles(prof_dir: str, probe_mib: int) -> None:
     WRITE_SIZE passes in `<prof_dir>/pmc_<counter>`, each counter scaled by
     what it reads for the plain copy probe of probe_mib MiB in, probe_mib out."""
     trace_cmd = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o bench --output-format csv "
-                 "-- python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline")
+                 "-- python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras")
     pmc_cmd = ("rocprofv3 --pmc {ctr} -d gpurun_out/prof/pmc_{ctr} -o pmc --output-format csv -- python3 bench.py "
                "--rows put_wg_16MiB_ring,get_wg_16MiB_perm,alltoall_1MiB_fp32 --steps 2 --warmup 1 "
                f"--no-cpu-baseline --probe-copy-mib {probe_mib}")
@@ -870,7 +872,7 @@ def main():
         "roofline": roof,
         "device_errors": errs,
     }
-    if not want:
+    if not want and not args.no_extras:
         log("ceilings")
         ceil = measure_ceilings(v, torch, L, npes)
         rec["ceilings"] = ceil
@@ -893,7 +895,7 @@ def main():
         torch.cuda.synchronize()
         rec["probe_copy_bytes"] = n
     v.finalize()
-    if not want:
+    if not want and not args.no_extras:
         log("configuration sections")
         rec["configs"] = run_config_sections(v, torch)
     line = json.dumps(rec)

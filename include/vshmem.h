@@ -378,8 +378,8 @@ int shmemx_barrier_launch(shmem_team_t team, int iters, uint64_t tokens_off, uin
  * SHMEMX_ERR_ARG if team size * wgs_per_pe work-groups cannot be.
  * launch may be NULL; zero fields take the defaults: wgs_per_pe about one
  * work-group per CU in total, work-groups of 1024 threads (256 for the
- * reductions, which accept at most 256), chunk 256 KiB (alltoall 1 MiB,
- * reductions 16 KiB), nontemporal copies for alltoall and the reductions.
+ * reductions, which accept at most 256), chunk 256 KiB (reductions 16 KiB),
+ * nontemporal copies for alltoall (8 deep) and the reductions.
  */
 #define SHMEMX_DT_INT64 0
 #define SHMEMX_DT_FP32 1

@@ -437,8 +437,8 @@ int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, si
     int tsize = shmem_team_n_pes(team);
     int rc = tsize <= 0 ? SHMEMX_ERR_ARG : SHMEMX_OK;
     if (!rc)
-        rc = make_geo(team, dest, src, (uint64_t)n * tsize, (uint64_t)n * tsize, launch, 256, g, L, 1ull << 20,
-                      SHMEMX_LAUNCH_NONTEMPORAL);
+        rc = make_geo(team, dest, src, (uint64_t)n * tsize, (uint64_t)n * tsize, launch, 1024, g, L, 256ull << 10,
+                      SHMEMX_LAUNCH_NONTEMPORAL | SHMEMX_LAUNCH_DEEP);
     if (!rc && overlap(g.dst_off, (uint64_t)n * tsize, g.src_off, (uint64_t)n * tsize)) rc = SHMEMX_ERR_ARG;
     if (rc) {
         set_last_error(rc);
