@@ -592,6 +592,20 @@ def timed_ms(torch, fn, reps):
     return float(np.median(ts))
 
 
+def sweep_launch(v, scope, size):
+    """Launch shape per scope from the measured shape sweeps: about one
+    work-group per CU; nontemporal copies from 4 KiB (wave) or 64 KiB (work-
+    group, grid) up, 8 deep for work-group and grid scope."""
+    nt, deep = v.LAUNCH_NONTEMPORAL, v.LAUNCH_DEEP
+    if scope == v.SCOPE_THREAD:
+        return v.launch_cfg(wgs_per_pe=4, wg_size=512)
+    if scope == v.SCOPE_WAVE:
+        return v.launch_cfg(wgs_per_pe=4, wg_size=256, flags=nt if size >= 4096 else 0)
+    if scope == v.SCOPE_WG:
+        return v.launch_cfg(wgs_per_pe=4, wg_size=1024, flags=(nt | deep) if size >= 65536 else 0)
+    return v.launch_cfg(wgs_per_pe=4, wg_size=256, flags=nt | deep)
+
+
 def run_sweep(v, torch, args):
     """The put/get bandwidth sweep: 8 B - 64 MiB, thread/wavefront/work-group
     (and grid for >= 1 MiB) scopes, ring and derangement, put and get; each
@@ -610,8 +624,7 @@ def run_sweep(v, torch, args):
         k = W.msgs_per_pe(size)
         scopes = [v.SCOPE_THREAD, v.SCOPE_WAVE, v.SCOPE_WG] + ([v.SCOPE_GRID] if size >= MiB else [])
         for scope in scopes:
-            wgs, wg = (4, 256) if scope == v.SCOPE_THREAD else (16, 512)
-            lc = v.launch_cfg(wgs_per_pe=wgs, wg_size=wg, flags=v.LAUNCH_NONTEMPORAL if size >= 65536 else 0)
+            lc = sweep_launch(v, scope, size)
             for pat in ("ring", "perm"):
                 for op in (v.OP_PUT, v.OP_GET):
                     ms = timed_ms(torch, lambda: v.rma_pattern(op, scope, tg[pat], A, B, size, k, launch=lc),
