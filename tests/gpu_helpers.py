@@ -52,3 +52,23 @@ def device_array(a: np.ndarray):
 
 def assert_no_device_errors():
     assert vs().device_errors() == 0
+
+
+GOLD = 0x9E3779B97F4A7C15
+
+
+def out_hash(b: np.ndarray) -> int:
+    """Output hash of the progress kernel's completion records: XOR over the
+    8-byte words w_i (zero padded) of mix(w_i ^ ((i + 1) * golden))."""
+    n = len(b)
+    pad = np.zeros(((n + 7) // 8) * 8, dtype=np.uint8)
+    pad[:n] = b
+    w = pad.view("<u8")
+    idx = np.arange(1, len(w) + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = w ^ (idx * np.uint64(GOLD))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return int(np.bitwise_xor.reduce(z)) if len(z) else 0
+

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workload as W
-from tests.gpu_helpers import assert_no_device_errors, heap, torch
+from tests.gpu_helpers import assert_no_device_errors, heap, out_hash, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -173,3 +173,55 @@ def test_collectives_64pes_full_size_sampled():
                     got = np.array([row[int(k) * es:(int(k) + 1) * es].view(want.dtype)[0] for k in ks])
                     assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), (dt, rop, p)
         assert_no_device_errors()
+
+
+def test_serving_128pes_full_size_sampled_hashes():
+    """Serving at full size: 128 PEs x 512 MiB, 4000 requests log-uniform
+    64 B - 16 MiB over put/get/fetch_add, a 64 GiB budget, the progress
+    kernel in the launch shape bench.py times.  Every request completes once
+    with status 0; the device's output hash of sampled requests equals the
+    hash of the bytes the seeded generator put at their sources (or of the
+    zero fetched values of fresh counters)."""
+    npes = 128
+    with heap(npes, 512 * MiB) as v:
+        t = torch()
+        src = v.offset(v.malloc(128 * MiB))
+        region = v.offset(v.malloc(384 * MiB))
+        base, stride = v.heap_base(), v.heap_stride()
+        seed_of = lambda p: W.subseed(W.SEED_SERVE, W.TAG_HEAP + p)  # noqa: E731
+        for p in range(npes):
+            v.fill_random(base + p * stride + src, 128 * MiB, seed_of(p))
+        v.heap_view()[:, region + 288 * MiB:region + 384 * MiB].zero_()
+        t.cuda.synchronize()
+        from paper_2607_08006_amd import Request
+        n = 4000
+        xs = W.splitmix64(W.subseed(W.SEED_SERVE, 0x77), 0, n)
+        reqs = []
+        for i, r in enumerate(W.serve_requests(W.SEED_SERVE, n, npes, rate_per_s=1e12, lanes=8)):
+            nb = r.nbytes
+            s0 = 0 if r.kind == W.OP_AMO_FETCH_ADD else int(xs[i] % np.uint64(128 * MiB - nb + 1))
+            reqs.append(Request(r.kind, r.issuer, r.target, r.lane, nb, s0, r.arrival_s))
+        side = t.cuda.Stream()
+        v.progress_start(nwg=0, wg_size=1024, ring_slots=4096, verify=True, chunk_bytes=256 << 10, stream=side)
+        try:
+            dst, lat, comps, stats = v.serve_run(reqs, 8, region, 384 * MiB, 64 << 30)
+        finally:
+            v.progress_stop(60000)
+            side.synchronize()
+        assert stats.max_reserved_bytes <= 64 << 30
+        assert all(c.status == 0 for c in comps)
+        assert len(set(c.ticket for c in comps)) == n
+        small = [i for i, r in enumerate(reqs) if r.nbytes <= 256 << 10]
+        large = [i for i, r in enumerate(reqs) if r.nbytes > 8 << 20]
+        pick = small[::max(1, len(small) // 300)] + large[:6]
+        assert len(pick) > 200
+        for i in pick:
+            r = reqs[i]
+            if r.op == W.OP_AMO_FETCH_ADD:
+                want = out_hash(np.zeros(r.nbytes, dtype=np.uint8))
+            else:
+                spe = r.issuer_pe if r.op == W.OP_PUT else r.target_pe
+                want = out_hash(W.payload(seed_of(spe), r.src_off, r.nbytes))
+            assert comps[i].hash == want, (i, r.op, r.nbytes)
+        assert_no_device_errors()
+

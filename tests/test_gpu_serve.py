@@ -10,28 +10,9 @@ import pytest
 
 import oracle
 import workload as W
-from tests.gpu_helpers import assert_no_device_errors, download, heap, torch, upload
+from tests.gpu_helpers import assert_no_device_errors, download, heap, out_hash, torch, upload
 
 pytestmark = pytest.mark.gpu
-
-GOLD = 0x9E3779B97F4A7C15
-M64 = (1 << 64) - 1
-
-
-def out_hash(b: np.ndarray) -> int:
-    """XOR over 8-byte words w_i (zero padded) of mix(w_i ^ ((i + 1) * golden))."""
-    n = len(b)
-    pad = np.zeros(((n + 7) // 8) * 8, dtype=np.uint8)
-    pad[:n] = b
-    w = pad.view("<u8")
-    idx = np.arange(1, len(w) + 1, dtype=np.uint64)
-    with np.errstate(over="ignore"):
-        z = w ^ (idx * np.uint64(GOLD))
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        z = z ^ (z >> np.uint64(31))
-    return int(np.bitwise_xor.reduce(z)) if len(z) else 0
-
 
 def _desc(op, issuer, target, src, dst, n, value=0):
     d = W.descs([(op, W.SCOPE_AUTO, 0, issuer, target, W.NO_RESULT, src, dst, n, value, 0)])
