@@ -339,9 +339,10 @@ def summarize_profiles(prof_dir: str, probe_mib: int) -> None:
     from `<prof_dir>/trace` and per-launch HBM bytes from the FETCH_SIZE and
     WRITE_SIZE passes in `<prof_dir>/pmc_<counter>`, each counter scaled by
     what it reads for the plain copy probe of probe_mib MiB in, probe_mib out."""
-    trace_cmd = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o bench --output-format csv "
+    rel = os.path.relpath(prof_dir, ROOT) if os.path.isabs(prof_dir) else prof_dir
+    trace_cmd = (f"rocprofv3 --kernel-trace --stats -d {rel}/trace -o bench --output-format csv "
                  "-- python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras")
-    pmc_cmd = ("rocprofv3 --pmc {ctr} -d gpurun_out/prof/pmc_{ctr} -o pmc --output-format csv -- python3 bench.py "
+    pmc_cmd = ("rocprofv3 --pmc {ctr} -d " + rel + "/pmc_{ctr} -o pmc --output-format csv -- python3 bench.py "
                "--rows put_wg_16MiB_ring,get_wg_16MiB_perm,alltoall_1MiB_fp32 --steps 2 --warmup 1 "
                f"--no-cpu-baseline --probe-copy-mib {probe_mib}")
     stats = _csv_rows(os.path.join(prof_dir, "trace", "**", "*kernel_stats.csv"))

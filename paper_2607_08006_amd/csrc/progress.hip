@@ -7,14 +7,15 @@
 // The device reports completion in a separate word (done[s] = t + 1, after
 // the completion record); the host's poll consumes the record and only then
 // frees the slot for ticket t + slots, so a record is never overwritten
-// before it was read.  On the device one front-end wavefront reads
-// published descriptors in ticket order and expands each into work items of
-// at most chunk_bytes in a device-memory queue; every other wavefront of the
-// grid claims items from that queue, executes them, and the wavefront that
-// finishes a request's last item writes its completion record to host
-// memory and then releases the slot with a system-scope store.  The kernel
-// ends when the host raises the stop flag or after idle_timeout_ms without
-// a request; either way every wavefront reaches its exit.
+// before it was read.  On the device one front-end wavefront (the first of
+// work-group 0) reads published descriptors in ticket order and expands
+// each into work items of at most chunk_bytes in a device-memory queue;
+// every other work-group claims items from that queue one at a time and
+// executes each with all its threads, and the work-group that finishes a
+// request's last item writes its completion record to host memory and then
+// releases the slot with a system-scope store.  The kernel ends when the
+// host raises the stop flag or after idle_timeout_ms without a request;
+// either way every wavefront reaches its exit.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
