@@ -328,7 +328,7 @@ def _csv_rows(pattern):
 
 
 def _short_kernel(name: str) -> str:
-    name = name.replace("(anonymous namespace)::", "")
+    name = name.replace("(anonymous namespace)::", "").replace("vshmem_detail::", "")
     if name.startswith("void "):
         name = name[5:]
     return name.split("(")[0].replace(", ", ",")

@@ -136,6 +136,17 @@ typedef int32_t shmem_team_t;
 #define SHMEM_DEVICE_TEAM_WORLD 2
 #define SHMEM_DEVICE_TEAM_SHARED 3
 
+/* What a kernel needs to address a team: members are the PEs start +
+ * k * stride for k < size; slot selects the team's barrier words in the
+ * scratch tail of its first member.  shmemx_team_device fills it on the
+ * host; kernels take it by value. */
+typedef struct {
+    int32_t start;
+    int32_t stride;
+    int32_t size;
+    int32_t slot;
+} shmemx_dteam_t;
+
 /* ------------------------------------------------------------ capabilities
  * Capability record (Section 6.5: queries distinguish host GPU-aware
  * support from device-initiated APIs, report stream variants separately,
@@ -244,6 +255,12 @@ const void *shmemx_device_ctx(void);
 int shmem_team_split_strided(shmem_team_t parent, int start, int stride, int size,
                              const void *config, long config_mask, shmem_team_t *new_team);
 int shmem_team_n_pes(shmem_team_t team);
+/* Device descriptor of a live team, for user kernels that call the device
+ * collectives and team barriers of vshmem_device.hpp.  Returns SHMEMX_OK,
+ * SHMEMX_ERR_STATE before init, SHMEMX_ERR_ARG for a NULL out or a team
+ * that does not exist.  The descriptor stays valid until the team is
+ * destroyed or the library finalised. */
+int shmemx_team_device(shmem_team_t team, shmemx_dteam_t *out);
 /* Team index of PE `pe` in `team`, or -1 if it is not a member. */
 int shmemx_team_pe_index(shmem_team_t team, int pe);
 void shmem_team_destroy(shmem_team_t team);

@@ -33,6 +33,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "vshmem.h"
+
 /* ------------------------------------------------------------- contexts */
 /* The published device context (one per library instance). */
 struct shmemx_dctx_pub_t {
@@ -52,14 +54,7 @@ struct shmem_dctx_t {
     int32_t me;
 };
 
-/* Device team: members start + k*stride, k < size; slot selects its
- * barrier words in the first member's scratch. */
-struct shmemx_dteam_t {
-    int32_t start;
-    int32_t stride;
-    int32_t size;
-    int32_t slot;
-};
+/* Device teams are shmemx_dteam_t of vshmem.h. */
 
 #define VSHMEM_SCRATCH_BYTES (64u << 10)
 #define VSHMEM_SYNC_SLOT_BYTES 128u
@@ -477,9 +472,20 @@ __device__ __forceinline__ uint64_t shmem_signal_wait_until_wg(const shmem_dctx_
 }
 
 /* ------------------------------------------------------------- barriers */
-/* Barrier of a team where `units_per_pe` work-groups act for each member
- * and every one of them calls this (work-group scope per caller).  Implies
- * quiet for every caller's earlier operations. */
+/* Team barriers (Section 6.3: barriers among the device-initiated
+ * collectives; the scope suffix names who calls, as in the _wave example
+ * of Section 8).  No member leaves before every member arrived, and each
+ * caller's earlier operations are complete and visible device-wide on
+ * return (the barrier implies quiet).  The counter lives in the scratch
+ * tail of the team's first member, at the team's slot.
+ *
+ *   plain  one thread acts for its PE (exactly one per member calls);
+ *   _wave  all 64 lanes of one wavefront act for the PE;
+ *   _wg    every thread of one work-group acts for the PE;
+ *   units  every thread of `units_per_pe` work-groups per PE.
+ *
+ * All callers of one barrier must be resident together: a caller that is
+ * waiting for a work-group slot never arrives. */
 __device__ __forceinline__ void shmemx_team_sync_units(const shmem_dctx_t &ctx, const shmemx_dteam_t &team,
                                                        uint64_t units_per_pe)
 {
@@ -494,15 +500,464 @@ __device__ __forceinline__ void shmemx_team_sync_units(const shmem_dctx_t &ctx, 
     __syncthreads();
 }
 
-/* barrier_all with one work-group per PE (rocSHMEM-style _wg routine). */
-__device__ __forceinline__ void shmem_barrier_all_wg(const shmem_dctx_t &ctx)
+__device__ __forceinline__ int shmem_team_sync(const shmem_dctx_t &ctx, const shmemx_dteam_t &team)
 {
-    shmemx_dteam_t world{0, 1, ctx.c.npes, 0};
-    shmemx_team_sync_units(ctx, world, 1);
+    vshmem_detail::counter_barrier(ctx.c, vshmem_detail::sync_slot(ctx.c, team.start, team.slot),
+                                   (uint64_t)team.size);
+    return 0;
 }
-__device__ __forceinline__ void shmem_team_sync_wg(const shmem_dctx_t &ctx, const shmemx_dteam_t &team)
+__device__ __forceinline__ int shmem_team_sync_wave(const shmem_dctx_t &ctx, const shmemx_dteam_t &team)
+{
+    // One wavefront: its memory counter covers all 64 lanes, so lane 0's
+    // release after the wait covers the wave's stores; the acquire runs
+    // with every lane active once lane 0 is back.
+    vshmem_detail::wait_vm_complete();
+    if (__lane_id() == 0)
+        vshmem_detail::counter_barrier(ctx.c, vshmem_detail::sync_slot(ctx.c, team.start, team.slot),
+                                       (uint64_t)team.size);
+    vshmem_detail::acquire_agent();
+    return 0;
+}
+__device__ __forceinline__ int shmem_team_sync_wg(const shmem_dctx_t &ctx, const shmemx_dteam_t &team)
 {
     shmemx_team_sync_units(ctx, team, 1);
+    return 0;
 }
+
+__device__ __forceinline__ shmemx_dteam_t shmemx_team_world(const shmem_dctx_t &ctx)
+{
+    return shmemx_dteam_t{0, 1, ctx.c.npes, 0};
+}
+__device__ __forceinline__ void shmem_barrier_all(const shmem_dctx_t &ctx) { shmem_team_sync(ctx, shmemx_team_world(ctx)); }
+__device__ __forceinline__ void shmem_barrier_all_wave(const shmem_dctx_t &ctx)
+{
+    shmem_team_sync_wave(ctx, shmemx_team_world(ctx));
+}
+__device__ __forceinline__ void shmem_barrier_all_wg(const shmem_dctx_t &ctx)
+{
+    shmemx_team_sync_units(ctx, shmemx_team_world(ctx), 1);
+}
+
+/* ---------------------------------------------------------- collectives */
+namespace vshmem_detail {
+
+constexpr uint64_t kCollChunk = 256ull << 10;   // bytes per task: broadcast, fcollect, alltoall
+constexpr uint64_t kRedChunk = 16ull << 10;     // bytes per task: reductions
+constexpr int kMcastTile = 16;                  // 16-byte vectors per lane in a multicast tile
+constexpr int kRedBatch = 8;                    // member loads in flight per lane before combining
+
+// The work-groups of a collective, numbered across the team: member k's
+// work-group `rank` (of nwgs) is worker k * nwgs + rank of size * nwgs.
+// (32-bit: a grid has fewer than 2^32 work-groups, and 64-bit division and
+// remainder would expand to long vector sequences.)
+struct Workers {
+    uint32_t w, n;
+};
+__device__ __forceinline__ Workers team_workers(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, int rank,
+                                                int nwgs)
+{
+    const uint32_t k = (uint32_t)((ctx.me - team.start) / team.stride);
+    return Workers{k * (uint32_t)nwgs + (uint32_t)rank, (uint32_t)team.size * (uint32_t)nwgs};
+}
+
+// Member 0's copy of a symmetric object, and the distance between members.
+__device__ __forceinline__ uint8_t *member0(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, const void *sym)
+{
+    return (uint8_t *)sym + (uint64_t)team.start * ctx.c.stride;
+}
+__device__ __forceinline__ uint64_t member_stride(const shmem_dctx_t &ctx, const shmemx_dteam_t &team)
+{
+    return (uint64_t)team.stride * ctx.c.stride;
+}
+
+// Copy one source range to the same place on every team member (d0 is
+// member 0's copy, members pstride apart).  Aligned ranges go through a
+// register tile: each lane loads kMcastTile 16-byte vectors once, then the
+// whole tile is written to one member after another, starting at a member
+// that depends on the worker so that concurrent work-groups spread over
+// the members.  Long contiguous writes per member page measured about 10%
+// faster on MI355X than writing every vector to all members in turn.
+template <bool NT>
+__device__ __forceinline__ void multicast(uint8_t *d0, uint64_t pstride, int P, const uint8_t *src, uint64_t len,
+                                          uint32_t worker)
+{
+    if ((((uintptr_t)src | (uintptr_t)d0 | len) & 15) == 0) {
+        const v4u *s = (const v4u *)src;
+        const uint64_t nv = len / 16, bd = blockDim.x;
+        for (uint64_t i0 = threadIdx.x; i0 < nv; i0 += kMcastTile * bd) {
+            v4u r[kMcastTile];
+#pragma unroll
+            for (int u = 0; u < kMcastTile; ++u)
+                if (i0 + u * bd < nv) r[u] = ld<true>(s + i0 + u * bd);
+            int p = (int)(worker % (uint32_t)P);
+            for (int k = 0; k < P; ++k) {
+                v4u *d = (v4u *)(d0 + (uint64_t)p * pstride);
+#pragma unroll
+                for (int u = 0; u < kMcastTile; ++u)
+                    if (i0 + u * bd < nv) st<NT>(d + i0 + u * bd, r[u]);
+                if (++p == P) p = 0;
+            }
+        }
+    } else {
+        for (int p = 0; p < P; ++p)
+            copy_bytes<VSHMEM_COPY_UNROLL, NT>(d0 + p * pstride, src, len, threadIdx.x, blockDim.x);
+    }
+}
+
+// Every member's dest[0, n) <- member root's src[0, n), root included.
+template <bool NT>
+__device__ __forceinline__ void broadcast(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
+                                          const void *src, uint64_t n, int root, int rank, int nwgs, uint64_t chunk)
+{
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+    const Workers W = team_workers(ctx, team, rank, nwgs);
+    const uint8_t *S = (const uint8_t *)src + (uint64_t)shmemx_team_pe(team, root) * ctx.c.stride;
+    uint8_t *D = member0(ctx, team, dest);
+    const uint64_t ps = member_stride(ctx, team);
+    const uint64_t ntask = (n + chunk - 1) / chunk;
+    for (uint64_t t = W.w; t < ntask; t += W.n) {
+        const uint64_t off = t * chunk;
+        multicast<NT>(D + off, ps, team.size, S + off, min(chunk, n - off), W.w);
+    }
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+}
+
+// Every member's dest[q*n, (q+1)*n) <- member q's src[0, n).
+template <bool NT>
+__device__ __forceinline__ void fcollect(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
+                                         const void *src, uint64_t n, int rank, int nwgs, uint64_t chunk)
+{
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+    const Workers W = team_workers(ctx, team, rank, nwgs);
+    const uint8_t *S0 = member0(ctx, team, src);
+    uint8_t *D = member0(ctx, team, dest);
+    const uint64_t ps = member_stride(ctx, team);
+    const uint64_t nch = (n + chunk - 1) / chunk;
+    const uint64_t ntask = nch * (uint64_t)team.size;
+    for (uint64_t t = W.w; t < ntask; t += W.n) {
+        const uint64_t q = t / nch;
+        const uint64_t off = (t - q * nch) * chunk;
+        multicast<NT>(D + q * n + off, ps, team.size, S0 + q * ps + off, min(chunk, n - off), W.w);
+    }
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+}
+
+// Member p's dest[q*n, (q+1)*n) <- member q's src[p*n, (p+1)*n).
+template <bool NT, int U>
+__device__ __forceinline__ void alltoall(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
+                                         const void *src, uint64_t n, int rank, int nwgs, uint64_t chunk)
+{
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+    const Workers W = team_workers(ctx, team, rank, nwgs);
+    const uint8_t *S0 = member0(ctx, team, src);
+    uint8_t *D0 = member0(ctx, team, dest);
+    const uint64_t ps = member_stride(ctx, team);
+    const uint64_t P = (uint64_t)team.size;
+    const uint64_t nch = (n + chunk - 1) / chunk;
+    const uint64_t ntask = nch * P * P;
+    for (uint64_t t = W.w; t < ntask; t += W.n) {
+        const uint64_t blk = t / nch;
+        const uint64_t p = blk / P;   // destination member
+        const uint64_t q = blk % P;   // source member
+        const uint64_t off = (t - blk * nch) * chunk;
+        copy_bytes<U, NT>(D0 + p * ps + q * n + off, S0 + q * ps + p * n + off, min(chunk, n - off), threadIdx.x,
+                          blockDim.x);
+    }
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+}
+
+// TREE in streaming form.  Pushing x_0, x_1, ... keeps, for every set bit j
+// of the count, the reduction of an aligned block of 2^j consecutive inputs
+// (slot j).  Pushing merges equal-sized blocks left to right, which is
+// exactly the pairing of one TREE level.  At the end the blocks, largest
+// (leftmost) first, are combined right-nested: op(B_a, op(B_b, ... B_z)),
+// which is how TREE's carried odd elements meet the full subtrees.
+struct OpSum {
+    template <typename T> __device__ __forceinline__ static T f(T a, T b) { return a + b; }
+};
+struct OpMax {
+    template <typename T> __device__ __forceinline__ static T f(T a, T b) { return (b > a) ? b : a; }
+};
+
+constexpr int kTreeLevels = 9;   // teams of up to 2^9 - 1 members
+
+template <typename A, int E, class OP, int LEVELS = kTreeLevels>
+struct TreeAcc {
+    A s[LEVELS][E];
+    __device__ __forceinline__ void push(uint32_t count, const A (&x)[E])
+    {
+        // The new input merges with the tz occupied slots below the first
+        // free one (tz = trailing ones of count) and lands in slot tz.
+        const uint32_t tz = (uint32_t)__builtin_ctz(~count);
+        A c[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) c[e] = x[e];
+#pragma unroll
+        for (int j = 0; j < LEVELS; ++j) {
+            if ((uint32_t)j < tz) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) c[e] = OP::f(s[j][e], c[e]);
+            } else if ((uint32_t)j == tz) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) s[j][e] = c[e];
+            }
+        }
+    }
+    // count >= 1 inputs pushed.
+    __device__ __forceinline__ void result(uint32_t count, A (&r)[E]) const
+    {
+        bool have = false;
+#pragma unroll
+        for (int j = 0; j < LEVELS; ++j) {
+            if ((count >> j) & 1u) {
+                if (!have) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) r[e] = s[j][e];
+                    have = true;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) r[e] = OP::f(s[j][e], r[e]);
+                }
+            }
+        }
+    }
+};
+
+// Element codecs: a 16-byte vector of the storage type <-> E accumulators.
+struct CodecI64 {
+    using A = int64_t;
+    static constexpr int E = 2;
+    static constexpr int ES = 8;
+    __device__ __forceinline__ static void unpack(const v4u &v, A (&x)[E])
+    {
+        x[0] = (int64_t)(((uint64_t)v.y << 32) | v.x);
+        x[1] = (int64_t)(((uint64_t)v.w << 32) | v.z);
+    }
+    __device__ __forceinline__ static v4u pack(const A (&x)[E])
+    {
+        v4u v;
+        v.x = (uint32_t)x[0];
+        v.y = (uint32_t)((uint64_t)x[0] >> 32);
+        v.z = (uint32_t)x[1];
+        v.w = (uint32_t)((uint64_t)x[1] >> 32);
+        return v;
+    }
+    __device__ __forceinline__ static A load1(const uint8_t *p) { return *(const int64_t *)p; }
+    __device__ __forceinline__ static void store1(uint8_t *p, A v) { *(int64_t *)p = v; }
+};
+
+struct CodecF32 {
+    using A = float;
+    static constexpr int E = 4;
+    static constexpr int ES = 4;
+    __device__ __forceinline__ static void unpack(const v4u &v, A (&x)[E])
+    {
+        x[0] = __uint_as_float(v.x);
+        x[1] = __uint_as_float(v.y);
+        x[2] = __uint_as_float(v.z);
+        x[3] = __uint_as_float(v.w);
+    }
+    __device__ __forceinline__ static v4u pack(const A (&x)[E])
+    {
+        v4u v;
+        v.x = __float_as_uint(x[0]);
+        v.y = __float_as_uint(x[1]);
+        v.z = __float_as_uint(x[2]);
+        v.w = __float_as_uint(x[3]);
+        return v;
+    }
+    __device__ __forceinline__ static A load1(const uint8_t *p) { return *(const float *)p; }
+    __device__ __forceinline__ static void store1(uint8_t *p, A v) { *(float *)p = v; }
+};
+
+// bf16 -> fp32 is exact (the bf16 bits are the high half of the fp32).
+// fp32 -> bf16 rounds to nearest, ties to even; NaN stays a quiet NaN.
+__device__ __forceinline__ float bf16_up(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ uint32_t bf16_down(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (u >> 16) | 0x40u;
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+struct CodecBF16 {
+    using A = float;
+    static constexpr int E = 8;
+    static constexpr int ES = 2;
+    __device__ __forceinline__ static void unpack(const v4u &v, A (&x)[E])
+    {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            x[2 * i] = bf16_up(w[i] & 0xFFFFu);
+            x[2 * i + 1] = bf16_up(w[i] >> 16);
+        }
+    }
+    __device__ __forceinline__ static v4u pack(const A (&x)[E])
+    {
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = bf16_down(x[2 * i]) | (bf16_down(x[2 * i + 1]) << 16);
+        v4u v;
+        v.x = w[0];
+        v.y = w[1];
+        v.z = w[2];
+        v.w = w[3];
+        return v;
+    }
+    __device__ __forceinline__ static A load1(const uint8_t *p) { return bf16_up(*(const uint16_t *)p); }
+    __device__ __forceinline__ static void store1(uint8_t *p, A v) { *(uint16_t *)p = (uint16_t)bf16_down(v); }
+};
+
+// Every member's dest[k] <- TREE over members of src[k], for k < nelem.
+// Each lane owns 16-byte vectors of the range: it loads the vector from
+// every member (kRedBatch loads in flight), folds them in member order and
+// writes the result to every member.  Returns SHMEMX_ERR_UNSUPPORTED,
+// without synchronising, for teams larger than the fold's depth allows.
+template <class CODEC, class OP, bool NT>
+__device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
+                                      const void *src, uint64_t nelem, int rank, int nwgs, uint64_t chunk)
+{
+    using A = typename CODEC::A;
+    constexpr int E = CODEC::E;
+    if (team.size >= (1 << kTreeLevels)) return SHMEMX_ERR_UNSUPPORTED;
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+    const Workers W = team_workers(ctx, team, rank, nwgs);
+    const int P = team.size;
+    const uint64_t pstride = member_stride(ctx, team);
+    const uint8_t *s0 = member0(ctx, team, src);
+    uint8_t *d0 = member0(ctx, team, dest);
+    const uint64_t nbytes = nelem * CODEC::ES;
+    const bool vec = (((uintptr_t)s0 | (uintptr_t)d0 | pstride) & 15) == 0;
+    const uint64_t nvec = vec ? nbytes / 16 : 0;
+    const uint64_t vpt = chunk / 16;   // vectors per task
+    const uint64_t ntask = (nvec + vpt - 1) / vpt;
+    for (uint64_t t = W.w; t < ntask; t += W.n) {
+        const uint64_t v1 = min(nvec, (t + 1) * vpt);
+        for (uint64_t i = t * vpt + threadIdx.x; i < v1; i += blockDim.x) {
+            TreeAcc<A, E, OP> acc;
+            const uint8_t *sp = s0 + i * 16;
+            for (int p0 = 0; p0 < P; p0 += kRedBatch) {
+                v4u raw[kRedBatch];
+#pragma unroll
+                for (int u = 0; u < kRedBatch; ++u)
+                    if (p0 + u < P) raw[u] = ld<NT>((const v4u *)(sp + (uint64_t)(p0 + u) * pstride));
+#pragma unroll
+                for (int u = 0; u < kRedBatch; ++u) {
+                    if (p0 + u < P) {
+                        A x[E];
+                        CODEC::unpack(raw[u], x);
+                        acc.push((uint32_t)(p0 + u), x);
+                    }
+                }
+            }
+            A r[E];
+            acc.result((uint32_t)P, r);
+            const v4u out = CODEC::pack(r);
+            uint8_t *dp = d0 + i * 16;
+            for (int p = 0; p < P; ++p, dp += pstride) st<NT>((v4u *)dp, out);
+        }
+    }
+    // Elements past the vector part (or all of them when unaligned).
+    const uint64_t e0 = nvec * 16 / CODEC::ES;
+    for (uint64_t k = e0 + (uint64_t)W.w * blockDim.x + threadIdx.x; k < nelem; k += (uint64_t)W.n * blockDim.x) {
+        TreeAcc<A, 1, OP> acc;
+        for (int p = 0; p < P; ++p) {
+            A x[1] = {CODEC::load1(s0 + (uint64_t)p * pstride + k * CODEC::ES)};
+            acc.push((uint32_t)p, x);
+        }
+        A r[1];
+        acc.result((uint32_t)P, r);
+        for (int p = 0; p < P; ++p) CODEC::store1(d0 + (uint64_t)p * pstride + k * CODEC::ES, r[0]);
+    }
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+    return 0;
+}
+
+} // namespace vshmem_detail
+
+/* Team collectives (Section 6.3 names broadcast and reductions among the
+ * device-initiated operations; fcollect and alltoall follow OpenSHMEM).
+ * Pointers are canonical symmetric addresses; n counts bytes for the
+ * data-movement routines and elements for the reductions.
+ *
+ *   _wg    one work-group per member calls it;
+ *   _grid  nwgs work-groups per member call it, this one being `rank`
+ *          (0 <= rank < nwgs) among those acting for its PE; the work is
+ *          spread over all team.size * nwgs of them.
+ *
+ * Every participant passes identical arguments (rank aside) and all of them
+ * must be resident together.  Each routine starts and ends with a barrier
+ * of the team (at its slot), so sources may be rewritten and destinations
+ * read, on any member, as soon as it returns.  Destination and source must
+ * not overlap (a reduction may run in place).  Reductions fold members in
+ * the fixed TREE order (pairs of neighbours, level by level), so results
+ * are reproducible bit for bit; bf16 accumulates in fp32 and rounds once to
+ * nearest-even; teams of 512 or more members get SHMEMX_ERR_UNSUPPORTED
+ * from the reductions, which then do nothing.  Return 0 otherwise. */
+__device__ __forceinline__ int shmemx_broadcastmem_grid(const shmem_dctx_t &ctx, const shmemx_dteam_t &team,
+                                                        void *dest, const void *src, size_t n, int root, int rank,
+                                                        int nwgs)
+{
+    vshmem_detail::broadcast<false>(ctx, team, dest, src, n, root, rank, nwgs, vshmem_detail::kCollChunk);
+    return 0;
+}
+__device__ __forceinline__ int shmem_broadcastmem_wg(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
+                                                     const void *src, size_t n, int root)
+{
+    return shmemx_broadcastmem_grid(ctx, team, dest, src, n, root, 0, 1);
+}
+__device__ __forceinline__ int shmemx_fcollectmem_grid(const shmem_dctx_t &ctx, const shmemx_dteam_t &team,
+                                                       void *dest, const void *src, size_t n, int rank, int nwgs)
+{
+    vshmem_detail::fcollect<false>(ctx, team, dest, src, n, rank, nwgs, vshmem_detail::kCollChunk);
+    return 0;
+}
+__device__ __forceinline__ int shmem_fcollectmem_wg(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
+                                                    const void *src, size_t n)
+{
+    return shmemx_fcollectmem_grid(ctx, team, dest, src, n, 0, 1);
+}
+__device__ __forceinline__ int shmemx_alltoallmem_grid(const shmem_dctx_t &ctx, const shmemx_dteam_t &team,
+                                                       void *dest, const void *src, size_t n, int rank, int nwgs)
+{
+    vshmem_detail::alltoall<true, 8>(ctx, team, dest, src, n, rank, nwgs, vshmem_detail::kCollChunk);
+    return 0;
+}
+__device__ __forceinline__ int shmem_alltoallmem_wg(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
+                                                    const void *src, size_t n)
+{
+    return shmemx_alltoallmem_grid(ctx, team, dest, src, n, 0, 1);
+}
+
+#define VSHMEM_DEVICE_REDUCE(PREFIX, NAME, T, CODEC, OP)                                                             \
+    __device__ __forceinline__ int PREFIX##NAME##_reduce_grid(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, \
+                                                              T *dest, const T *src, size_t nreduce, int rank,     \
+                                                              int nwgs)                                            \
+    {                                                                                                              \
+        return vshmem_detail::reduce<vshmem_detail::CODEC, vshmem_detail::OP, true>(                               \
+            ctx, team, dest, src, nreduce, rank, nwgs, vshmem_detail::kRedChunk);                                  \
+    }
+/* The grid forms carry the shmemx_ prefix; the _wg forms are OpenSHMEM names. */
+#define VSHMEM_DEVICE_REDUCE_WG(NAME, GRIDNAME, T)                                                                   \
+    __device__ __forceinline__ int NAME##_reduce_wg(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, T *dest,  \
+                                                    const T *src, size_t nreduce)                                  \
+    {                                                                                                              \
+        return GRIDNAME##_reduce_grid(ctx, team, dest, src, nreduce, 0, 1);                                        \
+    }
+VSHMEM_DEVICE_REDUCE(shmemx_, int64_sum, int64_t, CodecI64, OpSum)
+VSHMEM_DEVICE_REDUCE(shmemx_, int64_max, int64_t, CodecI64, OpMax)
+VSHMEM_DEVICE_REDUCE(shmemx_, float_sum, float, CodecF32, OpSum)
+VSHMEM_DEVICE_REDUCE(shmemx_, float_max, float, CodecF32, OpMax)
+VSHMEM_DEVICE_REDUCE(shmemx_, bfloat16_sum, uint16_t, CodecBF16, OpSum)   /* bf16 as its bits */
+VSHMEM_DEVICE_REDUCE(shmemx_, bfloat16_max, uint16_t, CodecBF16, OpMax)
+VSHMEM_DEVICE_REDUCE_WG(shmem_int64_sum, shmemx_int64_sum, int64_t)
+VSHMEM_DEVICE_REDUCE_WG(shmem_int64_max, shmemx_int64_max, int64_t)
+VSHMEM_DEVICE_REDUCE_WG(shmem_float_sum, shmemx_float_sum, float)
+VSHMEM_DEVICE_REDUCE_WG(shmem_float_max, shmemx_float_max, float)
+VSHMEM_DEVICE_REDUCE_WG(shmemx_bfloat16_sum, shmemx_bfloat16_sum, uint16_t)
+VSHMEM_DEVICE_REDUCE_WG(shmemx_bfloat16_max, shmemx_bfloat16_max, uint16_t)
+#undef VSHMEM_DEVICE_REDUCE
+#undef VSHMEM_DEVICE_REDUCE_WG
 
 #endif /* VSHMEM_DEVICE_HPP */

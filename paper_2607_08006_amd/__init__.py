@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _native
-from ._native import Caps, Completion, Desc, Launch, ProgressCfg, Request, ServeStats, Tune
+from ._native import Caps, Completion, Desc, DTeam, Launch, ProgressCfg, Request, ServeStats, Tune
 
 lib = _native.load()
 
@@ -194,6 +194,22 @@ def team_split_strided(parent: int, start: int, stride: int, size: int) -> int:
 
 def team_n_pes(team: int) -> int:
     return lib.shmem_team_n_pes(team)
+
+
+def team_device(team: int) -> DTeam:
+    """The device descriptor of `team` (shmemx_dteam_t), passed by value to
+    user kernels that call the device collectives."""
+    t = DTeam()
+    _check(lib.shmemx_team_device(team, C.byref(t)), "shmemx_team_device")
+    return t
+
+
+def device_ctx() -> int:
+    """Device address of the published default device context."""
+    p = lib.shmemx_device_ctx()
+    if not p:
+        raise VshmemError(ERR_STATE, "shmemx_device_ctx")
+    return p
 
 
 def team_destroy(team: int) -> None:

@@ -47,6 +47,10 @@ class Completion(C.Structure):
                 ("status", C.c_int32), ("reserved", C.c_int32), ("t_queued", C.c_uint64), ("submit_ns", C.c_uint64)]
 
 
+class DTeam(C.Structure):
+    _fields_ = [("start", C.c_int32), ("stride", C.c_int32), ("size", C.c_int32), ("slot", C.c_int32)]
+
+
 class Request(C.Structure):
     _fields_ = [("op", C.c_int32), ("issuer_pe", C.c_int32), ("target_pe", C.c_int32), ("lane", C.c_int32),
                 ("nbytes", C.c_uint64), ("src_off", C.c_uint64), ("arrival_s", C.c_double)]
@@ -81,6 +85,7 @@ SIGNATURES = {
     "shmemx_device_ctx": (vp, []),
     "shmem_team_split_strided": (i32, [C.c_int32, i32, i32, i32, vp, C.c_long, P(C.c_int32)]),
     "shmem_team_n_pes": (i32, [C.c_int32]),
+    "shmemx_team_device": (i32, [C.c_int32, P(DTeam)]),
     "shmemx_team_pe_index": (i32, [C.c_int32, i32]),
     "shmem_team_destroy": (None, [C.c_int32]),
     "shmemx_strerror": (C.c_char_p, [i32]),

@@ -49,6 +49,25 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+USER_TEST_SRC = os.path.join(ROOT, "tests", "devapi", "user_kernels.hip")
+USER_TEST_OUT = os.path.join(ROOT, "tests", "devapi", "libvshmem_usertest.so")
+
+
+def build_user_tests(verbose: bool = False) -> str:
+    """Compile the test suite's user-style kernels, which use only the public
+    headers (the device API is header-only), into their own library."""
+    tmp = USER_TEST_OUT + ".tmp"
+    cmd = [HIPCC, "-x", "hip", *FLAGS, "-shared", USER_TEST_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {USER_TEST_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, USER_TEST_OUT)
+    if verbose:
+        print(f"built {USER_TEST_OUT}")
+    return USER_TEST_OUT
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_user_tests(verbose=True)
     sys.exit(0)

@@ -469,6 +469,14 @@ int shmem_team_n_pes(shmem_team_t team)
     return t.size;
 }
 
+int shmemx_team_device(shmem_team_t team, shmemx_dteam_t *out)
+{
+    int rc = check_ready();
+    if (!rc && (!out || team_get(team, out) != SHMEMX_OK)) rc = SHMEMX_ERR_ARG;
+    if (rc) set_last_error(rc);
+    return rc;
+}
+
 int shmemx_team_pe_index(shmem_team_t team, int pe)
 {
     shmemx_dteam_t t;

@@ -1,0 +1,167 @@
+// Kernels written the way a library user writes them: they include only the
+// public headers, receive the published device context and a team
+// descriptor from the host, and call the device-side collectives and team
+// barriers themselves.  Built into its own shared library, apart from
+// libvshmem.so, so that the header-only device API is exercised on its own.
+#include <hip/hip_runtime.h>
+
+#include "vshmem.h"
+#include "vshmem_device.hpp"
+
+namespace {
+
+enum { KIND_BROADCAST = 0, KIND_FCOLLECT = 1, KIND_ALLTOALL = 2, KIND_REDUCE = 3 };
+
+// One collective per launch; nwgs == 1 selects the _wg routines, more the
+// _grid ones.  Work-group b acts for team member b / nwgs.  One kernel per
+// routine keeps each one's registers its own.
+template <int KIND, int DT, int OP>
+__device__ int one_collective(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest, const void *src,
+                              size_t n, int root, int rank, int nwgs)
+{
+    const bool wg = nwgs == 1;
+    if (KIND == KIND_BROADCAST)
+        return wg ? shmem_broadcastmem_wg(ctx, team, dest, src, n, root)
+                  : shmemx_broadcastmem_grid(ctx, team, dest, src, n, root, rank, nwgs);
+    if (KIND == KIND_FCOLLECT)
+        return wg ? shmem_fcollectmem_wg(ctx, team, dest, src, n)
+                  : shmemx_fcollectmem_grid(ctx, team, dest, src, n, rank, nwgs);
+    if (KIND == KIND_ALLTOALL)
+        return wg ? shmem_alltoallmem_wg(ctx, team, dest, src, n)
+                  : shmemx_alltoallmem_grid(ctx, team, dest, src, n, rank, nwgs);
+#define USER_RED(T, WGF, GRIDF)                                                                              \
+    return wg ? WGF(ctx, team, (T *)dest, (const T *)src, n) : GRIDF(ctx, team, (T *)dest, (const T *)src, n, \
+                                                                      rank, nwgs)
+    constexpr bool sum = OP == SHMEMX_RED_SUM;
+    if (DT == SHMEMX_DT_INT64) {
+        if (sum) USER_RED(int64_t, shmem_int64_sum_reduce_wg, shmemx_int64_sum_reduce_grid);
+        USER_RED(int64_t, shmem_int64_max_reduce_wg, shmemx_int64_max_reduce_grid);
+    }
+    if (DT == SHMEMX_DT_FP32) {
+        if (sum) USER_RED(float, shmem_float_sum_reduce_wg, shmemx_float_sum_reduce_grid);
+        USER_RED(float, shmem_float_max_reduce_wg, shmemx_float_max_reduce_grid);
+    }
+    if (sum) USER_RED(uint16_t, shmemx_bfloat16_sum_reduce_wg, shmemx_bfloat16_sum_reduce_grid);
+    USER_RED(uint16_t, shmemx_bfloat16_max_reduce_wg, shmemx_bfloat16_max_reduce_grid);
+#undef USER_RED
+}
+
+template <int KIND, int DT, int OP>
+__global__ void __launch_bounds__(256) k_user_collective(const shmemx_dctx_pub_t *pub, shmemx_dteam_t team, void *dest,
+                                                         const void *src, size_t n, int root, int nwgs, int *status)
+{
+    const int k = (int)(blockIdx.x / (unsigned)nwgs);
+    const shmem_dctx_t ctx = shmemx_dctx_bind(*pub, shmemx_team_pe(team, k));
+    const int rc = one_collective<KIND, DT, OP>(ctx, team, dest, src, n, root, (int)blockIdx.x - k * nwgs, nwgs);
+    if (threadIdx.x == 0) status[blockIdx.x] = rc;
+}
+
+// Three steps in one launch: every member scales its own int64 input by
+// (its PE number + 1) into x, the team sums x into y, and fcollect gathers
+// the first m elements of every member's y into z.
+__global__ void __launch_bounds__(256) k_user_pipeline(const shmemx_dctx_pub_t *pub, shmemx_dteam_t team,
+                                                       const int64_t *src, int64_t *x, int64_t *y, int64_t *z,
+                                                       size_t n, size_t m, int nwgs)
+{
+    const int k = (int)(blockIdx.x / (unsigned)nwgs);
+    const int rank = (int)blockIdx.x - k * nwgs;
+    const shmem_dctx_t ctx = shmemx_dctx_bind(*pub, shmemx_team_pe(team, k));
+    const int64_t *s = shmem_ptr(ctx, src, ctx.me);
+    int64_t *xm = shmem_ptr(ctx, x, ctx.me);
+    const int64_t f = ctx.me + 1;
+    for (size_t i = (size_t)rank * blockDim.x + threadIdx.x; i < n; i += (size_t)nwgs * blockDim.x) xm[i] = s[i] * f;
+    // The reduction opens with a team barrier, which completes these stores.
+    shmemx_int64_sum_reduce_grid(ctx, team, y, x, n, rank, nwgs);
+    shmemx_fcollectmem_grid(ctx, team, z, y, m * sizeof(int64_t), rank, nwgs);
+}
+
+// Token exchange through a barrier at one scope: in round r the caller of
+// member k stores r + 1 into its own tok, synchronises, checks that member
+// k + 1 (mod size) stored r + 1 too, and synchronises again before the next
+// round may overwrite it.  One work-group per member.
+__global__ void __launch_bounds__(256) k_user_barrier(const shmemx_dctx_pub_t *pub, shmemx_dteam_t team, int scope,
+                                                      int world, int iters, int64_t *tok, unsigned long long *bad)
+{
+    const int k = (int)blockIdx.x;
+    const shmem_dctx_t ctx = shmemx_dctx_bind(*pub, shmemx_team_pe(team, k));
+    const int64_t *next = shmem_ptr(ctx, tok, shmemx_team_pe(team, (k + 1) % team.size));
+    int64_t *mine = shmem_ptr(ctx, tok, ctx.me);
+    // Who calls: thread 0 (thread scope), wavefront 0 (wave scope) or all.
+    const bool caller = scope == SHMEMX_SCOPE_THREAD ? threadIdx.x == 0
+                        : scope == SHMEMX_SCOPE_WAVE ? threadIdx.x < 64
+                                                     : true;
+    const bool leader = threadIdx.x == 0;
+    if (!caller) return;
+    for (int r = 0; r < iters; ++r) {
+        if (leader) __hip_atomic_store(mine, (int64_t)r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int half = 0; half < 2; ++half) {
+            if (half == 1 && leader &&
+                __hip_atomic_load(next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (int64_t)r + 1)
+                atomicAdd(bad, 1ull);
+            if (scope == SHMEMX_SCOPE_THREAD) {
+                if (world) shmem_barrier_all(ctx);
+                else shmem_team_sync(ctx, team);
+            } else if (scope == SHMEMX_SCOPE_WAVE) {
+                if (world) shmem_barrier_all_wave(ctx);
+                else shmem_team_sync_wave(ctx, team);
+            } else {
+                if (world) shmem_barrier_all_wg(ctx);
+                else shmem_team_sync_wg(ctx, team);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Each launcher checks what it can on the host and returns 0, or -1 for an
+// argument its kernel would not handle.
+int usertest_collective(const void *dctx, const shmemx_dteam_t *team, int kind, int dtype, int op, void *dest,
+                        const void *src, size_t n, int root, int nwgs, int wg, int *status, void *stream)
+{
+    if (!dctx || !team || kind < 0 || kind > KIND_REDUCE || nwgs < 1 || wg < 64 || wg > 256 || wg % 64 || !status)
+        return -1;
+    if (kind == KIND_REDUCE && (dtype < SHMEMX_DT_INT64 || dtype > SHMEMX_DT_BF16 || op < SHMEMX_RED_SUM ||
+                                op > SHMEMX_RED_MAX))
+        return -1;
+    const dim3 grid(team->size * nwgs), block(wg);
+    const auto *pub = (const shmemx_dctx_pub_t *)dctx;
+    hipStream_t s = (hipStream_t)stream;
+#define USER_LAUNCH(K, D, O) \
+    hipLaunchKernelGGL((k_user_collective<K, D, O>), grid, block, 0, s, pub, *team, dest, src, n, root, nwgs, status)
+    if (kind == KIND_BROADCAST) USER_LAUNCH(KIND_BROADCAST, 0, 0);
+    else if (kind == KIND_FCOLLECT) USER_LAUNCH(KIND_FCOLLECT, 0, 0);
+    else if (kind == KIND_ALLTOALL) USER_LAUNCH(KIND_ALLTOALL, 0, 0);
+    else if (dtype == SHMEMX_DT_INT64 && op == SHMEMX_RED_SUM) USER_LAUNCH(KIND_REDUCE, SHMEMX_DT_INT64, SHMEMX_RED_SUM);
+    else if (dtype == SHMEMX_DT_INT64) USER_LAUNCH(KIND_REDUCE, SHMEMX_DT_INT64, SHMEMX_RED_MAX);
+    else if (dtype == SHMEMX_DT_FP32 && op == SHMEMX_RED_SUM) USER_LAUNCH(KIND_REDUCE, SHMEMX_DT_FP32, SHMEMX_RED_SUM);
+    else if (dtype == SHMEMX_DT_FP32) USER_LAUNCH(KIND_REDUCE, SHMEMX_DT_FP32, SHMEMX_RED_MAX);
+    else if (op == SHMEMX_RED_SUM) USER_LAUNCH(KIND_REDUCE, SHMEMX_DT_BF16, SHMEMX_RED_SUM);
+    else USER_LAUNCH(KIND_REDUCE, SHMEMX_DT_BF16, SHMEMX_RED_MAX);
+#undef USER_LAUNCH
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int usertest_pipeline(const void *dctx, const shmemx_dteam_t *team, const int64_t *src, int64_t *x, int64_t *y,
+                      int64_t *z, size_t n, size_t m, int nwgs, int wg, void *stream)
+{
+    if (!dctx || !team || m > n || nwgs < 1 || wg < 64 || wg > 256 || wg % 64) return -1;
+    hipLaunchKernelGGL(k_user_pipeline, dim3(team->size * nwgs), dim3(wg), 0, (hipStream_t)stream,
+                       (const shmemx_dctx_pub_t *)dctx, *team, src, x, y, z, n, m, nwgs);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int usertest_barrier(const void *dctx, const shmemx_dteam_t *team, int scope, int world, int iters, int64_t *tok,
+                     unsigned long long *bad, int wg, void *stream)
+{
+    if (!dctx || !team || scope < SHMEMX_SCOPE_THREAD || scope > SHMEMX_SCOPE_WG || iters < 0 || wg < 64 ||
+        wg > 256 || wg % 64 || !bad)
+        return -1;
+    hipLaunchKernelGGL(k_user_barrier, dim3(team->size), dim3(wg), 0, (hipStream_t)stream,
+                       (const shmemx_dctx_pub_t *)dctx, *team, scope, world, iters, tok, bad);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // extern "C"

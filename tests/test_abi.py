@@ -61,7 +61,7 @@ def test_binding_declares_exactly_the_header():
 
 STRUCTS = {"Desc": "shmemx_desc_t", "Caps": "shmemx_caps_t", "Launch": "shmemx_launch_t", "Tune": "shmemx_tune_t",
            "ProgressCfg": "shmemx_progress_cfg_t", "Completion": "shmemx_completion_t", "Request": "shmemx_request_t",
-           "ServeStats": "shmemx_serve_stats_t"}
+           "ServeStats": "shmemx_serve_stats_t", "DTeam": "shmemx_dteam_t"}
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -70,7 +70,7 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2607_08006_amd import _native
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vshmem.h"', "int main(void) {"]
     for py, c in STRUCTS.items():
-        lines.append(f'  printf("{py} size %zu\\n", sizeof({c}));')
+        lines.append(f'  printf("{py} .sizeof %zu\\n", sizeof({c}));')
         for f, _ in getattr(_native, py)._fields_:
             lines.append(f'  printf("{py} {f} %zu\\n", offsetof({c}, {f}));')
     lines += ["  return 0;", "}"]
@@ -82,7 +82,7 @@ def test_struct_layouts_match_header(tmp_path):
     got = {tuple(x.split()[:2]): int(x.split()[2]) for x in out if x}
     for py in STRUCTS:
         cls = getattr(_native, py)
-        assert got[(py, "size")] == ctypes.sizeof(cls), py
+        assert got[(py, ".sizeof")] == ctypes.sizeof(cls), py
         for f, _ in cls._fields_:
             assert got[(py, f)] == getattr(cls, f).offset, (py, f)
 
@@ -110,6 +110,7 @@ def test_calls_before_init_fail_cleanly():
     caps = v.Caps()
     assert lib.shmem_query_capabilities(0, ctypes.byref(caps)) == v.ERR_STATE
     assert lib.shmemx_device_errors() == v.ERR_STATE
+    assert lib.shmemx_team_device(0, ctypes.byref(v.DTeam())) == v.ERR_STATE
     assert lib.shmemx_init_attach(None, 1 << 21, 1, None) == v.ERR_ARG
     assert lib.shmemx_init_attach(ctypes.c_void_p(1 << 21), 3 << 20, 2, None) == v.ERR_ARG   # odd split
     assert lib.shmemx_strerror(v.ERR_TIMEOUT).decode() == "timed out"

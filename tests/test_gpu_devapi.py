@@ -1,0 +1,177 @@
+"""GPU parity: the header-only device API called from user-style kernels
+(tests/devapi/user_kernels.hip, built into its own library that does not link
+libvshmem.so).  Collectives at work-group and grid scope, several of them
+chained in one kernel, and team barriers at thread, wavefront and work-group
+scope, checked against the CPU oracle bit for bit."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workload as W
+from tests.gpu_helpers import assert_no_device_errors, download, heap, torch, upload
+
+pytestmark = pytest.mark.gpu
+
+LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "devapi", "libvshmem_usertest.so")
+BROADCAST, FCOLLECT, ALLTOALL, REDUCE = 0, 1, 2, 3
+ES = {oracle.DT_INT64: 8, oracle.DT_FP32: 4, oracle.DT_BF16: 2}
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        raise RuntimeError(f"{LIB} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    lib.usertest_collective.argtypes = [vp, vp, i32, i32, i32, vp, vp, sz, i32, i32, i32, vp, vp]
+    lib.usertest_pipeline.argtypes = [vp, vp, vp, vp, vp, vp, sz, sz, i32, i32, vp]
+    lib.usertest_barrier.argtypes = [vp, vp, i32, i32, i32, vp, vp, i32, vp]
+    for f in (lib.usertest_collective, lib.usertest_pipeline, lib.usertest_barrier):
+        f.restype = i32
+    return lib
+
+
+def _collective(lib, v, team, kind, dest, src, n, root=0, dt=0, rop=0, nwgs=1, wg=256, expect=0):
+    t = torch()
+    dteam = v.team_device(team)
+    status = t.full((dteam.size * nwgs,), 12345, dtype=t.int32, device="cuda")
+    rc = lib.usertest_collective(v.device_ctx(), ctypes.byref(dteam), kind, dt, rop, dest, src, n, root, nwgs, wg,
+                                 status.data_ptr(), None)
+    assert rc == 0
+    t.cuda.synchronize()
+    assert (status.cpu().numpy() == expect).all(), (kind, status.cpu().numpy()[:8])
+
+
+def _red_inputs(dt, npes, nreduce, seed):
+    gen = {oracle.DT_INT64: W.coll_i64, oracle.DT_FP32: W.coll_f32, oracle.DT_BF16: W.coll_bf16}[dt]
+    return np.stack([gen(seed, p, nreduce).view(np.uint8) for p in range(npes)])
+
+
+@pytest.mark.parametrize("npes,team_args", [(1, None), (3, None), (8, None), (9, (1, 2, 4))])
+def test_user_kernel_data_movement(npes, team_args):
+    lib = _lib()
+    with heap(npes, 4 << 20) as v:
+        team = v.TEAM_WORLD if team_args is None else v.team_split_strided(v.TEAM_WORLD, *team_args)
+        members = team_args   # the oracle takes a team as (start, stride, size)
+        tsize = v.team_n_pes(team)
+        src = v.malloc(1 << 20)
+        dst = v.malloc(2 << 20)
+        so, do = v.offset(src), v.offset(dst)
+        region = do + (2 << 20)
+        init = W.heap_fill(W.SEED_COLL + 77 * npes, npes, region)
+        for nwgs in (1, 3):
+            for n in (1, 40, 4096 + 24, 300_007):
+                root = (n + nwgs) % tsize
+                upload(init)
+                _collective(lib, v, team, BROADCAST, dst, src, n, root=root, nwgs=nwgs)
+                ref = init.copy()
+                oracle.broadcast(ref, do, so, n, root, team=members)
+                assert np.array_equal(download(region), ref), ("broadcast", n, nwgs)
+                if n * tsize > (1 << 20):
+                    continue
+                upload(init)
+                _collective(lib, v, team, FCOLLECT, dst, src, n, nwgs=nwgs)
+                ref = init.copy()
+                oracle.fcollect(ref, do, so, n, team=members)
+                assert np.array_equal(download(region), ref), ("fcollect", n, nwgs)
+                upload(init)
+                _collective(lib, v, team, ALLTOALL, dst, src, n, nwgs=nwgs)
+                ref = init.copy()
+                oracle.alltoall(ref, do, so, n, team=members)
+                assert np.array_equal(download(region), ref), ("alltoall", n, nwgs)
+        assert_no_device_errors()
+
+
+@pytest.mark.parametrize("dt", [oracle.DT_INT64, oracle.DT_FP32, oracle.DT_BF16])
+def test_user_kernel_reductions(dt):
+    lib = _lib()
+    es = ES[dt]
+    for npes in (1, 5, 13):
+        with heap(npes, 2 << 20) as v:
+            nmax = 40_003
+            src = v.malloc(nmax * es)
+            dst = v.malloc(nmax * es)
+            so, do = v.offset(src), v.offset(dst)
+            region = do + nmax * es
+            for nreduce in (1, 1001, nmax):
+                init = np.zeros((npes, region), dtype=np.uint8)
+                init[:, so:so + nreduce * es] = _red_inputs(dt, npes, nreduce, 31 * npes + nreduce)
+                for rop in (oracle.RO_SUM, oracle.RO_MAX):
+                    for nwgs, wg in ((1, 64), (2, 256)):
+                        upload(init)
+                        _collective(lib, v, v.TEAM_WORLD, REDUCE, dst, src, nreduce, dt=dt, rop=rop, nwgs=nwgs, wg=wg)
+                        ref = init.copy()
+                        oracle.reduce(ref, dt, rop, do, so, nreduce)
+                        assert np.array_equal(download(region), ref), (dt, rop, npes, nreduce, nwgs)
+            assert_no_device_errors()
+
+
+def test_user_kernel_reduction_rejects_teams_of_512():
+    """The TREE fold keeps 9 levels: a team of 512 members is refused by every
+    caller, before any barrier, and nothing is written."""
+    lib = _lib()
+    npes = 512
+    with heap(npes, 2 << 20) as v:
+        src = v.malloc(4096)
+        dst = v.malloc(4096)
+        region = v.offset(dst) + 4096
+        init = W.heap_fill(5, npes, region)
+        upload(init)
+        _collective(lib, v, v.TEAM_WORLD, REDUCE, dst, src, 512, dt=oracle.DT_INT64, rop=oracle.RO_SUM, wg=64,
+                    expect=v.ERR_UNSUPPORTED)
+        assert np.array_equal(download(region), init)
+        assert_no_device_errors()
+
+
+def test_user_kernel_chains_collectives_with_compute():
+    """One launch: scale the local input, sum-reduce it over the team, then
+    fcollect a prefix of the sums.  The oracle runs the same three steps."""
+    lib = _lib()
+    npes, n, m = 6, 10_007, 333
+    with heap(npes, 2 << 20) as v:
+        src, x, y, z = (v.malloc(n * 8), v.malloc(n * 8), v.malloc(n * 8), v.malloc(npes * m * 8))
+        so, xo, yo, zo = (v.offset(a) for a in (src, x, y, z))
+        region = zo + npes * m * 8
+        init = W.heap_fill(W.SEED_COLL + 5, npes, region)
+        init[:, so:so + n * 8] = _red_inputs(oracle.DT_INT64, npes, n, 99)
+        for nwgs in (1, 4):
+            upload(init)
+            dteam = v.team_device(v.TEAM_WORLD)
+            assert lib.usertest_pipeline(v.device_ctx(), ctypes.byref(dteam), src, x, y, z, n, m, nwgs, 256, None) == 0
+            got = download(region)
+            ref = init.copy()
+            with np.errstate(over="ignore"):
+                for p in range(npes):
+                    s = ref[p, so:so + n * 8].view(np.int64)
+                    ref[p, xo:xo + n * 8] = (s * np.int64(p + 1)).view(np.uint8)
+            oracle.reduce(ref, oracle.DT_INT64, oracle.RO_SUM, yo, xo, n)
+            oracle.fcollect(ref, zo, yo, m * 8)
+            assert np.array_equal(got, ref), nwgs
+        assert_no_device_errors()
+
+
+@pytest.mark.parametrize("scope", [0, 1, 2])
+def test_user_kernel_barriers(scope):
+    """Tokens written before a barrier are seen by the next member after it,
+    at thread, wavefront and work-group scope, for the world and for a
+    strided team."""
+    lib = _lib()
+    t = torch()
+    npes, iters = 12, 64
+    with heap(npes, 2 << 20) as v:
+        tok = v.calloc(1, 8)
+        for team, world in ((v.TEAM_WORLD, 1), (v.team_split_strided(v.TEAM_WORLD, 2, 3, 3), 0)):
+            upload(np.zeros((npes, v.offset(tok) + 8), dtype=np.uint8))
+            bad = t.zeros(1, dtype=t.int64, device="cuda")
+            dteam = v.team_device(team)
+            assert lib.usertest_barrier(v.device_ctx(), ctypes.byref(dteam), scope, world, iters, tok,
+                                        bad.data_ptr(), 128, None) == 0
+            t.cuda.synchronize()
+            assert int(bad.item()) == 0, (scope, world)
+            words = download(v.offset(tok) + 8)[:, v.offset(tok):].view(np.int64)[:, 0]
+            members = range(npes) if world else (2, 5, 8)
+            for p in range(npes):
+                assert words[p] == (iters if p in members else 0), (scope, world, p)
+        assert_no_device_errors()
