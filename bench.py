@@ -441,6 +441,67 @@ def measure_ceilings(v, torch, L: Layout, npes: int):
     return out
 
 
+PCIE_GBS = 64.0   # PCIe 5.0 x16, one direction
+
+
+def measure_host_paths(v, torch, L: Layout, npes: int):
+    """Host-initiated operations (the host default context) and stream-
+    triggered puts, outside the timed step: blocking puts and gets of
+    256 MiB between pinned host memory and a PE, a 64 MiB put from pageable
+    memory, a 256 MiB device-to-device put executed by the copy kernel, the
+    round trip of a blocking host fetch_add, and the issue rate of 8-byte
+    stream-triggered puts."""
+    from paper_2607_08006_amd import host
+
+    def wall(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    base = v.heap_base()
+    big = int(256 * MiB * min(1.0, L.scale))
+    out = {}
+    pinned = torch.empty(big, dtype=torch.uint8).pin_memory()
+    pinned.fill_(7)
+    s = wall(lambda: host.putmem(base + L.B, pinned, big, 5))
+    out["put_pinned_256MiB_GB_s"] = round(big / s / 1e9, 2)
+    s = wall(lambda: host.getmem(pinned, base + L.B, big, 5))
+    out["get_pinned_256MiB_GB_s"] = round(big / s / 1e9, 2)
+    out["pcie_frac_put_get"] = [round(out["put_pinned_256MiB_GB_s"] / PCIE_GBS, 3),
+                                round(out["get_pinned_256MiB_GB_s"] / PCIE_GBS, 3)]
+    page = np.full(64 * MiB, 3, dtype=np.uint8)
+    s = wall(lambda: host.putmem(base + L.B, page, page.size, 6))
+    out["put_pageable_64MiB_GB_s"] = round(page.size / s / 1e9, 2)
+    del pinned, page
+    s = wall(lambda: host.putmem(base + L.B, base + L.A, big, npes - 1))
+    out["put_device_256MiB_hbm_GB_s"] = round(2 * big / s / 1e9, 1)
+    out["put_device_256MiB_hbm_frac"] = round(out["put_device_256MiB_hbm_GB_s"] / HBM_PEAK_GBS, 4)
+    word = base + L.H
+    host.int64_atomic_fetch_add(word, 1, 1)
+    ts = []
+    for _ in range(200):
+        t0 = time.perf_counter()
+        host.int64_atomic_fetch_add(word, 1, 1)
+        ts.append(time.perf_counter() - t0)
+    out["fetch_add_round_trip_us"] = {"p50": round(percentile(np.array(ts) * 1e6, 50), 1),
+                                      "p99": round(percentile(np.array(ts) * 1e6, 99), 1)}
+    stream = torch.cuda.Stream()
+    nput = 2000
+
+    def burst():
+        for i in range(nput):
+            host.putmem_on_stream(base + L.B + 8 * i, base + L.A + 8 * i, 8, i % npes, stream=stream)
+        stream.synchronize()
+    s = wall(burst, reps=2)
+    out["put_on_stream_8B_ops_s"] = round(nput / s, 0)
+    return out
+
+
 def run_config_sections(v, torch):
     """Measurements at the small configurations' own shapes, each on a heap
     of its own: the 4-PE x 1 MiB mixed program (1000 put/get of 8 B - 4 KiB
@@ -898,6 +959,9 @@ def main():
             out_rows["gups_fetch_xor_add"]["frac_of_atomic_ceiling_1GiB"] = round(
                 g / ceil["atomics_G_updates_s"]["table_1GiB"], 4)
         rec["errors_after_ceilings"] = v.device_errors()
+        log("host-initiated paths")
+        rec["host_paths"] = measure_host_paths(v, torch, L, npes)
+        rec["errors_after_host_paths"] = v.device_errors()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

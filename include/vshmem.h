@@ -159,13 +159,13 @@ typedef struct {
 typedef struct shmemx_caps {
     int32_t gpu_heap;              /* 1: a GPU-attached symmetric heap exists */
     int32_t default_heap_is_gpu;   /* 1: GPU-first; shmem_malloc == shmemg_malloc */
-    int32_t host_initiated;        /* host-issued RMA on GPU buffers (0 here) */
+    int32_t host_initiated;        /* 1: host-issued RMA, AMO, sync, collectives on GPU buffers */
     int32_t device_initiated;      /* 1: device-initiated RMA, AMO, sync */
     int32_t device_ctx_default;    /* 1: SHMEM_DEVICE_CTX_DEFAULT available */
     int32_t explicit_device_ctx;   /* 0: not provided */
     uint32_t scopes;               /* bit (1 << SHMEMX_SCOPE_*) per supported scope */
     int32_t device_collectives;    /* 1 */
-    int32_t stream_triggered;      /* 0: no _on_stream host APIs */
+    int32_t stream_triggered;      /* 1: shmemx_*_on_stream host APIs */
     uint32_t progress;             /* SHMEMX_PROGRESS_* bits */
     int32_t path;                  /* SHMEMX_PATH_* */
     int32_t ptr_domain;            /* domain of shmem_ptr results */
@@ -267,7 +267,12 @@ void shmem_team_destroy(shmem_team_t team);
 
 /* Error reporting. */
 const char *shmemx_strerror(int code);
+/* Code of the most recent failure recorded on this thread (SHMEMX_OK if
+ * none since the last clear); successful calls leave it unchanged. */
 int shmemx_last_error(void);
+/* Reset the recorded failure and its detail to SHMEMX_OK; for checking a
+ * call that returns void. */
+void shmemx_clear_last_error(void);
 /* Detail of the most recent SHMEMX_ERR_HIP: returns the hipError_t code of
  * the HIP runtime call that failed (0 when the library itself refused, e.g.
  * a kernel that cannot be resident) and, when buf is not NULL, writes a
@@ -411,6 +416,148 @@ int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, si
                               const shmemx_launch_t *launch, void *stream);
 int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const void *src, size_t nreduce,
                          const shmemx_launch_t *launch, void *stream);
+
+/* --------------------------------------------- host-initiated operations
+ * Tier 0 of Section 7: OpenSHMEM operations issued by the host on GPU-
+ * resident symmetric objects, through the host default context (Section
+ * 6.2).  The calling host thread acts for PE 0 (shmem_my_pe() == 0): a
+ * canonical symmetric address used as a local operand names PE 0's copy.
+ * Internal GPU kernels and copies on the context's own stream execute the
+ * operations (Section 6.3 allows an implementation to accelerate host-
+ * issued operations with internal kernels); the issuing agent, ordering and
+ * progress contract remain those of the host API.
+ *
+ * Operands: `dest` of a put and `source` of a get are canonical symmetric
+ * addresses, resolved on PE `pe`; the other buffer is any memory the HIP
+ * runtime can copy (pageable or pinned host memory, device memory,
+ * symmetric addresses).  Device-to-device moves run on a copy kernel;
+ * moves that touch host memory use the runtime's copies.  AMO targets and
+ * signal words are naturally aligned 8-byte symmetric words; a GPU kernel
+ * performs each AMO at device (agent) scope, so host AMOs are atomic with
+ * respect to device-initiated AMOs on the same word.
+ *
+ * Completion (Section 6.3 and the quiet table of Section 6.4): blocking
+ * calls return at completion of the operation (stronger than the local
+ * completion the paper requires; the data are visible device-wide on
+ * return).  _nbi calls return after enqueueing; their buffers must stay
+ * unchanged until shmem_quiet, which completes every operation the host
+ * context issued and makes it visible device-wide.  shmem_fence orders
+ * nothing more: the context executes its operations in issue order.
+ * Host operations are not ordered with work on other streams: GPU work that
+ * writes a local buffer or a symmetric source must have completed (stream
+ * synchronised) before the call, a kernel that consumes host-put data must
+ * be launched after shmem_quiet returns (or after the blocking call), and
+ * host reads of device-written data need the writing kernel to have
+ * finished.
+ *
+ * Collectives and barriers: the host thread acts for every member at once
+ * (all virtual PEs live in this process), so a host collective performs
+ * the whole collective, on the context's stream, and returns when it is
+ * complete on every member.  shmem_barrier_all / shmem_sync_all /
+ * shmem_team_sync complete the host context's operations (quiet); no other
+ * agent has to arrive.  Host and device collectives on one team share its
+ * barrier words: running them concurrently is undefined (Section 6.3).
+ *
+ * Errors: calls before init, non-symmetric operands, out-of-range PEs or
+ * misaligned words set shmemx_last_error() (SHMEMX_ERR_STATE or
+ * SHMEMX_ERR_ARG) and do nothing; fetching calls then return 0.  Integer
+ * returning calls return 0 on success and the negative code otherwise.
+ */
+void shmem_putmem(void *dest, const void *source, size_t nelems, int pe);
+void shmem_getmem(void *dest, const void *source, size_t nelems, int pe);
+void shmem_putmem_nbi(void *dest, const void *source, size_t nelems, int pe);
+void shmem_getmem_nbi(void *dest, const void *source, size_t nelems, int pe);
+/* Put, then update PE pe's signal word sig_addr (SHMEM_SIGNAL_SET or
+ * SHMEM_SIGNAL_ADD) once the data are complete (Section 4.3 put-with-signal). */
+void shmem_putmem_signal(void *dest, const void *source, size_t nelems, uint64_t *sig_addr, uint64_t signal,
+                         int sig_op, int pe);
+void shmem_putmem_signal_nbi(void *dest, const void *source, size_t nelems, uint64_t *sig_addr, uint64_t signal,
+                             int sig_op, int pe);
+/* The host PE's (PE 0's) signal word. */
+uint64_t shmem_signal_fetch(const uint64_t *sig_addr);
+/* Wait until PE 0's word satisfies cmp (SHMEM_CMP_*) against cmp_value and
+ * return the value seen (unsigned compare for signals, signed for int64).
+ * A GPU kernel on the context's stream polls the word; the wait is bounded
+ * by shmemx_set_wait_timeout_ns, after which SHMEMX_DEVERR_WAIT_TIMEOUT is
+ * latched and the last value seen is returned. */
+uint64_t shmem_signal_wait_until(uint64_t *sig_addr, int cmp, uint64_t cmp_value);
+void shmem_int64_wait_until(int64_t *ivar, int cmp, int64_t cmp_value);
+/* 1 if PE 0's word satisfies cmp now, else 0. */
+int shmem_int64_test(int64_t *ivar, int cmp, int64_t cmp_value);
+/* Atomics on PE pe's copy of dest (Section 2.1; relaxed, agent scope). */
+int64_t shmem_int64_atomic_fetch_add(int64_t *dest, int64_t value, int pe);
+void shmem_int64_atomic_add(int64_t *dest, int64_t value, int pe);
+int64_t shmem_int64_atomic_fetch_xor(int64_t *dest, int64_t value, int pe);
+void shmem_int64_atomic_xor(int64_t *dest, int64_t value, int pe);
+uint64_t shmem_uint64_atomic_fetch_xor(uint64_t *dest, uint64_t value, int pe);
+void shmem_uint64_atomic_xor(uint64_t *dest, uint64_t value, int pe);
+int64_t shmem_int64_atomic_compare_swap(int64_t *dest, int64_t cond, int64_t value, int pe);
+int64_t shmem_int64_atomic_fetch(const int64_t *source, int pe);
+void shmem_int64_atomic_set(int64_t *dest, int64_t value, int pe);
+int64_t shmem_int64_atomic_swap(int64_t *dest, int64_t value, int pe);
+void shmem_quiet(void);
+void shmem_fence(void);
+void shmem_barrier_all(void);
+void shmem_sync_all(void);
+int shmem_team_sync(shmem_team_t team);
+/* Collectives with the meanings of the launchers above (team-relative
+ * root; n in bytes for the data-movement routines, in elements for the
+ * reductions), run with the launchers' default shapes. */
+int shmem_broadcastmem(shmem_team_t team, void *dest, const void *source, size_t nelems, int PE_root);
+int shmem_fcollectmem(shmem_team_t team, void *dest, const void *source, size_t nelems);
+int shmem_alltoallmem(shmem_team_t team, void *dest, const void *source, size_t nelems);
+int shmem_int64_sum_reduce(shmem_team_t team, int64_t *dest, const int64_t *source, size_t nreduce);
+int shmem_int64_max_reduce(shmem_team_t team, int64_t *dest, const int64_t *source, size_t nreduce);
+int shmem_float_sum_reduce(shmem_team_t team, float *dest, const float *source, size_t nreduce);
+int shmem_float_max_reduce(shmem_team_t team, float *dest, const float *source, size_t nreduce);
+/* bf16 passed as its 16-bit pattern; fp32 accumulation, one rounding. */
+int shmemx_bfloat16_sum_reduce(shmem_team_t team, uint16_t *dest, const uint16_t *source, size_t nreduce);
+int shmemx_bfloat16_max_reduce(shmem_team_t team, uint16_t *dest, const uint16_t *source, size_t nreduce);
+
+/* ------------------------------------------- stream-triggered operations
+ * Tier 2 of Section 7 (Section 6.4): host-issued operations whose execution
+ * is ordered in the caller's HIP stream `stream` (NULL = the null stream).
+ * Each call enqueues and returns; the operation runs after everything
+ * enqueued on the stream before it and completes before anything enqueued
+ * after it starts, so a consumer later on the same stream sees its results
+ * without further calls.  The host observes completion by synchronising
+ * the stream.  The issuing agent is the host, as for the blocking calls
+ * (PE 0 for local operands).  With pageable host memory as an operand the
+ * runtime may stage the copy before the call returns.
+ *
+ * Prohibited patterns (Section 6.4 requires them to be documented):
+ *   - a wait on a stream whose condition only work enqueued later on the
+ *     same stream satisfies: it can never complete; the spin limit ends it
+ *     with SHMEMX_DEVERR_WAIT_TIMEOUT;
+ *   - a wait satisfied by work on another stream that is itself ordered
+ *     after the waiting stream (through events or the null stream): same;
+ *   - collectives or barriers of one team in flight on two streams at once,
+ *     or concurrently with device collectives of that team: they share the
+ *     team's barrier words (undefined, as in Section 6.3);
+ *   - a collective whose members' work-groups cannot be co-resident with
+ *     other kernels running at the same time on other streams: its barriers
+ *     wait for work-groups that cannot start (bounded by the spin limit).
+ * Returns 0 on success or a negative SHMEMX_ERR_* code (nothing enqueued).
+ */
+int shmemx_putmem_on_stream(void *dest, const void *source, size_t nelems, int pe, void *stream);
+int shmemx_getmem_on_stream(void *dest, const void *source, size_t nelems, int pe, void *stream);
+int shmemx_putmem_signal_on_stream(void *dest, const void *source, size_t nelems, uint64_t *sig_addr,
+                                   uint64_t signal, int sig_op, int pe, void *stream);
+/* Blocks the stream until PE 0's signal word satisfies cmp. */
+int shmemx_signal_wait_until_on_stream(uint64_t *sig_addr, int cmp, uint64_t cmp_value, void *stream);
+/* A team barrier (one work-group per member) ordered in the stream. */
+int shmemx_barrier_all_on_stream(void *stream);
+int shmemx_team_sync_on_stream(shmem_team_t team, void *stream);
+/* Nothing to enqueue: stream order already completes every earlier
+ * operation before later ones start.  Validates and returns 0. */
+int shmemx_quiet_on_stream(void *stream);
+int shmemx_broadcastmem_on_stream(shmem_team_t team, void *dest, const void *source, size_t nelems, int PE_root,
+                                  void *stream);
+int shmemx_fcollectmem_on_stream(shmem_team_t team, void *dest, const void *source, size_t nelems, void *stream);
+int shmemx_alltoallmem_on_stream(shmem_team_t team, void *dest, const void *source, size_t nelems, void *stream);
+/* dtype SHMEMX_DT_*, op SHMEMX_RED_*. */
+int shmemx_reduce_on_stream(shmem_team_t team, int dtype, int op, void *dest, const void *source, size_t nreduce,
+                            void *stream);
 
 /* ---------------------------------------------------- batched execution
  * A plan is a program of descriptors prepared once and launched many times.

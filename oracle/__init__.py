@@ -74,6 +74,9 @@ def lib():
         L.orc_gups.restype = ctypes.c_int
         L.orc_witness_check.argtypes = [vp, vp, vp, vp, u64, vp, vp, u64, u64]
         L.orc_witness_check.restype = ctypes.c_int64
+        for f in (L.orc_host_put, L.orc_host_get):
+            f.argtypes = [vp, ctypes.c_int, u64, ctypes.c_int, u64, vp, u64]
+            f.restype = ctypes.c_int
         del u8p
         _lib = L
     return _lib
@@ -107,6 +110,21 @@ def run_program(heap: np.ndarray, descs: np.ndarray, nresults: int = 0, check: b
                                1 if check else 0, err, 256)
     _check(rc, err.value.decode())
     return res[:nresults]
+
+
+def host_put(heap, pe: int, dst: int, buf: np.ndarray) -> None:
+    """Host-initiated put from a private host buffer into PE pe's copy."""
+    hp, npes, stride = _heap_args(heap)
+    b = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(lib().orc_host_put(hp, npes, stride, pe, dst, _ptr(b), b.size))
+
+
+def host_get(heap, pe: int, src: int, n: int) -> np.ndarray:
+    """Host-initiated get of PE pe's bytes [src, src + n) into a new buffer."""
+    hp, npes, stride = _heap_args(heap)
+    out = np.zeros(n, dtype=np.uint8)
+    _check(lib().orc_host_get(hp, npes, stride, pe, src, _ptr(out), n))
+    return out
 
 
 def broadcast(heap, dst, src, n, root, team=None):

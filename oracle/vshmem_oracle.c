@@ -463,6 +463,31 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------- host-memory operands
+ * Host-initiated put and get (Tier 0 of Section 7: the host issues OpenSHMEM
+ * operations on GPU-resident symmetric objects, Section 6.3).  The local
+ * operand is a private buffer of the issuing host, not a heap object:
+ *   put: H[pe][dst, dst+n) <- buf[0, n)
+ *   get: buf[0, n)         <- H[pe][src, src+n)
+ * A heap-to-heap host operation is an ordinary put/get of PE 0 (the PE the
+ * host acts for) and goes through orc_run_program.
+ */
+int orc_host_put(uint8_t *heap, int npes, uint64_t stride, int pe, uint64_t dst, const uint8_t *buf, uint64_t n)
+{
+    if (pe < 0 || pe >= npes || (!buf && n)) return ORC_ERR_ARG;
+    if (!in_heap(stride, dst, n)) return ORC_ERR_RANGE;
+    memcpy(heap + (uint64_t)pe * stride + dst, buf, n);
+    return ORC_OK;
+}
+
+int orc_host_get(const uint8_t *heap, int npes, uint64_t stride, int pe, uint64_t src, uint8_t *buf, uint64_t n)
+{
+    if (pe < 0 || pe >= npes || (!buf && n)) return ORC_ERR_ARG;
+    if (!in_heap(stride, src, n)) return ORC_ERR_RANGE;
+    memcpy(buf, heap + (uint64_t)pe * stride + src, n);
+    return ORC_OK;
+}
+
 /* --------------------------------------------------------------- teams */
 /* Team member k is PE start + k*stride_pe (OpenSHMEM strided teams). */
 static int team_pe(int start, int stride_pe, int k) { return start + k * stride_pe; }

@@ -27,6 +27,7 @@ OP_AMO_FETCH_ADD, OP_AMO_FETCH_XOR, OP_AMO_COMPARE_SWAP, OP_AMO_ADD, OP_AMO_XOR 
 OP_AMO_SET, OP_AMO_FETCH, OP_AMO_SWAP, OP_WAIT_UNTIL, OP_FENCE, OP_QUIET, OP_BARRIER_ALL = 9, 10, 11, 12, 13, 14, 15
 SCOPE_THREAD, SCOPE_WAVE, SCOPE_WG, SCOPE_GRID, SCOPE_AUTO = 0, 1, 2, 3, 255
 SIGNAL_SET, SIGNAL_ADD = 0, 1
+CMP_EQ, CMP_NE, CMP_GT, CMP_GE, CMP_LT, CMP_LE = range(6)
 DT_INT64, DT_FP32, DT_BF16 = 0, 1, 2
 RED_SUM, RED_MAX = 0, 1
 TEAM_WORLD, TEAM_SHARED, DEVICE_TEAM_WORLD, DEVICE_TEAM_SHARED = 0, 1, 2, 3

@@ -90,6 +90,7 @@ SIGNATURES = {
     "shmem_team_destroy": (None, [C.c_int32]),
     "shmemx_strerror": (C.c_char_p, [i32]),
     "shmemx_last_error": (i32, []),
+    "shmemx_clear_last_error": (None, []),
     "shmemx_device_errors": (i32, []),
     "shmemx_set_wait_timeout_ns": (i32, [u64]),
     "shmemx_rma_pattern": (i32, [i32, i32, vp, u64, u64, u64, u64, u64, u64, P(Launch), vp]),
@@ -125,6 +126,53 @@ SIGNATURES = {
     "shmemx_launch_request": (i32, [P(Desc), u64, i32, vp]),
     "shmemx_serve_run_batched": (i32, [P(Request), sz, i32, u64, u64, u64, u64, i32, u64, i32, vp, vp,
                                         P(Completion), P(ServeStats)]),
+    # host-initiated operations (host default context)
+    "shmem_putmem": (None, [vp, vp, sz, i32]),
+    "shmem_getmem": (None, [vp, vp, sz, i32]),
+    "shmem_putmem_nbi": (None, [vp, vp, sz, i32]),
+    "shmem_getmem_nbi": (None, [vp, vp, sz, i32]),
+    "shmem_putmem_signal": (None, [vp, vp, sz, vp, u64, i32, i32]),
+    "shmem_putmem_signal_nbi": (None, [vp, vp, sz, vp, u64, i32, i32]),
+    "shmem_signal_fetch": (u64, [vp]),
+    "shmem_signal_wait_until": (u64, [vp, i32, u64]),
+    "shmem_int64_wait_until": (None, [vp, i32, C.c_int64]),
+    "shmem_int64_test": (i32, [vp, i32, C.c_int64]),
+    "shmem_int64_atomic_fetch_add": (C.c_int64, [vp, C.c_int64, i32]),
+    "shmem_int64_atomic_add": (None, [vp, C.c_int64, i32]),
+    "shmem_int64_atomic_fetch_xor": (C.c_int64, [vp, C.c_int64, i32]),
+    "shmem_int64_atomic_xor": (None, [vp, C.c_int64, i32]),
+    "shmem_uint64_atomic_fetch_xor": (u64, [vp, u64, i32]),
+    "shmem_uint64_atomic_xor": (None, [vp, u64, i32]),
+    "shmem_int64_atomic_compare_swap": (C.c_int64, [vp, C.c_int64, C.c_int64, i32]),
+    "shmem_int64_atomic_fetch": (C.c_int64, [vp, i32]),
+    "shmem_int64_atomic_set": (None, [vp, C.c_int64, i32]),
+    "shmem_int64_atomic_swap": (C.c_int64, [vp, C.c_int64, i32]),
+    "shmem_quiet": (None, []),
+    "shmem_fence": (None, []),
+    "shmem_barrier_all": (None, []),
+    "shmem_sync_all": (None, []),
+    "shmem_team_sync": (i32, [C.c_int32]),
+    "shmem_broadcastmem": (i32, [C.c_int32, vp, vp, sz, i32]),
+    "shmem_fcollectmem": (i32, [C.c_int32, vp, vp, sz]),
+    "shmem_alltoallmem": (i32, [C.c_int32, vp, vp, sz]),
+    "shmem_int64_sum_reduce": (i32, [C.c_int32, vp, vp, sz]),
+    "shmem_int64_max_reduce": (i32, [C.c_int32, vp, vp, sz]),
+    "shmem_float_sum_reduce": (i32, [C.c_int32, vp, vp, sz]),
+    "shmem_float_max_reduce": (i32, [C.c_int32, vp, vp, sz]),
+    "shmemx_bfloat16_sum_reduce": (i32, [C.c_int32, vp, vp, sz]),
+    "shmemx_bfloat16_max_reduce": (i32, [C.c_int32, vp, vp, sz]),
+    # stream-triggered operations
+    "shmemx_putmem_on_stream": (i32, [vp, vp, sz, i32, vp]),
+    "shmemx_getmem_on_stream": (i32, [vp, vp, sz, i32, vp]),
+    "shmemx_putmem_signal_on_stream": (i32, [vp, vp, sz, vp, u64, i32, i32, vp]),
+    "shmemx_signal_wait_until_on_stream": (i32, [vp, i32, u64, vp]),
+    "shmemx_barrier_all_on_stream": (i32, [vp]),
+    "shmemx_team_sync_on_stream": (i32, [C.c_int32, vp]),
+    "shmemx_quiet_on_stream": (i32, [vp]),
+    "shmemx_broadcastmem_on_stream": (i32, [C.c_int32, vp, vp, sz, i32, vp]),
+    "shmemx_fcollectmem_on_stream": (i32, [C.c_int32, vp, vp, sz, vp]),
+    "shmemx_alltoallmem_on_stream": (i32, [C.c_int32, vp, vp, sz, vp]),
+    "shmemx_reduce_on_stream": (i32, [C.c_int32, i32, i32, vp, vp, sz, vp]),
     "shmemx_fill_random": (i32, [vp, u64, u64, u64, vp]),
     "shmemx_fill_typed": (i32, [vp, u64, i32, u64, u64, vp]),
     "shmemx_probe_copy": (i32, [vp, vp, u64, i32, i32, vp]),

@@ -226,6 +226,9 @@ static int finish_init(void *heap, size_t heap_bytes, int npes, hipStream_t stre
     for (int p = 0; p < npes; ++p)
         VSHMEM_HIP(hipMemsetAsync(s.base + (uint64_t)p * s.stride + s.user_bytes, 0, VSHMEM_SCRATCH_BYTES, stream));
     VSHMEM_HIP(hipMalloc((void **)&s.d_ctx, sizeof(shmemx_dctx_pub_t)));
+    VSHMEM_HIP(hipStreamCreateWithFlags(&s.host_stream, hipStreamNonBlocking));
+    VSHMEM_HIP(hipHostMalloc((void **)&s.host_words, kHostWords * sizeof(uint64_t), hipHostMallocMapped));
+    VSHMEM_HIP(hipHostGetDevicePointer((void **)&s.host_words_dev, s.host_words, 0));
     s.heap.reset(s.user_bytes);
     reset_teams();
     s.initialised = true;
@@ -308,6 +311,8 @@ void shmem_finalize(void)
     progress_release();
     if (s.d_ctx) (void)hipFree(s.d_ctx);
     if (s.d_err) (void)hipFree(s.d_err);
+    if (s.host_stream) (void)hipStreamDestroy(s.host_stream);
+    if (s.host_words) (void)hipHostFree(s.host_words);
     if (s.owns_heap && s.base) (void)hipFree(s.base);
     s = State{};
 }
@@ -389,14 +394,14 @@ int shmem_query_capabilities(shmem_team_t team, shmemx_caps_t *caps)
     memset(caps, 0, sizeof(*caps));
     caps->gpu_heap = 1;
     caps->default_heap_is_gpu = 1;
-    caps->host_initiated = 0;
+    caps->host_initiated = 1;
     caps->device_initiated = 1;
     caps->device_ctx_default = 1;
     caps->explicit_device_ctx = 0;
     caps->scopes = (1u << SHMEMX_SCOPE_THREAD) | (1u << SHMEMX_SCOPE_WAVE) | (1u << SHMEMX_SCOPE_WG) |
                    (1u << SHMEMX_SCOPE_GRID);
     caps->device_collectives = 1;
-    caps->stream_triggered = 0;
+    caps->stream_triggered = 1;
     caps->progress = SHMEMX_PROGRESS_KERNEL_LAUNCH | SHMEMX_PROGRESS_PERSISTENT_GPU;
     caps->path = SHMEMX_PATH_SINGLE_GPU_LOADSTORE;
     caps->ptr_domain = SHMEMX_PTR_DOMAIN_DEVICE;
@@ -514,6 +519,7 @@ const char *shmemx_strerror(int code)
 }
 
 int shmemx_last_error(void) { return vshmem::g_last_error; }
+void shmemx_clear_last_error(void) { vshmem::set_last_error(SHMEMX_OK); }
 
 int shmemx_device_errors(void)
 {

@@ -58,7 +58,14 @@ struct State {
     int num_cus = 256;
     SymAllocator heap;
     std::vector<Team> teams;
+    // Host default context (host-initiated operations): its own stream and
+    // a pinned page that receives fetched values.
+    hipStream_t host_stream = nullptr;
+    uint64_t *host_words = nullptr;       // host view
+    uint64_t *host_words_dev = nullptr;   // the same page as kernels address it
 };
+
+constexpr int kHostWords = 512;
 
 State &st();
 void set_last_error(int code);

@@ -111,6 +111,18 @@ def test_calls_before_init_fail_cleanly():
     assert lib.shmem_query_capabilities(0, ctypes.byref(caps)) == v.ERR_STATE
     assert lib.shmemx_device_errors() == v.ERR_STATE
     assert lib.shmemx_team_device(0, ctypes.byref(v.DTeam())) == v.ERR_STATE
+    # host-initiated and stream-triggered calls refuse before init without touching a device
+    lib.shmemx_clear_last_error()
+    assert lib.shmemx_last_error() == v.OK
+    lib.shmem_putmem(None, None, 8, 0)
+    assert lib.shmemx_last_error() == v.ERR_STATE
+    lib.shmemx_clear_last_error()
+    assert lib.shmem_int64_atomic_fetch_add(None, 1, 0) == 0 and lib.shmemx_last_error() == v.ERR_STATE
+    assert lib.shmem_broadcastmem(0, None, None, 8, 0) == v.ERR_STATE
+    assert lib.shmem_team_sync(0) == v.ERR_STATE
+    assert lib.shmemx_putmem_on_stream(None, None, 8, 0, None) == v.ERR_STATE
+    assert lib.shmemx_barrier_all_on_stream(None) == v.ERR_STATE
+    assert lib.shmemx_quiet_on_stream(None) == v.ERR_STATE
     assert lib.shmemx_init_attach(None, 1 << 21, 1, None) == v.ERR_ARG
     assert lib.shmemx_init_attach(ctypes.c_void_p(1 << 21), 3 << 20, 2, None) == v.ERR_ARG   # odd split
     assert lib.shmemx_strerror(v.ERR_TIMEOUT).decode() == "timed out"

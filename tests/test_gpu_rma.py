@@ -208,7 +208,7 @@ def test_heap_allocator_symmetry_and_queries():
         h = download(v.offset(z) + 512)
         assert not h[:, v.offset(z):v.offset(z) + 512].any()
         caps = v.query_capabilities(v.DEVICE_TEAM_WORLD)
-        assert caps["gpu_heap"] == 1 and caps["device_initiated"] == 1 and caps["stream_triggered"] == 0
+        assert caps["gpu_heap"] == 1 and caps["device_initiated"] == 1 and caps["stream_triggered"] == 1 and caps["host_initiated"] == 1
         assert caps["npes"] == 4 and caps["team_npes"] == 4 and caps["ptr_domain"] == 2
         tm = v.team_split_strided(v.DEVICE_TEAM_WORLD, 1, 2, 2)
         assert v.query_capabilities(tm)["team_start"] == 1 and v.team_n_pes(tm) == 2

@@ -128,6 +128,34 @@ def test_put_then_get_round_trip_and_byte_granularity():
     assert np.array_equal(heap[1, 113:], orig[1, 113:]) and np.array_equal(heap[1, :100], orig[1, :100])
 
 
+def test_host_put_get_agree_with_pe0_programs_and_touch_only_their_range():
+    """A host put from a private buffer equals PE 0's put from a heap region
+    holding the same bytes; a host get returns what PE 0's get would copy
+    into its own heap.  Only the named byte range changes."""
+    heap = W.heap_fill(41, 3, 512)
+    for pe, dst, n, src0 in [(2, 100, 37, 300), (0, 0, 1, 256), (1, 448, 64, 0)]:
+        buf = heap[0, src0:src0 + n].copy()
+        h1, h2 = heap.copy(), heap.copy()
+        oracle.host_put(h1, pe, dst, buf)
+        oracle.run_program(h2, _desc(W.OP_PUT, issuer=0, target=pe, src=src0, dst=dst, n=n))
+        assert np.array_equal(h1, h2), (pe, dst, n)
+        changed = np.argwhere(h1 != heap)
+        assert all(r == pe and dst <= c < dst + n for r, c in changed)
+        got = oracle.host_get(heap, pe, dst, n)
+        h3 = heap.copy()
+        oracle.run_program(h3, _desc(W.OP_GET, issuer=0, target=pe, src=dst, dst=src0, n=n))
+        assert np.array_equal(got, h3[0, src0:src0 + n])
+    # round trip, and arguments outside the heap are refused
+    h = heap.copy()
+    data = np.arange(200, dtype=np.uint8)
+    oracle.host_put(h, 1, 5, data)
+    assert np.array_equal(oracle.host_get(h, 1, 5, 200), data)
+    for bad in (lambda: oracle.host_put(h, 3, 0, data), lambda: oracle.host_put(h, 0, 400, data),
+                lambda: oracle.host_get(h, -1, 0, 8), lambda: oracle.host_get(h, 0, 500, 13)):
+        with pytest.raises(oracle.OracleError):
+            bad()
+
+
 def test_random_tiny_programs_match_exhaustive_byte_tracking():
     """Brute force on tiny heaps: track every byte's provenance (pe, offset)
     through a random conflict-free epoch and compare with the oracle."""
