@@ -162,7 +162,7 @@ typedef struct shmemx_caps {
     int32_t host_initiated;        /* 1: host-issued RMA, AMO, sync, collectives on GPU buffers */
     int32_t device_initiated;      /* 1: device-initiated RMA, AMO, sync */
     int32_t device_ctx_default;    /* 1: SHMEM_DEVICE_CTX_DEFAULT available */
-    int32_t explicit_device_ctx;   /* 0: not provided */
+    int32_t explicit_device_ctx;   /* 1: shmemx_device_ctx_create */
     uint32_t scopes;               /* bit (1 << SHMEMX_SCOPE_*) per supported scope */
     int32_t device_collectives;    /* 1 */
     int32_t stream_triggered;      /* 1: shmemx_*_on_stream host APIs */
@@ -176,7 +176,8 @@ typedef struct shmemx_caps {
     uint64_t heap_user_bytes;      /* allocatable bytes per PE */
     uint64_t heap_stride;          /* bytes between PE slices */
     int32_t debug;                 /* VSHMEM_DEBUG */
-    int32_t reserved[7];
+    int32_t max_device_ctx;        /* explicit device contexts that can be live at once */
+    int32_t reserved[6];
 } shmemx_caps_t;
 
 /* ---------------------------------------------------- init and allocation */
@@ -247,6 +248,35 @@ uint64_t shmemx_heap_user_bytes(void);
  * SHMEM_DEVICE_CTX_DEFAULT of Section 6.2), for user kernels that include
  * vshmem_device.hpp.  NULL before init. */
 const void *shmemx_device_ctx(void);
+
+/* Explicit device contexts (Section 6.2: created on the host, cached in
+ * GPU-accessible memory, passed to kernels as device-visible handles;
+ * Tier 1 of Section 7).  A context is created from a team: kernels bind it
+ * with shmemx_dctx_bind_explicit (vshmem_device.hpp) and then number PEs in
+ * that team, shmem_my_pe and shmem_n_pes answering for the team (the team
+ * contexts of OpenSHMEM).  The published record is read-only, so one
+ * context may be used by any number of threads, wavefronts and work-groups
+ * at every scope at once.  Lifetime: from create to destroy or finalise;
+ * destroy a context before its team, and not while kernels use it.
+ * Ordering: fence and quiet of a caller order and complete its operations
+ * through every context, not only the one named (on this part they are a
+ * release of the caller's stores), which is stronger than the independent
+ * ordering a context may have.  options: SHMEM_CTX_* bits, recorded for
+ * kernels to read; they change nothing here.  At most SHMEMX_MAX_DEVICE_CTX
+ * contexts are live at once (also reported by shmem_query_capabilities).
+ * create returns SHMEMX_OK, SHMEMX_ERR_STATE, SHMEMX_ERR_ARG (bad team or
+ * NULL out), SHMEMX_ERR_NOMEM (all in use) or SHMEMX_ERR_HIP.  record
+ * returns the device address of the context's record, or NULL when the
+ * handle is not live. */
+typedef int32_t shmemx_ctx_t;
+#define SHMEMX_CTX_INVALID (-1)
+#define SHMEM_CTX_SERIALIZED 1L
+#define SHMEM_CTX_PRIVATE 2L
+#define SHMEM_CTX_NOSTORE 4L
+#define SHMEMX_MAX_DEVICE_CTX 64
+int shmemx_device_ctx_create(shmem_team_t team, long options, shmemx_ctx_t *ctx);
+const void *shmemx_device_ctx_record(shmemx_ctx_t ctx);
+void shmemx_device_ctx_destroy(shmemx_ctx_t ctx);
 
 /* Strided team split (OpenSHMEM teams, Section 2.2): members are parent
  * members start, start+stride, ... (size of them).  config/config_mask are

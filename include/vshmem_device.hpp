@@ -48,34 +48,89 @@ struct shmemx_dctx_pub_t {
     int32_t debug;
 };
 
-/* The default context bound to one virtual PE. */
+/* A context bound to the virtual PE a caller acts for.  PE arguments of
+ * the operations are numbered in the context's team: argument p names
+ * world PE tstart + p * tstride.  The default context's team is the world
+ * (identity numbering); an explicit context's team is the team it was
+ * created from. */
 struct shmem_dctx_t {
     shmemx_dctx_pub_t c;
-    int32_t me;
+    int32_t me;      /* world PE the caller acts for */
+    int32_t idx;     /* its number in the context's team: shmem_my_pe */
+    int32_t tstart;
+    int32_t tstride;
+    int32_t tsize;   /* shmem_n_pes */
+    int32_t tslot;   /* the team's barrier words */
+    int64_t options; /* SHMEM_CTX_* bits it was created with */
 };
 
 /* Device teams are shmemx_dteam_t of vshmem.h. */
+
+/* An explicit device context as shmemx_device_ctx_create publishes it in
+ * device memory (the explicit contexts of Section 6.2: created on the host,
+ * passed to kernels as device-visible handles).  Read-only for kernels. */
+struct shmemx_dctx_rec_t {
+    shmemx_dctx_pub_t pub;
+    shmemx_dteam_t team;
+    int64_t options;
+};
 
 #define VSHMEM_SCRATCH_BYTES (64u << 10)
 #define VSHMEM_SYNC_SLOT_BYTES 128u
 #define VSHMEM_MAX_TEAMS 256
 
+/* The default context (SHMEM_DEVICE_CTX_DEFAULT) for world PE `me`. */
 __device__ __forceinline__ shmem_dctx_t shmemx_dctx_bind(const shmemx_dctx_pub_t &pub, int me)
 {
     shmem_dctx_t c;
     c.c = pub;
     c.me = me;
+    c.idx = me;
+    c.tstart = 0;
+    c.tstride = 1;
+    c.tsize = pub.npes;
+    c.tslot = 0;
+    c.options = 0;
     return c;
 }
 
-__device__ __forceinline__ int shmem_my_pe(const shmem_dctx_t &ctx) { return ctx.me; }
-__device__ __forceinline__ int shmem_n_pes(const shmem_dctx_t &ctx) { return ctx.c.npes; }
+/* An explicit context for its team's member `idx` (0 <= idx < team size). */
+__device__ __forceinline__ shmem_dctx_t shmemx_dctx_bind_explicit(const shmemx_dctx_rec_t &rec, int idx)
+{
+    shmem_dctx_t c;
+    c.c = rec.pub;
+    c.me = rec.team.start + idx * rec.team.stride;
+    c.idx = idx;
+    c.tstart = rec.team.start;
+    c.tstride = rec.team.stride;
+    c.tsize = rec.team.size;
+    c.tslot = rec.team.slot;
+    c.options = rec.options;
+    return c;
+}
 
-/* PE `pe`'s copy of a symmetric object: the device-domain shmem_ptr. */
+__device__ __forceinline__ int shmem_my_pe(const shmem_dctx_t &ctx) { return ctx.idx; }
+__device__ __forceinline__ int shmem_n_pes(const shmem_dctx_t &ctx) { return ctx.tsize; }
+
+/* The context's team as a device team descriptor. */
+__device__ __forceinline__ shmemx_dteam_t shmemx_ctx_team(const shmem_dctx_t &ctx)
+{
+    return shmemx_dteam_t{ctx.tstart, ctx.tstride, ctx.tsize, ctx.tslot};
+}
+
+/* PE `pe`'s copy of a symmetric object, pe numbered in the context's team:
+ * the device-domain shmem_ptr. */
 template <typename T>
 __device__ __forceinline__ T *shmem_ptr(const shmem_dctx_t &ctx, const T *sym, int pe)
 {
-    return (T *)((uint8_t *)sym + (uint64_t)pe * ctx.c.stride);
+    return (T *)((uint8_t *)sym + (uint64_t)(ctx.tstart + pe * ctx.tstride) * ctx.c.stride);
+}
+
+/* The caller's own copy of a symmetric object. */
+template <typename T>
+__device__ __forceinline__ T *shmemx_local_ptr(const shmem_dctx_t &ctx, const T *sym)
+{
+    return (T *)((uint8_t *)sym + (uint64_t)ctx.me * ctx.c.stride);
 }
 
 __device__ __forceinline__ int shmemx_team_pe(const shmemx_dteam_t &t, int k) { return t.start + k * t.stride; }
@@ -269,7 +324,7 @@ __device__ __forceinline__ void counter_barrier(const shmemx_dctx_pub_t &c, uint
 __device__ __forceinline__ void shmem_putmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
-                                                         shmem_ptr(ctx, (const uint8_t *)src, ctx.me), n, 0, 1);
+                                                         shmemx_local_ptr(ctx, (const uint8_t *)src), n, 0, 1);
 }
 __device__ __forceinline__ void shmem_putmem_nbi(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
@@ -278,7 +333,7 @@ __device__ __forceinline__ void shmem_putmem_nbi(const shmem_dctx_t &ctx, void *
 __device__ __forceinline__ void shmem_putmem_wave(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
-                                                         shmem_ptr(ctx, (const uint8_t *)src, ctx.me), n,
+                                                         shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          __lane_id(), 64);
 }
 __device__ __forceinline__ void shmem_putmem_nbi_wave(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
@@ -288,7 +343,7 @@ __device__ __forceinline__ void shmem_putmem_nbi_wave(const shmem_dctx_t &ctx, v
 __device__ __forceinline__ void shmem_putmem_nbi_wg(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
-                                                         shmem_ptr(ctx, (const uint8_t *)src, ctx.me), n,
+                                                         shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          threadIdx.x, blockDim.x);
 }
 __device__ __forceinline__ void shmem_putmem_wg(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
@@ -302,7 +357,7 @@ __device__ __forceinline__ void shmemx_putmem_grid(const shmem_dctx_t &ctx, void
                                                    int pe, int rank, int nwgs)
 {
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
-                                                         shmem_ptr(ctx, (const uint8_t *)src, ctx.me), n,
+                                                         shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          (uint64_t)rank * blockDim.x + threadIdx.x,
                                                          (uint64_t)nwgs * blockDim.x);
 }
@@ -310,7 +365,7 @@ __device__ __forceinline__ void shmemx_putmem_grid(const shmem_dctx_t &ctx, void
 /* get: my dest[0, n) <- PE `pe`'s src[0, n) */
 __device__ __forceinline__ void shmem_getmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, ctx.me),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n, 0, 1);
 }
 __device__ __forceinline__ void shmem_getmem_nbi(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
@@ -319,7 +374,7 @@ __device__ __forceinline__ void shmem_getmem_nbi(const shmem_dctx_t &ctx, void *
 }
 __device__ __forceinline__ void shmem_getmem_wave(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, ctx.me),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          __lane_id(), 64);
 }
@@ -329,7 +384,7 @@ __device__ __forceinline__ void shmem_getmem_nbi_wave(const shmem_dctx_t &ctx, v
 }
 __device__ __forceinline__ void shmem_getmem_nbi_wg(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, ctx.me),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          threadIdx.x, blockDim.x);
 }
@@ -341,7 +396,7 @@ __device__ __forceinline__ void shmem_getmem_wg(const shmem_dctx_t &ctx, void *d
 __device__ __forceinline__ void shmemx_getmem_grid(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n,
                                                    int pe, int rank, int nwgs)
 {
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, ctx.me),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          (uint64_t)rank * blockDim.x + threadIdx.x,
                                                          (uint64_t)nwgs * blockDim.x);
@@ -447,15 +502,15 @@ __device__ __forceinline__ void shmem_putmem_signal_wg(const shmem_dctx_t &ctx, 
 /* Wait on my own copy of a symmetric uint64 signal. */
 __device__ __forceinline__ uint64_t shmem_signal_wait_until(const shmem_dctx_t &ctx, uint64_t *sig, int cmp, uint64_t v)
 {
-    return vshmem_detail::spin_until<false>(ctx.c, shmem_ptr(ctx, sig, ctx.me), cmp, v);
+    return vshmem_detail::spin_until<false>(ctx.c, shmemx_local_ptr(ctx, sig), cmp, v);
 }
 __device__ __forceinline__ void shmem_int64_wait_until(const shmem_dctx_t &ctx, int64_t *ivar, int cmp, int64_t v)
 {
-    vshmem_detail::spin_until<true>(ctx.c, (uint64_t *)shmem_ptr(ctx, ivar, ctx.me), cmp, (uint64_t)v);
+    vshmem_detail::spin_until<true>(ctx.c, (uint64_t *)shmemx_local_ptr(ctx, ivar), cmp, (uint64_t)v);
 }
 __device__ __forceinline__ int shmem_int64_test(const shmem_dctx_t &ctx, int64_t *ivar, int cmp, int64_t v)
 {
-    int64_t x = (int64_t)__hip_atomic_load((uint64_t *)shmem_ptr(ctx, ivar, ctx.me), __ATOMIC_RELAXED,
+    int64_t x = (int64_t)__hip_atomic_load((uint64_t *)shmemx_local_ptr(ctx, ivar), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
     bool ok = vshmem_detail::cmp_holds_s(x, cmp, v);
     if (ok) vshmem_detail::acquire_agent();

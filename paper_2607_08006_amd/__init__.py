@@ -12,6 +12,11 @@ import ctypes as C
 from typing import Optional, Sequence
 
 import numpy as np
+# torch's GPU runtime is loaded before the native library so that one HIP
+# runtime serves both.  Loaded the other way round, with a second HIP
+# library already in the process, torch's device initialisation failed on
+# MI355X (no device).
+import torch  # noqa: F401
 
 from . import _native
 from ._native import Caps, Completion, Desc, DTeam, Launch, ProgressCfg, Request, ServeStats, Tune
@@ -211,6 +216,32 @@ def device_ctx() -> int:
     if not p:
         raise VshmemError(ERR_STATE, "shmemx_device_ctx")
     return p
+
+
+CTX_SERIALIZED, CTX_PRIVATE, CTX_NOSTORE = 1, 2, 4
+
+
+def device_ctx_create(team: int = TEAM_WORLD, options: int = 0) -> int:
+    """An explicit device context bound to `team`; its handle."""
+    h = C.c_int32(-1)
+    _check(lib.shmemx_device_ctx_create(team, options, C.byref(h)), "shmemx_device_ctx_create")
+    return h.value
+
+
+def device_ctx_record(ctx: int) -> int:
+    """Device address of an explicit context's published record."""
+    p = lib.shmemx_device_ctx_record(ctx)
+    if not p:
+        raise VshmemError(ERR_ARG, "shmemx_device_ctx_record")
+    return p
+
+
+def device_ctx_destroy(ctx: int) -> None:
+    lib.shmemx_clear_last_error()
+    lib.shmemx_device_ctx_destroy(ctx)
+    rc = lib.shmemx_last_error()
+    if rc:
+        raise VshmemError(rc, "shmemx_device_ctx_destroy")
 
 
 def team_destroy(team: int) -> None:

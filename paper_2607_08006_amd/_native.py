@@ -24,7 +24,8 @@ class Caps(C.Structure):
                 ("stream_triggered", C.c_int32), ("progress", C.c_uint32), ("path", C.c_int32),
                 ("ptr_domain", C.c_int32), ("team_npes", C.c_int32), ("team_start", C.c_int32),
                 ("team_stride", C.c_int32), ("npes", C.c_int32), ("heap_user_bytes", C.c_uint64),
-                ("heap_stride", C.c_uint64), ("debug", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("heap_stride", C.c_uint64), ("debug", C.c_int32), ("max_device_ctx", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class Launch(C.Structure):
@@ -83,6 +84,9 @@ SIGNATURES = {
     "shmemx_heap_stride": (u64, []),
     "shmemx_heap_user_bytes": (u64, []),
     "shmemx_device_ctx": (vp, []),
+    "shmemx_device_ctx_create": (i32, [C.c_int32, C.c_long, P(C.c_int32)]),
+    "shmemx_device_ctx_record": (vp, [C.c_int32]),
+    "shmemx_device_ctx_destroy": (None, [C.c_int32]),
     "shmem_team_split_strided": (i32, [C.c_int32, i32, i32, i32, vp, C.c_long, P(C.c_int32)]),
     "shmem_team_n_pes": (i32, [C.c_int32]),
     "shmemx_team_device": (i32, [C.c_int32, P(DTeam)]),

@@ -226,6 +226,7 @@ static int finish_init(void *heap, size_t heap_bytes, int npes, hipStream_t stre
     for (int p = 0; p < npes; ++p)
         VSHMEM_HIP(hipMemsetAsync(s.base + (uint64_t)p * s.stride + s.user_bytes, 0, VSHMEM_SCRATCH_BYTES, stream));
     VSHMEM_HIP(hipMalloc((void **)&s.d_ctx, sizeof(shmemx_dctx_pub_t)));
+    VSHMEM_HIP(hipMalloc((void **)&s.d_ctx_recs, sizeof(shmemx_dctx_rec_t) * SHMEMX_MAX_DEVICE_CTX));
     VSHMEM_HIP(hipStreamCreateWithFlags(&s.host_stream, hipStreamNonBlocking));
     VSHMEM_HIP(hipHostMalloc((void **)&s.host_words, kHostWords * sizeof(uint64_t), hipHostMallocMapped));
     VSHMEM_HIP(hipHostGetDevicePointer((void **)&s.host_words_dev, s.host_words, 0));
@@ -245,8 +246,14 @@ static int finish_init(void *heap, size_t heap_bytes, int npes, hipStream_t stre
 
 static int republish()
 {
+    State &s = g_state;
     shmemx_dctx_pub_t c = pub();
-    VSHMEM_HIP(hipMemcpy(g_state.d_ctx, &c, sizeof(c), hipMemcpyHostToDevice));
+    VSHMEM_HIP(hipMemcpy(s.d_ctx, &c, sizeof(c), hipMemcpyHostToDevice));
+    for (int i = 0; i < SHMEMX_MAX_DEVICE_CTX; ++i) {
+        if (!s.ctx_live[i]) continue;
+        s.ctx_recs[i].pub = c;
+        VSHMEM_HIP(hipMemcpy(s.d_ctx_recs + i, &s.ctx_recs[i], sizeof(shmemx_dctx_rec_t), hipMemcpyHostToDevice));
+    }
     return SHMEMX_OK;
 }
 
@@ -310,6 +317,7 @@ void shmem_finalize(void)
     (void)hipDeviceSynchronize();
     progress_release();
     if (s.d_ctx) (void)hipFree(s.d_ctx);
+    if (s.d_ctx_recs) (void)hipFree(s.d_ctx_recs);
     if (s.d_err) (void)hipFree(s.d_err);
     if (s.host_stream) (void)hipStreamDestroy(s.host_stream);
     if (s.host_words) (void)hipHostFree(s.host_words);
@@ -397,7 +405,8 @@ int shmem_query_capabilities(shmem_team_t team, shmemx_caps_t *caps)
     caps->host_initiated = 1;
     caps->device_initiated = 1;
     caps->device_ctx_default = 1;
-    caps->explicit_device_ctx = 0;
+    caps->explicit_device_ctx = 1;
+    caps->max_device_ctx = SHMEMX_MAX_DEVICE_CTX;
     caps->scopes = (1u << SHMEMX_SCOPE_THREAD) | (1u << SHMEMX_SCOPE_WAVE) | (1u << SHMEMX_SCOPE_WG) |
                    (1u << SHMEMX_SCOPE_GRID);
     caps->device_collectives = 1;
@@ -419,6 +428,45 @@ void *shmemx_heap_base(void) { return st().initialised ? st().base : nullptr; }
 uint64_t shmemx_heap_stride(void) { return st().initialised ? st().stride : 0; }
 uint64_t shmemx_heap_user_bytes(void) { return st().initialised ? st().user_bytes : 0; }
 const void *shmemx_device_ctx(void) { return st().initialised ? st().d_ctx : nullptr; }
+
+int shmemx_device_ctx_create(shmem_team_t team, long options, shmemx_ctx_t *ctx)
+{
+    if (int rc = check_ready()) return rc;
+    State &s = st();
+    shmemx_dteam_t t;
+    if (!ctx || team_get(team, &t) != SHMEMX_OK) {
+        set_last_error(SHMEMX_ERR_ARG);
+        return SHMEMX_ERR_ARG;
+    }
+    int i = 0;
+    while (i < SHMEMX_MAX_DEVICE_CTX && s.ctx_live[i]) ++i;
+    if (i == SHMEMX_MAX_DEVICE_CTX) {
+        set_last_error(SHMEMX_ERR_NOMEM);
+        return SHMEMX_ERR_NOMEM;
+    }
+    s.ctx_recs[i] = shmemx_dctx_rec_t{pub(), t, (int64_t)options};
+    VSHMEM_HIP(hipMemcpy(s.d_ctx_recs + i, &s.ctx_recs[i], sizeof(shmemx_dctx_rec_t), hipMemcpyHostToDevice));
+    s.ctx_live[i] = true;
+    *ctx = i;
+    return SHMEMX_OK;
+}
+
+const void *shmemx_device_ctx_record(shmemx_ctx_t ctx)
+{
+    const State &s = st();
+    if (!s.initialised || ctx < 0 || ctx >= SHMEMX_MAX_DEVICE_CTX || !s.ctx_live[ctx]) return nullptr;
+    return s.d_ctx_recs + ctx;
+}
+
+void shmemx_device_ctx_destroy(shmemx_ctx_t ctx)
+{
+    State &s = st();
+    if (!s.initialised || ctx < 0 || ctx >= SHMEMX_MAX_DEVICE_CTX || !s.ctx_live[ctx]) {
+        set_last_error(s.initialised ? SHMEMX_ERR_ARG : SHMEMX_ERR_STATE);
+        return;
+    }
+    s.ctx_live[ctx] = false;
+}
 uint64_t shmemx_wallclock_hz(void) { return st().wallclock_hz; }
 
 int shmem_team_split_strided(shmem_team_t parent, int start, int stride, int size, const void *config,

@@ -63,6 +63,10 @@ struct State {
     hipStream_t host_stream = nullptr;
     uint64_t *host_words = nullptr;       // host view
     uint64_t *host_words_dev = nullptr;   // the same page as kernels address it
+    // Explicit device contexts: published records and which are live.
+    shmemx_dctx_rec_t *d_ctx_recs = nullptr;
+    shmemx_dctx_rec_t ctx_recs[SHMEMX_MAX_DEVICE_CTX] = {};
+    bool ctx_live[SHMEMX_MAX_DEVICE_CTX] = {};
 };
 
 constexpr int kHostWords = 512;

@@ -66,8 +66,8 @@ __global__ void __launch_bounds__(256) k_user_pipeline(const shmemx_dctx_pub_t *
     const int k = (int)(blockIdx.x / (unsigned)nwgs);
     const int rank = (int)blockIdx.x - k * nwgs;
     const shmem_dctx_t ctx = shmemx_dctx_bind(*pub, shmemx_team_pe(team, k));
-    const int64_t *s = shmem_ptr(ctx, src, ctx.me);
-    int64_t *xm = shmem_ptr(ctx, x, ctx.me);
+    const int64_t *s = shmemx_local_ptr(ctx, src);
+    int64_t *xm = shmemx_local_ptr(ctx, x);
     const int64_t f = ctx.me + 1;
     for (size_t i = (size_t)rank * blockDim.x + threadIdx.x; i < n; i += (size_t)nwgs * blockDim.x) xm[i] = s[i] * f;
     // The reduction opens with a team barrier, which completes these stores.
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) k_user_barrier(const shmemx_dctx_pub_t *p
     const int k = (int)blockIdx.x;
     const shmem_dctx_t ctx = shmemx_dctx_bind(*pub, shmemx_team_pe(team, k));
     const int64_t *next = shmem_ptr(ctx, tok, shmemx_team_pe(team, (k + 1) % team.size));
-    int64_t *mine = shmem_ptr(ctx, tok, ctx.me);
+    int64_t *mine = shmemx_local_ptr(ctx, tok);
     // Who calls: thread 0 (thread scope), wavefront 0 (wave scope) or all.
     const bool caller = scope == SHMEMX_SCOPE_THREAD ? threadIdx.x == 0
                         : scope == SHMEMX_SCOPE_WAVE ? threadIdx.x < 64
@@ -108,6 +108,58 @@ __global__ void __launch_bounds__(256) k_user_barrier(const shmemx_dctx_pub_t *p
                 if (world) shmem_barrier_all_wg(ctx);
                 else shmem_team_sync_wg(ctx, team);
             }
+        }
+    }
+}
+
+// An explicit context bound to a team, one work-group per member: record
+// shmem_my_pe and shmem_n_pes, put the local block to member k + 1 (team
+// numbering), synchronise the context's team, get member k - 1's block, and
+// add one to member 0's counter, keeping the value fetched.
+__global__ void __launch_bounds__(256) k_user_ctx(const shmemx_dctx_rec_t *rec, const uint8_t *src, uint8_t *dst,
+                                                  uint8_t *back, size_t n, int64_t *ctr, int32_t *ids,
+                                                  int64_t *fetched)
+{
+    const shmem_dctx_t ctx = shmemx_dctx_bind_explicit(*rec, (int)blockIdx.x);
+    const int me = shmem_my_pe(ctx), np = shmem_n_pes(ctx);
+    if (threadIdx.x == 0) {
+        ids[2 * blockIdx.x] = me;
+        ids[2 * blockIdx.x + 1] = np;
+    }
+    shmem_putmem_wg(ctx, dst, src, n, (me + 1) % np);
+    shmem_team_sync_wg(ctx, shmemx_ctx_team(ctx));   // completes every member's put
+    shmem_getmem_wg(ctx, back, dst, n, (me + np - 1) % np);
+    if (threadIdx.x == 0) fetched[blockIdx.x] = shmem_int64_atomic_fetch_add(ctx, ctr, 1, 0);
+    shmem_quiet_wg(ctx);
+}
+
+// Ordering by fence: the producer (work-group 0, PE prod) fills its local
+// block with the round number, puts it to the consumer, fences, and sets the
+// consumer's flag to round + 1; the consumer (work-group 1, PE cons) waits
+// for the flag, checks every word it received and acknowledges on the
+// producer's flag before the next round may overwrite the block.
+__global__ void __launch_bounds__(256) k_user_fence(const shmemx_dctx_pub_t *pub, int prod, int cons, int64_t *block,
+                                                    size_t nwords, uint64_t *flag, int rounds,
+                                                    unsigned long long *bad)
+{
+    const bool producer = blockIdx.x == 0;
+    const shmem_dctx_t ctx = shmemx_dctx_bind(*pub, producer ? prod : cons);
+    int64_t *mine = shmemx_local_ptr(ctx, block);
+    for (int r = 0; r < rounds; ++r) {
+        if (producer) {
+            for (size_t i = threadIdx.x; i < nwords; i += blockDim.x) mine[i] = r;
+            __syncthreads();
+            shmem_putmem_nbi_wg(ctx, block, block, nwords * sizeof(int64_t), cons);
+            shmem_fence_wg(ctx);
+            if (threadIdx.x == 0) vshmemx_signal_update(ctx, flag, (uint64_t)r + 1, SHMEM_SIGNAL_SET, cons);
+            shmem_signal_wait_until_wg(ctx, flag, SHMEM_CMP_GE, (uint64_t)r + 1);
+        } else {
+            shmem_signal_wait_until_wg(ctx, flag, SHMEM_CMP_GE, (uint64_t)r + 1);
+            unsigned long long nb = 0;
+            for (size_t i = threadIdx.x; i < nwords; i += blockDim.x) nb += mine[i] != r;
+            if (nb) atomicAdd(bad, nb);
+            __syncthreads();
+            if (threadIdx.x == 0) vshmemx_signal_update(ctx, flag, (uint64_t)r + 1, SHMEM_SIGNAL_SET, prod);
         }
     }
 }
@@ -161,6 +213,24 @@ int usertest_barrier(const void *dctx, const shmemx_dteam_t *team, int scope, in
         return -1;
     hipLaunchKernelGGL(k_user_barrier, dim3(team->size), dim3(wg), 0, (hipStream_t)stream,
                        (const shmemx_dctx_pub_t *)dctx, *team, scope, world, iters, tok, bad);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int usertest_ctx(const void *rec, int team_size, const void *src, void *dst, void *back, size_t n, int64_t *ctr,
+                 int32_t *ids, int64_t *fetched, int wg, void *stream)
+{
+    if (!rec || team_size < 1 || wg < 64 || wg > 256 || wg % 64 || !ids || !fetched) return -1;
+    hipLaunchKernelGGL(k_user_ctx, dim3(team_size), dim3(wg), 0, (hipStream_t)stream, (const shmemx_dctx_rec_t *)rec,
+                       (const uint8_t *)src, (uint8_t *)dst, (uint8_t *)back, n, ctr, ids, fetched);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int usertest_fence(const void *dctx, int prod, int cons, int64_t *block, size_t nwords, uint64_t *flag, int rounds,
+                   unsigned long long *bad, void *stream)
+{
+    if (!dctx || prod == cons || rounds < 0 || !bad) return -1;
+    hipLaunchKernelGGL(k_user_fence, dim3(2), dim3(256), 0, (hipStream_t)stream, (const shmemx_dctx_pub_t *)dctx,
+                       prod, cons, block, nwords, flag, rounds, bad);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -4,8 +4,13 @@ oracle on the same inputs."""
 from __future__ import annotations
 
 import contextlib
+import ctypes
+import os
 
 import numpy as np
+
+USER_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "devapi", "libvshmem_usertest.so")
+_user = None
 
 
 def vs():
@@ -72,3 +77,29 @@ def out_hash(b: np.ndarray) -> int:
         z = z ^ (z >> np.uint64(31))
     return int(np.bitwise_xor.reduce(z)) if len(z) else 0
 
+
+
+def user_lib():
+    """The user-style kernels of tests/devapi (their own library, built by
+    __graft_entry__.build()); fails when it is missing."""
+    global _user
+    if _user is not None:
+        return _user
+    if not os.path.exists(USER_LIB):
+        raise RuntimeError(f"{USER_LIB} is not built; run __graft_entry__.build()")
+    vs()   # torch's runtime and libvshmem.so first, as the package arranges for itself
+    lib = ctypes.CDLL(USER_LIB)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    sigs = {
+        "usertest_collective": [vp, vp, i32, i32, i32, vp, vp, sz, i32, i32, i32, vp, vp],
+        "usertest_pipeline": [vp, vp, vp, vp, vp, vp, sz, sz, i32, i32, vp],
+        "usertest_barrier": [vp, vp, i32, i32, i32, vp, vp, i32, vp],
+        "usertest_ctx": [vp, i32, vp, vp, vp, sz, vp, vp, vp, i32, vp],
+        "usertest_fence": [vp, i32, i32, vp, sz, vp, i32, vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = i32
+    _user = lib
+    return lib

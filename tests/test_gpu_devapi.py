@@ -4,33 +4,19 @@ libvshmem.so).  Collectives at work-group and grid scope, several of them
 chained in one kernel, and team barriers at thread, wavefront and work-group
 scope, checked against the CPU oracle bit for bit."""
 import ctypes
-import os
 
 import numpy as np
 import pytest
 
 import oracle
 import workload as W
-from tests.gpu_helpers import assert_no_device_errors, download, heap, torch, upload
+from tests.gpu_helpers import assert_no_device_errors, download, heap, torch, upload, user_lib
 
 pytestmark = pytest.mark.gpu
 
-LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "devapi", "libvshmem_usertest.so")
 BROADCAST, FCOLLECT, ALLTOALL, REDUCE = 0, 1, 2, 3
 ES = {oracle.DT_INT64: 8, oracle.DT_FP32: 4, oracle.DT_BF16: 2}
-
-
-def _lib():
-    if not os.path.exists(LIB):
-        raise RuntimeError(f"{LIB} is not built; run __graft_entry__.build()")
-    lib = ctypes.CDLL(LIB)
-    vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
-    lib.usertest_collective.argtypes = [vp, vp, i32, i32, i32, vp, vp, sz, i32, i32, i32, vp, vp]
-    lib.usertest_pipeline.argtypes = [vp, vp, vp, vp, vp, vp, sz, sz, i32, i32, vp]
-    lib.usertest_barrier.argtypes = [vp, vp, i32, i32, i32, vp, vp, i32, vp]
-    for f in (lib.usertest_collective, lib.usertest_pipeline, lib.usertest_barrier):
-        f.restype = i32
-    return lib
+_lib = user_lib
 
 
 def _collective(lib, v, team, kind, dest, src, n, root=0, dt=0, rop=0, nwgs=1, wg=256, expect=0):
@@ -175,3 +161,61 @@ def test_user_kernel_barriers(scope):
             for p in range(npes):
                 assert words[p] == (iters if p in members else 0), (scope, world, p)
         assert_no_device_errors()
+
+
+@pytest.mark.parametrize("team_args", [None, (2, 3, 4), (5, 1, 1)])
+def test_explicit_context_numbers_pes_in_its_team(team_args):
+    """An explicit device context created from a team: kernels see team
+    numbering for shmem_my_pe, shmem_n_pes and every PE argument.  Puts to
+    the next member and gets from the previous one follow the oracle's
+    programs in world numbering; the contended fetch_add on member 0 hands
+    out every old value once."""
+    lib = _lib()
+    t = torch()
+    npes, n = 14, 3000
+    with heap(npes, 2 << 20) as v:
+        team = v.TEAM_WORLD if team_args is None else v.team_split_strided(v.TEAM_WORLD, *team_args)
+        start, stride, size = team_args or (0, 1, npes)
+        world = [start + k * stride for k in range(size)]
+        ctx = v.device_ctx_create(team, v.CTX_PRIVATE)
+        src, dst, back, ctr = v.malloc(n), v.malloc(n), v.malloc(n), v.calloc(1, 8)
+        so, do, bo, co = (v.offset(a) for a in (src, dst, back, ctr))
+        region = co + 8
+        init = W.heap_fill(W.SEED_SMALL + size, npes, region)
+        init[:, co:co + 8] = 0
+        upload(init)
+        ids = t.zeros(2 * size, dtype=t.int32, device="cuda")
+        fetched = t.zeros(size, dtype=t.int64, device="cuda")
+        assert lib.usertest_ctx(v.device_ctx_record(ctx), size, src, dst, back, n, ctr, ids.data_ptr(),
+                                fetched.data_ptr(), 128, None) == 0
+        got = download(region)
+        ref = init.copy()
+        oracle.run_program(ref, np.concatenate([
+            W.descs([(W.OP_PUT, W.SCOPE_WG, 0, world[k], world[(k + 1) % size], W.NO_RESULT, so, do, n, 0, 0)])
+            for k in range(size)]))
+        oracle.run_program(ref, np.concatenate([
+            W.descs([(W.OP_GET, W.SCOPE_WG, 0, world[k], world[(k - 1) % size], W.NO_RESULT, do, bo, n, 0, 0)])
+            for k in range(size)]))
+        ref[world[0], co:co + 8] = np.array([size], dtype=np.int64).view(np.uint8)
+        assert np.array_equal(got, ref)
+        assert ids.cpu().numpy().tolist() == [x for k in range(size) for x in (k, size)]
+        assert sorted(fetched.cpu().numpy().tolist()) == list(range(size))
+        v.device_ctx_destroy(ctx)
+        with pytest.raises(v.VshmemError):
+            v.device_ctx_record(ctx)
+        assert_no_device_errors()
+
+
+def test_explicit_context_pool_and_capabilities():
+    with heap(3, 2 << 20) as v:
+        caps = v.query_capabilities(v.TEAM_WORLD)
+        assert caps["explicit_device_ctx"] == 1 and caps["max_device_ctx"] == 64
+        hs = [v.device_ctx_create(v.TEAM_WORLD) for _ in range(64)]
+        assert sorted(hs) == list(range(64))
+        with pytest.raises(v.VshmemError) as e:
+            v.device_ctx_create(v.TEAM_WORLD)
+        assert e.value.code == v.ERR_NOMEM
+        v.device_ctx_destroy(hs[10])
+        assert v.device_ctx_create(v.TEAM_WORLD) == 10
+        with pytest.raises(v.VshmemError):
+            v.device_ctx_create(999)
