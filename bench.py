@@ -150,7 +150,7 @@ def build_rows(v, torch, L: Layout, npes: int, want):
     f, b = rma(v.OP_PUT, v.SCOPE_GRID, perm, huge, 4, 256, flags=deep)
     add("put_grid_64MiB_perm", f, b, kernel="k_rma_pattern<3,true,true,8>")
     f, b = rma(v.OP_PUT, v.SCOPE_WAVE, perm, 4096, 4, 256, flags=v.LAUNCH_NONTEMPORAL)
-    add("put_wave_4KiB_perm", f, b)
+    add("put_wave_4KiB_perm", f, b, kernel="k_rma_pattern<1,true,true,4>")
     f, b = rma(v.OP_GET, v.SCOPE_THREAD, ring, 64, 4, 256)
     add("get_thread_64B_ring", f, b)
     f, b = rma(v.OP_PUT, v.SCOPE_THREAD, perm, 8, 4, 1024)
@@ -178,17 +178,21 @@ def build_rows(v, torch, L: Layout, npes: int, want):
     add("alltoall_1MiB_fp32", lambda: v.alltoallmem(L.addr(L.B), L.addr(L.C), blk), 2 * npes * npes * blk,
         kernel="k_alltoall<true,8>")
     fc = int(4 * MiB * min(1.0, scale))
-    add("fcollect_4MiB", lambda: v.fcollectmem(L.addr(L.B), L.addr(L.C), fc), npes * fc + npes * npes * fc)
+    add("fcollect_4MiB", lambda: v.fcollectmem(L.addr(L.B), L.addr(L.C), fc), npes * fc + npes * npes * fc,
+        kernel="k_fcollect<false>")
     bc = L.D - L.C
-    add("broadcast_256MiB", lambda: v.broadcastmem(L.addr(L.B), L.addr(L.C), bc, 0), bc + npes * bc)
+    add("broadcast_256MiB", lambda: v.broadcastmem(L.addr(L.B), L.addr(L.C), bc, 0), bc + npes * bc,
+        kernel="k_broadcast<false>")
     nred = (L.E - L.D) // 8
-    for dt, src, es, tag in ((v.DT_INT64, L.D, 8, "i64"), (v.DT_FP32, L.E, 4, "f32"), (v.DT_BF16, L.F, 2, "bf16")):
+    for dt, src, es, tag, codec in ((v.DT_INT64, L.D, 8, "i64", "CodecI64"), (v.DT_FP32, L.E, 4, "f32", "CodecF32"),
+                                    (v.DT_BF16, L.F, 2, "bf16", "CodecBF16")):
         n = min(nred, (L.G - src) // es) if dt != v.DT_INT64 else nred
         add(f"reduce_sum_{tag}", (lambda dt=dt, src=src, n=n: v.reduce(dt, v.RED_SUM, L.addr(L.B), L.addr(src), n)),
-            2 * npes * n * es)
-    add("reduce_max_i64", lambda: v.reduce(v.DT_INT64, v.RED_MAX, L.addr(L.B), L.addr(L.D), nred), 2 * npes * nred * 8)
+            2 * npes * n * es, kernel=f"k_reduce<{codec},OpSum,true>")
+    add("reduce_max_i64", lambda: v.reduce(v.DT_INT64, v.RED_MAX, L.addr(L.B), L.addr(L.D), nred), 2 * npes * nred * 8,
+        kernel="k_reduce<CodecI64,OpMax,true>")
     add("reduce_max_f32", lambda: v.reduce(v.DT_FP32, v.RED_MAX, L.addr(L.B), L.addr(L.E), nred),
-        2 * npes * nred * 4)
+        2 * npes * nred * 4, kernel="k_reduce<CodecF32,OpMax,true>")
     return rows
 
 
@@ -283,10 +287,16 @@ def percentile(a, q):
 KERNEL_SOURCES = {
     "k_rma_pattern": ["paper_2607_08006_amd/csrc/rma.hip"],
     "k_alltoall": ["paper_2607_08006_amd/csrc/coll.hip"],
+    "k_broadcast": ["paper_2607_08006_amd/csrc/coll.hip"],
+    "k_fcollect": ["paper_2607_08006_amd/csrc/coll.hip"],
+    "k_reduce": ["paper_2607_08006_amd/csrc/coll.hip"],
 }
-COMMON_SOURCES = ["include/vshmem.h", "include/vshmem_device.hpp", "paper_2607_08006_amd/csrc/runtime.hpp",
-                  "paper_2607_08006_amd/csrc/runtime.cpp"]
+COMMON_SOURCES = ["include/vshmem.h", "include/vshmem_device.hpp", "paper_2607_08006_amd/csrc/runtime.hpp"]
 PROFILE_DIR = os.path.join(ROOT, "profiles")
+# Rows whose kernels get HBM counter passes (FETCH_SIZE, WRITE_SIZE).
+PMC_ROWS = ["put_wg_16MiB_ring", "get_wg_16MiB_perm", "put_grid_64MiB_perm", "put_wave_4KiB_perm",
+            "alltoall_1MiB_fp32", "fcollect_4MiB", "broadcast_256MiB", "reduce_sum_i64", "reduce_sum_f32",
+            "reduce_sum_bf16"]
 
 
 def kernel_digest(kernel: str) -> str:
@@ -343,7 +353,7 @@ def summarize_profiles(prof_dir: str, probe_mib: int) -> None:
     trace_cmd = (f"rocprofv3 --kernel-trace --stats -d {rel}/trace -o bench --output-format csv "
                  "-- python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras")
     pmc_cmd = ("rocprofv3 --pmc {ctr} -d " + rel + "/pmc_{ctr} -o pmc --output-format csv -- python3 bench.py "
-               "--rows put_wg_16MiB_ring,get_wg_16MiB_perm,alltoall_1MiB_fp32 --steps 2 --warmup 1 "
+               "--rows " + ",".join(PMC_ROWS) + " --steps 2 --warmup 1 "
                f"--no-cpu-baseline --probe-copy-mib {probe_mib}")
     stats = _csv_rows(os.path.join(prof_dir, "trace", "**", "*kernel_stats.csv"))
     if stats:
@@ -877,6 +887,11 @@ def main():
         if r.bytes:
             d["GB_s"] = round(r.bytes / (ms * 1e-3) / 1e9, 2)
             d["hbm_frac"] = round(d["GB_s"] / HBM_PEAK_GBS, 4)
+            tr = pmc_traffic(r.kernel, r.bytes) if r.kernel else None
+            if tr:
+                # counter-measured HBM bytes per launch against the algorithmic bytes
+                d["pmc_traffic_bytes"] = tr
+                d["traffic_over_algorithmic"] = round(tr / r.bytes, 4)
         if r.ops:
             d["Mops_s"] = round(r.ops / (ms * 1e-3) / 1e6, 2)
         out_rows[r.name] = d

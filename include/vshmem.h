@@ -233,6 +233,11 @@ void shmem_free(void *ptr);
  * the host (access domain reported as SHMEMX_PTR_DOMAIN_DEVICE).  NULL if
  * `sym` is not inside the heap or pe is out of range. */
 void *shmem_ptr(const void *sym, int pe);
+/* The team-scoped form (Section 6.3: a host-callable team pointer query
+ * with a stated access domain): member `pe` of `team` (team numbering).
+ * Same domain and NULL cases as shmem_ptr, plus NULL for a team that does
+ * not exist. */
+void *shmem_team_ptr(shmem_team_t team, const void *dest, int pe);
 
 /* Capability query for a team (Section 6.5).  Returns SHMEMX_OK or an
  * error for an unknown team / NULL out. */

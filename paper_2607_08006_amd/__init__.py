@@ -186,6 +186,10 @@ def ptr(sym: int, pe: int) -> Optional[int]:
     return lib.shmem_ptr(sym, pe)
 
 
+def team_ptr(team: int, sym: int, pe: int) -> Optional[int]:
+    return lib.shmem_team_ptr(team, sym, pe)
+
+
 def query_capabilities(team: int = TEAM_WORLD) -> dict:
     c = Caps()
     _check(lib.shmem_query_capabilities(team, C.byref(c)), "shmem_query_capabilities")

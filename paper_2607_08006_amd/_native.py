@@ -79,6 +79,7 @@ SIGNATURES = {
     "shmem_align": (vp, [sz, sz]),
     "shmem_free": (None, [vp]),
     "shmem_ptr": (vp, [vp, i32]),
+    "shmem_team_ptr": (vp, [C.c_int32, vp, i32]),
     "shmem_query_capabilities": (i32, [C.c_int32, P(Caps)]),
     "shmemx_heap_base": (vp, []),
     "shmemx_heap_stride": (u64, []),

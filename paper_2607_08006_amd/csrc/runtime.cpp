@@ -381,6 +381,13 @@ void shmem_free(void *ptr)
     if (a < b || a - b >= s.user_bytes || !s.heap.free(a - b)) set_last_error(SHMEMX_ERR_ARG);
 }
 
+void *shmem_team_ptr(shmem_team_t team, const void *dest, int pe)
+{
+    shmemx_dteam_t t;
+    if (!st().initialised || team_get(team, &t) != SHMEMX_OK || pe < 0 || pe >= t.size) return nullptr;
+    return shmem_ptr(dest, t.start + pe * t.stride);
+}
+
 void *shmem_ptr(const void *sym, int pe)
 {
     State &s = st();

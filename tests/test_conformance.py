@@ -187,6 +187,9 @@ def test_pointer_accessibility():
             view = v.heap_view()[pe, v.offset(x):v.offset(x) + 64]
             assert view.data_ptr() == p and view.is_cuda
         assert v.ptr(x, 4) is None and v.ptr(x, -1) is None
+        tm = v.team_split_strided(v.TEAM_WORLD, 1, 2, 2)    # PEs 1 and 3
+        assert v.team_ptr(tm, x, 1) == v.ptr(x, 3) and v.team_ptr(tm, x, 2) is None
+        assert v.team_ptr(999, x, 0) is None
         assert v.ptr(torch().zeros(8, device="cuda").data_ptr(), 0) is None
 
 
