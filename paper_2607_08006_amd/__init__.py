@@ -12,10 +12,10 @@ import ctypes as C
 from typing import Optional, Sequence
 
 import numpy as np
-# torch's GPU runtime is loaded before the native library so that one HIP
-# runtime serves both.  Loaded the other way round, with a second HIP
-# library already in the process, torch's device initialisation failed on
-# MI355X (no device).
+# torch (which carries its own HIP runtime) is loaded before the native
+# library: with another HIP library already in the process, loading the
+# native library between torch's import and torch's device initialisation
+# made that initialisation fail on MI355X (no device).
 import torch  # noqa: F401
 
 from . import _native
