@@ -53,6 +53,10 @@ extern "C" {
 #define SHMEMX_DEVERR_BAD_DESC 0x2u       /* descriptor outside the heap or bad op */
 #define SHMEMX_DEVERR_PROGRESS_IDLE 0x4u  /* progress kernel stopped by its idle limit */
 #define SHMEMX_DEVERR_PROGRESS_STATE 0x8u /* progress kernel saw an inconsistent request record */
+/* With VSHMEM_DEBUG set at init the device API checks its arguments; an
+ * operation that fails a check latches one of these and does nothing. */
+#define SHMEMX_DEVERR_BAD_ADDRESS 0x10u   /* operand outside the symmetric heap, misaligned word, PE out of range */
+#define SHMEMX_DEVERR_NONUNIFORM 0x20u    /* participants of a _wave/_wg/_grid call passed different arguments */
 
 /* -------------------------------------------------- operations and scopes
  * Operation codes of a descriptor (Section 2.1 operation list; put with

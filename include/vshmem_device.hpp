@@ -317,12 +317,98 @@ __device__ __forceinline__ void counter_barrier(const shmemx_dctx_pub_t &c, uint
 
 } // namespace vshmem_detail
 
+/* ---------------------------------------------------------- debug checks */
+/* Contexts published with debug set (VSHMEM_DEBUG at init) check every
+ * operation's arguments: operands inside PE 0's user heap (canonical
+ * symmetric addresses), 8-byte words aligned, PE numbers inside the
+ * context's team, and for _wave/_wg/_grid calls one argument set across the
+ * participants.  A failed check latches SHMEMX_DEVERR_BAD_ADDRESS or
+ * SHMEMX_DEVERR_NONUNIFORM and the operation does nothing (every
+ * participant of a scoped call takes the same decision).  Without debug the
+ * checks reduce to one uniform branch. */
+namespace vshmem_detail {
+
+__device__ __forceinline__ uint64_t first_lane64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ bool in_user_heap(const shmem_dctx_t &ctx, const void *p, uint64_t n)
+{
+    const uint8_t *q = (const uint8_t *)p;
+    if (q < ctx.c.base) return false;
+    const uint64_t off = (uint64_t)(q - ctx.c.base);
+    return off <= ctx.c.user_bytes && n <= ctx.c.user_bytes - off;
+}
+
+__device__ __forceinline__ bool pe_in_team(const shmem_dctx_t &ctx, int pe) { return pe >= 0 && pe < ctx.tsize; }
+
+__device__ __forceinline__ bool checked(const shmem_dctx_t &ctx, bool ok)
+{
+    if (!ok) latch_error(ctx.c, SHMEMX_DEVERR_BAD_ADDRESS);
+    return ok;
+}
+
+/* A put or get of n bytes with PE pe (both operands symmetric). */
+__device__ __forceinline__ bool rma_ok(const shmem_dctx_t &ctx, const void *dest, const void *src, uint64_t n, int pe)
+{
+    return !ctx.c.debug || checked(ctx, in_user_heap(ctx, dest, n) && in_user_heap(ctx, src, n) && pe_in_team(ctx, pe));
+}
+
+/* A naturally aligned symmetric 8-byte word on PE pe. */
+__device__ __forceinline__ bool word_ok(const shmem_dctx_t &ctx, const void *w, int pe)
+{
+    return !ctx.c.debug || checked(ctx, ((uintptr_t)w & 7) == 0 && in_user_heap(ctx, w, 8) && pe_in_team(ctx, pe));
+}
+
+/* Wavefront scope: every lane passed lane 0's arguments and found them
+ * valid.  All lanes return the same answer. */
+__device__ __forceinline__ bool wave_agree(const shmem_dctx_t &ctx, bool ok, uint64_t a, uint64_t b, uint64_t c,
+                                           uint64_t d)
+{
+    if (!ctx.c.debug) return true;
+    const bool same = a == first_lane64(a) && b == first_lane64(b) && c == first_lane64(c) && d == first_lane64(d);
+    if (__ballot(!same) != 0 && __lane_id() == 0) latch_error(ctx.c, SHMEMX_DEVERR_NONUNIFORM);
+    return __ballot(!(ok && same)) == 0;
+}
+
+/* Work-group scope: the same through LDS.  Every thread must call it. */
+__device__ __forceinline__ bool wg_agree(const shmem_dctx_t &ctx, bool ok, uint64_t a, uint64_t b, uint64_t c,
+                                         uint64_t d)
+{
+    if (!ctx.c.debug) return true;
+    __shared__ uint64_t ref[4];
+    __shared__ uint32_t verdict;   // bit 0: a thread found its arguments invalid; bit 1: arguments differ
+    if (threadIdx.x == 0) {
+        ref[0] = a;
+        ref[1] = b;
+        ref[2] = c;
+        ref[3] = d;
+        verdict = 0;
+    }
+    __syncthreads();
+    const bool same = a == ref[0] && b == ref[1] && c == ref[2] && d == ref[3];
+    if (!ok || !same) atomicOr(&verdict, (ok ? 0u : 1u) | (same ? 0u : 2u));
+    __syncthreads();
+    const uint32_t v = __builtin_amdgcn_readfirstlane(verdict);
+    __syncthreads();   // ref and verdict are free for the next call
+    if ((v & 2u) && threadIdx.x == 0) latch_error(ctx.c, SHMEMX_DEVERR_NONUNIFORM);
+    return v == 0;
+}
+
+} // namespace vshmem_detail
+
+#define VSHMEM_U64(x) ((uint64_t)(uintptr_t)(x))
+
 /* ------------------------------------------------------------ put / get */
 #define VSHMEM_COPY_UNROLL 4
 
 /* put: PE `pe`'s dest[0, n) <- my src[0, n) */
 __device__ __forceinline__ void shmem_putmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
+    if (!vshmem_detail::rma_ok(ctx, dest, src, n, pe)) return;
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
                                                          shmemx_local_ptr(ctx, (const uint8_t *)src), n, 0, 1);
 }
@@ -332,6 +418,9 @@ __device__ __forceinline__ void shmem_putmem_nbi(const shmem_dctx_t &ctx, void *
 }
 __device__ __forceinline__ void shmem_putmem_wave(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
+    if (!vshmem_detail::wave_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest),
+                                   VSHMEM_U64(src), n, (uint64_t)pe))
+        return;
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
                                                          shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          __lane_id(), 64);
@@ -342,6 +431,9 @@ __device__ __forceinline__ void shmem_putmem_nbi_wave(const shmem_dctx_t &ctx, v
 }
 __device__ __forceinline__ void shmem_putmem_nbi_wg(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
+    if (!vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest), VSHMEM_U64(src),
+                                 n, (uint64_t)pe))
+        return;
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
                                                          shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          threadIdx.x, blockDim.x);
@@ -352,10 +444,14 @@ __device__ __forceinline__ void shmem_putmem_wg(const shmem_dctx_t &ctx, void *d
     __syncthreads();
 }
 /* Grid scope: the nwgs work-groups acting for the PE (this one is `rank`)
- * share the message; each returns when its own share is locally complete. */
+ * share the message; each returns when its own share is locally complete.
+ * Debug checks compare arguments within each work-group. */
 __device__ __forceinline__ void shmemx_putmem_grid(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n,
                                                    int pe, int rank, int nwgs)
 {
+    if (!vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest), VSHMEM_U64(src),
+                                 n, ((uint64_t)(uint32_t)nwgs << 32) | (uint32_t)pe))
+        return;
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
                                                          shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          (uint64_t)rank * blockDim.x + threadIdx.x,
@@ -365,6 +461,7 @@ __device__ __forceinline__ void shmemx_putmem_grid(const shmem_dctx_t &ctx, void
 /* get: my dest[0, n) <- PE `pe`'s src[0, n) */
 __device__ __forceinline__ void shmem_getmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
+    if (!vshmem_detail::rma_ok(ctx, dest, src, n, pe)) return;
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n, 0, 1);
 }
@@ -374,6 +471,9 @@ __device__ __forceinline__ void shmem_getmem_nbi(const shmem_dctx_t &ctx, void *
 }
 __device__ __forceinline__ void shmem_getmem_wave(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
+    if (!vshmem_detail::wave_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest),
+                                   VSHMEM_U64(src), n, (uint64_t)pe))
+        return;
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          __lane_id(), 64);
@@ -384,6 +484,9 @@ __device__ __forceinline__ void shmem_getmem_nbi_wave(const shmem_dctx_t &ctx, v
 }
 __device__ __forceinline__ void shmem_getmem_nbi_wg(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
+    if (!vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest), VSHMEM_U64(src),
+                                 n, (uint64_t)pe))
+        return;
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          threadIdx.x, blockDim.x);
@@ -396,6 +499,9 @@ __device__ __forceinline__ void shmem_getmem_wg(const shmem_dctx_t &ctx, void *d
 __device__ __forceinline__ void shmemx_getmem_grid(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n,
                                                    int pe, int rank, int nwgs)
 {
+    if (!vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest), VSHMEM_U64(src),
+                                 n, ((uint64_t)(uint32_t)nwgs << 32) | (uint32_t)pe))
+        return;
     vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          (uint64_t)rank * blockDim.x + threadIdx.x,
@@ -417,33 +523,40 @@ __device__ __forceinline__ void shmem_fence_wg(const shmem_dctx_t &ctx) { shmem_
 
 __device__ __forceinline__ int64_t shmem_int64_atomic_fetch_add(const shmem_dctx_t &ctx, int64_t *dest, int64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return 0;
     return (int64_t)__hip_atomic_fetch_add(VSHMEM_AMO_PTR(uint64_t), (uint64_t)v, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void shmem_int64_atomic_add(const shmem_dctx_t &ctx, int64_t *dest, int64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return;
     __hip_atomic_fetch_add(VSHMEM_AMO_PTR(uint64_t), (uint64_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t shmem_uint64_atomic_fetch_xor(const shmem_dctx_t &ctx, uint64_t *dest, uint64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return 0;
     return __hip_atomic_fetch_xor(VSHMEM_AMO_PTR(uint64_t), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int64_t shmem_int64_atomic_fetch_xor(const shmem_dctx_t &ctx, int64_t *dest, int64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return 0;
     return (int64_t)__hip_atomic_fetch_xor(VSHMEM_AMO_PTR(uint64_t), (uint64_t)v, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void shmem_uint64_atomic_xor(const shmem_dctx_t &ctx, uint64_t *dest, uint64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return;
     __hip_atomic_fetch_xor(VSHMEM_AMO_PTR(uint64_t), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void shmem_int64_atomic_xor(const shmem_dctx_t &ctx, int64_t *dest, int64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return;
     __hip_atomic_fetch_xor(VSHMEM_AMO_PTR(uint64_t), (uint64_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int64_t shmem_int64_atomic_compare_swap(const shmem_dctx_t &ctx, int64_t *dest, int64_t cond,
                                                                    int64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return 0;
     uint64_t expected = (uint64_t)cond;
     __hip_atomic_compare_exchange_strong(VSHMEM_AMO_PTR(uint64_t), &expected, (uint64_t)v, __ATOMIC_RELAXED,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -451,15 +564,18 @@ __device__ __forceinline__ int64_t shmem_int64_atomic_compare_swap(const shmem_d
 }
 __device__ __forceinline__ int64_t shmem_int64_atomic_fetch(const shmem_dctx_t &ctx, const int64_t *dest, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return 0;
     return (int64_t)__hip_atomic_load((uint64_t *)shmem_ptr(ctx, (const uint8_t *)dest, pe), __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void shmem_int64_atomic_set(const shmem_dctx_t &ctx, int64_t *dest, int64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return;
     __hip_atomic_store(VSHMEM_AMO_PTR(uint64_t), (uint64_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int64_t shmem_int64_atomic_swap(const shmem_dctx_t &ctx, int64_t *dest, int64_t v, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, dest, pe)) return 0;
     return (int64_t)__hip_atomic_exchange(VSHMEM_AMO_PTR(uint64_t), (uint64_t)v, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -467,6 +583,7 @@ __device__ __forceinline__ int64_t shmem_int64_atomic_swap(const shmem_dctx_t &c
 /* ------------------------------------------------- signals and waiting */
 __device__ __forceinline__ void vshmemx_signal_update(const shmem_dctx_t &ctx, uint64_t *sig, uint64_t v, int sig_op, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, sig, pe)) return;
     uint64_t *s = shmem_ptr(ctx, sig, pe);
     if (sig_op == 1)
         __hip_atomic_fetch_add(s, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -479,6 +596,7 @@ __device__ __forceinline__ void vshmemx_signal_update(const shmem_dctx_t &ctx, u
 __device__ __forceinline__ void shmem_putmem_signal(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n,
                                                     uint64_t *sig, uint64_t sigval, int sig_op, int pe)
 {
+    if (!vshmem_detail::word_ok(ctx, sig, pe) || !vshmem_detail::rma_ok(ctx, dest, src, n, pe)) return;
     shmem_putmem(ctx, dest, src, n, pe);
     vshmem_detail::release_agent();
     vshmemx_signal_update(ctx, sig, sigval, sig_op, pe);
@@ -486,6 +604,11 @@ __device__ __forceinline__ void shmem_putmem_signal(const shmem_dctx_t &ctx, voi
 __device__ __forceinline__ void shmem_putmem_signal_wave(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n,
                                                          uint64_t *sig, uint64_t sigval, int sig_op, int pe)
 {
+    const bool data_ok = vshmem_detail::wave_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest),
+                                                   VSHMEM_U64(src), n, (uint64_t)pe);
+    const bool sig_ok = vshmem_detail::wave_agree(ctx, vshmem_detail::word_ok(ctx, sig, pe), VSHMEM_U64(sig), sigval,
+                                                  (uint64_t)sig_op, (uint64_t)pe);
+    if (!data_ok || !sig_ok) return;
     shmem_putmem_wave(ctx, dest, src, n, pe);
     vshmem_detail::release_agent();
     if (__lane_id() == 0) vshmemx_signal_update(ctx, sig, sigval, sig_op, pe);
@@ -493,6 +616,11 @@ __device__ __forceinline__ void shmem_putmem_signal_wave(const shmem_dctx_t &ctx
 __device__ __forceinline__ void shmem_putmem_signal_wg(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n,
                                                        uint64_t *sig, uint64_t sigval, int sig_op, int pe)
 {
+    const bool data_ok = vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest),
+                                                 VSHMEM_U64(src), n, (uint64_t)pe);
+    const bool sig_ok = vshmem_detail::wg_agree(ctx, vshmem_detail::word_ok(ctx, sig, pe), VSHMEM_U64(sig), sigval,
+                                                (uint64_t)sig_op, (uint64_t)pe);
+    if (!data_ok || !sig_ok) return;
     shmem_putmem_nbi_wg(ctx, dest, src, n, pe);
     vshmem_detail::release_wg_at_exit();
     if (threadIdx.x == 0) vshmemx_signal_update(ctx, sig, sigval, sig_op, pe);
@@ -502,14 +630,17 @@ __device__ __forceinline__ void shmem_putmem_signal_wg(const shmem_dctx_t &ctx, 
 /* Wait on my own copy of a symmetric uint64 signal. */
 __device__ __forceinline__ uint64_t shmem_signal_wait_until(const shmem_dctx_t &ctx, uint64_t *sig, int cmp, uint64_t v)
 {
+    if (!vshmem_detail::word_ok(ctx, sig, ctx.idx)) return 0;
     return vshmem_detail::spin_until<false>(ctx.c, shmemx_local_ptr(ctx, sig), cmp, v);
 }
 __device__ __forceinline__ void shmem_int64_wait_until(const shmem_dctx_t &ctx, int64_t *ivar, int cmp, int64_t v)
 {
+    if (!vshmem_detail::word_ok(ctx, ivar, ctx.idx)) return;
     vshmem_detail::spin_until<true>(ctx.c, (uint64_t *)shmemx_local_ptr(ctx, ivar), cmp, (uint64_t)v);
 }
 __device__ __forceinline__ int shmem_int64_test(const shmem_dctx_t &ctx, int64_t *ivar, int cmp, int64_t v)
 {
+    if (!vshmem_detail::word_ok(ctx, ivar, ctx.idx)) return 0;
     int64_t x = (int64_t)__hip_atomic_load((uint64_t *)shmemx_local_ptr(ctx, ivar), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
     bool ok = vshmem_detail::cmp_holds_s(x, cmp, v);
@@ -931,6 +1062,24 @@ __device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dtea
 
 } // namespace vshmem_detail
 
+namespace vshmem_detail {
+/* Debug check of a collective call: the team lies inside the world and has
+ * the caller as a member, both ranges are inside PE 0's user heap, `extra`
+ * holds, and the work-group's threads agree on (dest, src, n, tag). */
+__device__ __forceinline__ bool coll_ok(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, const void *dest,
+                                        uint64_t dbytes, const void *src, uint64_t sbytes, bool extra, uint64_t n,
+                                        uint64_t tag)
+{
+    if (!ctx.c.debug) return true;
+    const bool team_ok = team.size >= 1 && team.stride >= 1 && team.start >= 0 &&
+                         (int64_t)team.start + (int64_t)(team.size - 1) * team.stride < ctx.c.npes &&
+                         ctx.me >= team.start && (ctx.me - team.start) % team.stride == 0 &&
+                         (ctx.me - team.start) / team.stride < team.size;
+    const bool ok = checked(ctx, team_ok && extra && in_user_heap(ctx, dest, dbytes) && in_user_heap(ctx, src, sbytes));
+    return wg_agree(ctx, ok, VSHMEM_U64(dest), VSHMEM_U64(src), n, tag);
+}
+} // namespace vshmem_detail
+
 /* Team collectives (Section 6.3 names broadcast and reductions among the
  * device-initiated operations; fcollect and alltoall follow OpenSHMEM).
  * Pointers are canonical symmetric addresses; n counts bytes for the
@@ -949,11 +1098,16 @@ __device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dtea
  * the fixed TREE order (pairs of neighbours, level by level), so results
  * are reproducible bit for bit; bf16 accumulates in fp32 and rounds once to
  * nearest-even; teams of 512 or more members get SHMEMX_ERR_UNSUPPORTED
- * from the reductions, which then do nothing.  Return 0 otherwise. */
+ * from the reductions, which then do nothing.  With debug checks on, a call
+ * whose arguments fail them returns SHMEMX_ERR_ARG before any barrier.
+ * Return 0 otherwise. */
 __device__ __forceinline__ int shmemx_broadcastmem_grid(const shmem_dctx_t &ctx, const shmemx_dteam_t &team,
                                                         void *dest, const void *src, size_t n, int root, int rank,
                                                         int nwgs)
 {
+    if (!vshmem_detail::coll_ok(ctx, team, dest, n, src, n, root >= 0 && root < team.size && rank >= 0 && rank < nwgs,
+                                n, ((uint64_t)(uint32_t)nwgs << 32) | (uint32_t)root))
+        return SHMEMX_ERR_ARG;
     vshmem_detail::broadcast<false>(ctx, team, dest, src, n, root, rank, nwgs, vshmem_detail::kCollChunk);
     return 0;
 }
@@ -965,6 +1119,9 @@ __device__ __forceinline__ int shmem_broadcastmem_wg(const shmem_dctx_t &ctx, co
 __device__ __forceinline__ int shmemx_fcollectmem_grid(const shmem_dctx_t &ctx, const shmemx_dteam_t &team,
                                                        void *dest, const void *src, size_t n, int rank, int nwgs)
 {
+    if (!vshmem_detail::coll_ok(ctx, team, dest, (uint64_t)n * team.size, src, n, rank >= 0 && rank < nwgs, n,
+                                (uint64_t)nwgs))
+        return SHMEMX_ERR_ARG;
     vshmem_detail::fcollect<false>(ctx, team, dest, src, n, rank, nwgs, vshmem_detail::kCollChunk);
     return 0;
 }
@@ -976,6 +1133,9 @@ __device__ __forceinline__ int shmem_fcollectmem_wg(const shmem_dctx_t &ctx, con
 __device__ __forceinline__ int shmemx_alltoallmem_grid(const shmem_dctx_t &ctx, const shmemx_dteam_t &team,
                                                        void *dest, const void *src, size_t n, int rank, int nwgs)
 {
+    if (!vshmem_detail::coll_ok(ctx, team, dest, (uint64_t)n * team.size, src, (uint64_t)n * team.size,
+                                rank >= 0 && rank < nwgs, n, (uint64_t)nwgs))
+        return SHMEMX_ERR_ARG;
     vshmem_detail::alltoall<true, 8>(ctx, team, dest, src, n, rank, nwgs, vshmem_detail::kCollChunk);
     return 0;
 }
@@ -990,6 +1150,9 @@ __device__ __forceinline__ int shmem_alltoallmem_wg(const shmem_dctx_t &ctx, con
                                                               T *dest, const T *src, size_t nreduce, int rank,     \
                                                               int nwgs)                                            \
     {                                                                                                              \
+        if (!vshmem_detail::coll_ok(ctx, team, dest, nreduce * sizeof(T), src, nreduce * sizeof(T),               \
+                                    rank >= 0 && rank < nwgs, nreduce, (uint64_t)nwgs))                            \
+            return SHMEMX_ERR_ARG;                                                                                 \
         return vshmem_detail::reduce<vshmem_detail::CODEC, vshmem_detail::OP, true>(                               \
             ctx, team, dest, src, nreduce, rank, nwgs, vshmem_detail::kRedChunk);                                  \
     }

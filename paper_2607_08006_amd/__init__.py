@@ -26,6 +26,7 @@ lib = _native.load()
 OK = 0
 ERR_ARG, ERR_NOMEM, ERR_STATE, ERR_HIP, ERR_BUSY, ERR_TIMEOUT, ERR_DEVICE, ERR_UNSUPPORTED = range(-1, -9, -1)
 DEVERR_WAIT_TIMEOUT, DEVERR_BAD_DESC, DEVERR_PROGRESS_IDLE, DEVERR_PROGRESS_STATE = 0x1, 0x2, 0x4, 0x8
+DEVERR_BAD_ADDRESS, DEVERR_NONUNIFORM = 0x10, 0x20
 
 OP_NOP, OP_PUT, OP_GET, OP_PUT_SIGNAL = 0, 1, 2, 3
 OP_AMO_FETCH_ADD, OP_AMO_FETCH_XOR, OP_AMO_COMPARE_SWAP, OP_AMO_ADD, OP_AMO_XOR = 4, 5, 6, 7, 8

@@ -164,6 +164,45 @@ __global__ void __launch_bounds__(256) k_user_fence(const shmemx_dctx_pub_t *pub
     }
 }
 
+// Debug-mode argument checks (the library initialised with VSHMEM_DEBUG
+// set): each case makes calls that a check must refuse, except case 4,
+// which is valid.  `outside` is device memory outside the heap and every
+// refused PE number still names memory inside the heap, so a call that got
+// past its check would write valid memory rather than fault.
+__global__ void __launch_bounds__(256) k_user_debug(const shmemx_dctx_pub_t *pub, const shmemx_dctx_rec_t *rec,
+                                                    shmemx_dteam_t pair, int which, uint8_t *sym, uint8_t *outside,
+                                                    int64_t *out)
+{
+    const shmem_dctx_t ctx = shmemx_dctx_bind(*pub, (int)blockIdx.x);
+    switch (which) {
+    case 0:   // destination outside the heap
+        if (threadIdx.x == 0) shmem_putmem(ctx, outside, sym, 64, 1);
+        break;
+    case 1:   // atomic on a word outside the heap
+        if (threadIdx.x == 0) out[0] = shmem_int64_atomic_fetch_add(ctx, (int64_t *)outside, 1, 1);
+        break;
+    case 2:   // wavefront call where lane 5 passes another size
+        if (threadIdx.x < 64) shmem_putmem_wave(ctx, sym + 4096, sym, threadIdx.x == 5 ? 32 : 64, 1);
+        break;
+    case 3:   // work-group call where thread 100 passes another PE
+        shmem_putmem_wg(ctx, sym + 4096, sym, 64, threadIdx.x == 100 ? 2 : 1);
+        break;
+    case 4:   // valid
+        if (threadIdx.x == 0) shmem_putmem(ctx, sym + 4096, sym, 64, 1);
+        break;
+    case 5: { // PE 2 of a two-member explicit context
+        const shmem_dctx_t two = shmemx_dctx_bind_explicit(*rec, 0);
+        if (threadIdx.x == 0) shmem_putmem(two, sym + 4096, sym, 64, 2);
+        break;
+    }
+    default: { // broadcast from a root outside the two-member team: refused before any barrier
+        const int rc = shmem_broadcastmem_wg(ctx, pair, sym + 4096, sym, 64, 2);
+        if (threadIdx.x == 0) out[blockIdx.x] = rc;
+        break;
+    }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -231,6 +270,15 @@ int usertest_fence(const void *dctx, int prod, int cons, int64_t *block, size_t 
     if (!dctx || prod == cons || rounds < 0 || !bad) return -1;
     hipLaunchKernelGGL(k_user_fence, dim3(2), dim3(256), 0, (hipStream_t)stream, (const shmemx_dctx_pub_t *)dctx,
                        prod, cons, block, nwords, flag, rounds, bad);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int usertest_debug(const void *dctx, const void *rec, const shmemx_dteam_t *pair, int which, void *sym, void *outside,
+                   int64_t *out, int grid, void *stream)
+{
+    if (!dctx || !rec || !pair || which < 0 || which > 6 || grid < 1 || grid > 2) return -1;
+    hipLaunchKernelGGL(k_user_debug, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const shmemx_dctx_pub_t *)dctx,
+                       (const shmemx_dctx_rec_t *)rec, *pair, which, (uint8_t *)sym, (uint8_t *)outside, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -96,6 +96,7 @@ def user_lib():
         "usertest_barrier": [vp, vp, i32, i32, i32, vp, vp, i32, vp],
         "usertest_ctx": [vp, i32, vp, vp, vp, sz, vp, vp, vp, i32, vp],
         "usertest_fence": [vp, i32, i32, vp, sz, vp, i32, vp, vp],
+        "usertest_debug": [vp, vp, vp, i32, vp, vp, vp, i32, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)

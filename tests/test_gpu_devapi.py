@@ -219,3 +219,46 @@ def test_explicit_context_pool_and_capabilities():
         assert v.device_ctx_create(v.TEAM_WORLD) == 10
         with pytest.raises(v.VshmemError):
             v.device_ctx_create(999)
+
+
+def test_debug_checks_refuse_bad_calls(monkeypatch):
+    """With VSHMEM_DEBUG set at init, calls with operands outside the heap,
+    PEs outside the context's team, or arguments that differ across a
+    _wave/_wg call latch a device error and do nothing; a valid call still
+    moves its data."""
+    lib = _lib()
+    t = torch()
+    monkeypatch.setenv("VSHMEM_DEBUG", "1")
+    npes = 4
+    with heap(npes, 2 << 20) as v:
+        assert v.query_capabilities(v.TEAM_WORLD)["debug"] == 1
+        sym = v.malloc(8192)
+        so = v.offset(sym)
+        region = so + 8192
+        init = W.heap_fill(55, npes, region)
+        pair_team = v.team_split_strided(v.TEAM_WORLD, 0, 1, 2)      # PEs 0 and 1
+        pair = v.team_device(pair_team)
+        ctx = v.device_ctx_create(pair_team)
+        outside = t.zeros(64, dtype=t.uint8, device="cuda")
+        out = t.zeros(4, dtype=t.int64, device="cuda")
+        bad_addr, nonuniform = v.DEVERR_BAD_ADDRESS, v.DEVERR_NONUNIFORM
+        for which, grid, bits in ((0, 1, bad_addr), (1, 1, bad_addr), (2, 1, nonuniform), (3, 1, nonuniform),
+                                  (5, 1, bad_addr), (6, 2, bad_addr), (4, 1, 0)):
+            upload(init)
+            outside.zero_()
+            out.fill_(7)
+            t.cuda.synchronize()
+            assert lib.usertest_debug(v.device_ctx(), v.device_ctx_record(ctx), ctypes.byref(pair), which, sym,
+                                      outside.data_ptr(), out.data_ptr(), grid, None) == 0
+            t.cuda.synchronize()
+            assert v.device_errors() == bits, which
+            got = download(region)
+            ref = init.copy()
+            if which == 4:
+                ref[1, so + 4096:so + 4160] = init[0, so:so + 64]
+            assert np.array_equal(got, ref), which
+            assert not outside.cpu().numpy().any(), which
+            if which == 1:
+                assert int(out[0].item()) == 0
+            if which == 6:
+                assert out[:2].cpu().tolist() == [v.ERR_ARG, v.ERR_ARG]
