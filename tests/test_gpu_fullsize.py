@@ -225,3 +225,31 @@ def test_serving_128pes_full_size_sampled_hashes():
             assert comps[i].hash == want, (i, r.op, r.nbytes)
         assert_no_device_errors()
 
+
+
+def test_host_paths_64pes_1gib_full_size():
+    """The host-initiated transfers at the sizes bench.py times them (64 PEs x
+    1 GiB): a 256 MiB blocking put from pinned host memory, the 256 MiB
+    device-to-device put the copy kernel executes, and 256 MiB gets back to
+    pinned memory, compared byte for byte with the seeded source."""
+    from paper_2607_08006_amd import host
+    t = torch()
+    npes, n = 64, 256 * MiB
+    with heap(npes, 1024 * MiB) as v:
+        a, b = v.malloc(n), v.malloc(n)
+        src = W.heap_fill(W.SEED_SWEEP + 11, 1, n)[0]
+        pinned = t.from_numpy(src.copy()).pin_memory()
+        back = t.zeros(n, dtype=t.uint8).pin_memory()
+        t.cuda.synchronize()
+        host.putmem(a, pinned, n, 0)                 # host memory -> PE 0
+        host.putmem(b, a, n, npes - 1)               # PE 0 -> PE 63 on the copy kernel
+        host.getmem(back, b, n, npes - 1)
+        assert np.array_equal(back.numpy(), src)
+        back.zero_()
+        host.getmem(back, a, n, 0)
+        assert np.array_equal(back.numpy(), src)
+        # an unaligned sub-range through the copy kernel's head and tail paths
+        host.putmem(b + 3, a + 5, n - 4096 - 7, 17)
+        host.getmem(back, b, n, 17)
+        assert np.array_equal(back.numpy()[3:n - 4096 - 4], src[5:n - 4096 - 2])
+        assert_no_device_errors()
