@@ -225,13 +225,83 @@ __device__ __forceinline__ void copy_aligned(uint8_t *__restrict__ d, const uint
     for (uint64_t i = head + nv * A + lane; i < n; i += nl) d[i] = s[i];
 }
 
-/* Copy n bytes with nl cooperating lanes (this one is `lane`): 16-byte
- * vectors when source and destination agree modulo 16, else 8, 4 or 1. */
+/* Body of a copy whose source is `sh` = 4*Q + r bytes (1 <= sh <= 15) past
+ * a 16-byte boundary while the destination is 16-byte aligned: destination
+ * vector i is bytes [16i + sh, 16i + sh + 16) of the aligned source stream
+ * s_al, taken from the two aligned vectors that hold them with byte funnel
+ * shifts (v_alignbyte_b32).  Both loaded vectors hold bytes of the source
+ * range, so no load touches a page the range does not touch.  Neighbouring
+ * lanes load each other's vectors, which the caches absorb: HBM still
+ * reads each source byte once. */
+template <int Q, int U, bool NT>
+__device__ __forceinline__ void copy_shifted_body(v4u *__restrict__ d, const v4u *__restrict__ s_al, uint32_t r,
+                                                  uint64_t nv, uint64_t lane, uint64_t nl)
+{
+    auto join = [r](const v4u &a, const v4u &b) {
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        v4u o;
+        o.x = __builtin_amdgcn_alignbyte(w[Q + 1], w[Q + 0], r);
+        o.y = __builtin_amdgcn_alignbyte(w[Q + 2], w[Q + 1], r);
+        o.z = __builtin_amdgcn_alignbyte(w[Q + 3], w[Q + 2], r);
+        o.w = __builtin_amdgcn_alignbyte(w[Q + 4], w[Q + 3], r);
+        return o;
+    };
+    uint64_t i = lane;
+    for (; i + (uint64_t)(U - 1) * nl < nv; i += (uint64_t)U * nl) {
+        v4u a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = ld<NT>(s_al + i + (uint64_t)u * nl);
+            b[u] = ld<NT>(s_al + i + (uint64_t)u * nl + 1);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) st<NT>(d + i + (uint64_t)u * nl, join(a[u], b[u]));
+    }
+    for (; i < nv; i += nl) st<NT>(d + i, join(ld<NT>(s_al + i), ld<NT>(s_al + i + 1)));
+}
+
 template <int U, bool NT>
+__device__ __forceinline__ void copy_shifted(uint8_t *__restrict__ d, const uint8_t *__restrict__ s, uint64_t n,
+                                             uint64_t lane, uint64_t nl)
+{
+    uint64_t head = (16 - ((uintptr_t)d & 15)) & 15;
+    if (head > n) head = n;
+    for (uint64_t i = lane; i < head; i += nl) d[i] = s[i];
+    const uint8_t *sb = s + head;
+    const uint64_t nv = (n - head) / 16;
+    const uint32_t sh = (uint32_t)((uintptr_t)sb & 15);   // not 0: source and destination disagree mod 16
+    const v4u *s_al = (const v4u *)(sb - sh);
+    v4u *db = (v4u *)(d + head);
+    // Two loads per stored vector: half the unroll keeps the same bytes in
+    // flight without raising register pressure in the aligned path's kernels.
+    constexpr int US = U > 2 ? U / 2 : 1;
+    switch (sh >> 2) {
+    case 0: copy_shifted_body<0, US, NT>(db, s_al, sh & 3, nv, lane, nl); break;
+    case 1: copy_shifted_body<1, US, NT>(db, s_al, sh & 3, nv, lane, nl); break;
+    case 2: copy_shifted_body<2, US, NT>(db, s_al, sh & 3, nv, lane, nl); break;
+    default: copy_shifted_body<3, US, NT>(db, s_al, sh & 3, nv, lane, nl); break;
+    }
+    for (uint64_t i = head + nv * 16 + lane; i < n; i += nl) d[i] = s[i];
+}
+
+/* Copies shorter than this take the narrower vector paths below when source
+ * and destination disagree modulo 16. */
+constexpr uint64_t kShiftedMin = 256;
+
+/* Copy n bytes with nl cooperating lanes (this one is `lane`): 16-byte
+ * vectors when source and destination agree modulo 16; otherwise, with
+ * SHIFT, 16-byte destination vectors assembled from the source by funnel
+ * shifts (copies of kShiftedMin bytes or more), else 8-, 4- or 1-byte
+ * elements.  SHIFT is for callers that see arbitrary offsets (the device
+ * API, serving, plans, host-issued moves); the put/get pattern kernels keep
+ * it off so that their aligned path's registers stay as they were (the
+ * grid-scope kernel is already at the 128-register limit of its launch). */
+template <int U, bool NT, bool SHIFT = false>
 __device__ __forceinline__ void copy_bytes(uint8_t *d, const uint8_t *s, uint64_t n, uint64_t lane, uint64_t nl)
 {
     uint64_t x = (uintptr_t)d ^ (uintptr_t)s;
     if ((x & 15) == 0) copy_aligned<v4u, U, NT>(d, s, n, lane, nl);
+    else if (SHIFT && n >= kShiftedMin) copy_shifted<U, NT>(d, s, n, lane, nl);
     else if ((x & 7) == 0) copy_aligned<uint64_t, U, NT>(d, s, n, lane, nl);
     else if ((x & 3) == 0) copy_aligned<uint32_t, U, NT>(d, s, n, lane, nl);
     else
@@ -409,7 +479,7 @@ __device__ __forceinline__ bool wg_agree(const shmem_dctx_t &ctx, bool ok, uint6
 __device__ __forceinline__ void shmem_putmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
     if (!vshmem_detail::rma_ok(ctx, dest, src, n, pe)) return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmem_ptr(ctx, (uint8_t *)dest, pe),
                                                          shmemx_local_ptr(ctx, (const uint8_t *)src), n, 0, 1);
 }
 __device__ __forceinline__ void shmem_putmem_nbi(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
@@ -421,7 +491,7 @@ __device__ __forceinline__ void shmem_putmem_wave(const shmem_dctx_t &ctx, void 
     if (!vshmem_detail::wave_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest),
                                    VSHMEM_U64(src), n, (uint64_t)pe))
         return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmem_ptr(ctx, (uint8_t *)dest, pe),
                                                          shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          __lane_id(), 64);
 }
@@ -434,7 +504,7 @@ __device__ __forceinline__ void shmem_putmem_nbi_wg(const shmem_dctx_t &ctx, voi
     if (!vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest), VSHMEM_U64(src),
                                  n, (uint64_t)pe))
         return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmem_ptr(ctx, (uint8_t *)dest, pe),
                                                          shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          threadIdx.x, blockDim.x);
 }
@@ -452,7 +522,7 @@ __device__ __forceinline__ void shmemx_putmem_grid(const shmem_dctx_t &ctx, void
     if (!vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest), VSHMEM_U64(src),
                                  n, ((uint64_t)(uint32_t)nwgs << 32) | (uint32_t)pe))
         return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmem_ptr(ctx, (uint8_t *)dest, pe),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmem_ptr(ctx, (uint8_t *)dest, pe),
                                                          shmemx_local_ptr(ctx, (const uint8_t *)src), n,
                                                          (uint64_t)rank * blockDim.x + threadIdx.x,
                                                          (uint64_t)nwgs * blockDim.x);
@@ -462,7 +532,7 @@ __device__ __forceinline__ void shmemx_putmem_grid(const shmem_dctx_t &ctx, void
 __device__ __forceinline__ void shmem_getmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
     if (!vshmem_detail::rma_ok(ctx, dest, src, n, pe)) return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n, 0, 1);
 }
 __device__ __forceinline__ void shmem_getmem_nbi(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
@@ -474,7 +544,7 @@ __device__ __forceinline__ void shmem_getmem_wave(const shmem_dctx_t &ctx, void 
     if (!vshmem_detail::wave_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest),
                                    VSHMEM_U64(src), n, (uint64_t)pe))
         return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          __lane_id(), 64);
 }
@@ -487,7 +557,7 @@ __device__ __forceinline__ void shmem_getmem_nbi_wg(const shmem_dctx_t &ctx, voi
     if (!vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest), VSHMEM_U64(src),
                                  n, (uint64_t)pe))
         return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          threadIdx.x, blockDim.x);
 }
@@ -502,7 +572,7 @@ __device__ __forceinline__ void shmemx_getmem_grid(const shmem_dctx_t &ctx, void
     if (!vshmem_detail::wg_agree(ctx, vshmem_detail::rma_ok(ctx, dest, src, n, pe), VSHMEM_U64(dest), VSHMEM_U64(src),
                                  n, ((uint64_t)(uint32_t)nwgs << 32) | (uint32_t)pe))
         return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(shmemx_local_ptr(ctx, (uint8_t *)dest),
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmemx_local_ptr(ctx, (uint8_t *)dest),
                                                          shmem_ptr(ctx, (const uint8_t *)src, pe), n,
                                                          (uint64_t)rank * blockDim.x + threadIdx.x,
                                                          (uint64_t)nwgs * blockDim.x);

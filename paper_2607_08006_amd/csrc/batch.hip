@@ -90,7 +90,7 @@ __device__ __forceinline__ void exec_copy(const shmemx_dctx_pub_t &c, const shme
     const int dpe = get ? d.issuer_pe : d.target_pe;
     const uint8_t *S = c.base + (uint64_t)spe * c.stride + d.src + lo;
     uint8_t *D = c.base + (uint64_t)dpe * c.stride + d.dst + lo;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false>(D, S, hi - lo, lane, nl);
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(D, S, hi - lo, lane, nl);
 }
 
 __device__ __forceinline__ void signal_of(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d)

@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(64) k_host_wait(shmemx_dctx_pub_t c, uint64_t 
 // vectors i, i + lanes, ...), nontemporal, 8 loads in flight per lane.
 __global__ void __launch_bounds__(1024) k_host_copy(uint8_t *d, const uint8_t *s, uint64_t n)
 {
-    vshmem_detail::copy_bytes<8, true>(d, s, n, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+    vshmem_detail::copy_bytes<8, true, true>(d, s, n, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
                                        (uint64_t)gridDim.x * blockDim.x);
 }
 

@@ -31,7 +31,7 @@ __device__ __forceinline__ uint8_t *exec_request_range(const shmemx_dctx_pub_t &
     const int spe = get ? d.target_pe : d.issuer_pe;
     const int dpe = get ? d.issuer_pe : d.target_pe;
     uint8_t *out = pe_slice(c, dpe) + d.dst;
-    if (lo < hi) vshmem_detail::copy_bytes<8, true>(out + lo, pe_slice(c, spe) + d.src + lo, hi - lo, lane, nl);
+    if (lo < hi) vshmem_detail::copy_bytes<8, true, true>(out + lo, pe_slice(c, spe) + d.src + lo, hi - lo, lane, nl);
     return out;
 }
 

@@ -292,3 +292,34 @@ def test_stream_triggered_sequence_is_ordered_in_the_stream():
         assert np.array_equal(download(region), ref)
         assert np.array_equal(out.numpy(), oracle.host_get(ref, 5, v.offset(b), n))
         assert_no_device_errors()
+
+
+def test_copy_alignment_matrix():
+    """Every pair of source and destination offsets modulo 16, on lengths
+    around the funnel-shift threshold and well past it, through the copy
+    kernel of host-issued heap-to-heap puts; the oracle applies PE 0's
+    puts in the same order."""
+    from paper_2607_08006_amd import host
+    npes = 3
+    sizes = (200, 255, 256, 300, 4099, 70001)
+    with heap(npes, 32 << 20) as v:
+        a = v.malloc(1 << 20)
+        span = sum(s + 32 for s in sizes) * 256
+        b = v.malloc(span)
+        region = v.offset(b) + span
+        init = W.heap_fill(2718, npes, region)
+        upload(init)
+        ref = init.copy()
+        descs = []
+        pos = 0
+        for dm in range(16):
+            for sm in range(16):
+                for n in sizes:
+                    src = v.offset(a) + 1024 * sm + sm          # 1024 * sm keeps sources apart
+                    dst = v.offset(b) + pos + dm
+                    host.putmem(v.heap_base() + dst, v.heap_base() + src, n, 2)
+                    descs.append(_desc(W.OP_PUT, 2, src=src, dst=dst, n=n))
+                    pos += (n + 32) // 16 * 16
+        oracle.run_program(ref, np.concatenate(descs), check=False)
+        assert np.array_equal(download(region), ref)
+        assert_no_device_errors()
