@@ -6,6 +6,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -17,13 +18,55 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-struct Admission {
+// Admission is sharded so that producers for different PEs do not
+// serialise: the budget is one atomic counter, each PE's destination
+// allocator has its own lock, and counter pools are atomic bump pointers.
+// Producers that cannot be admitted sleep on a generation count that every
+// completion advances.  (One global lock here capped a burst at about
+// 0.7 M requests/s.)
+struct PeRegion {
     std::mutex mu;
+    SymAllocator dst;                  // offsets relative to the region
+    std::atomic<uint64_t> ctr_next{0}; // bump pointer of the PE's counter pool
+};
+
+struct Admission {
+    std::vector<std::unique_ptr<PeRegion>> pe;
+    uint64_t ctr_base = 0, ctr_bytes = 0, budget = 0;
+    std::atomic<uint64_t> reserved{0}, max_reserved{0}, waits{0}, gen{0};
+    std::atomic<int> waiting{0};
+    std::mutex wait_mu;
     std::condition_variable cv;
-    std::vector<SymAllocator> dst;     // per PE, offsets relative to the region
-    std::vector<uint64_t> ctr_next;    // per PE bump pointer of the counter pool
-    uint64_t ctr_base = 0, ctr_bytes = 0;
-    uint64_t budget = 0, reserved = 0, max_reserved = 0, waits = 0;
+
+    // Reserve `bytes` of the budget; false when it does not fit now.
+    bool reserve(uint64_t bytes)
+    {
+        uint64_t cur = reserved.load(std::memory_order_relaxed);
+        do {
+            if (cur + bytes > budget) return false;
+        } while (!reserved.compare_exchange_weak(cur, cur + bytes, std::memory_order_relaxed));
+        uint64_t m = max_reserved.load(std::memory_order_relaxed);
+        while (cur + bytes > m && !max_reserved.compare_exchange_weak(m, cur + bytes, std::memory_order_relaxed)) {
+        }
+        return true;
+    }
+    // Wake producers waiting for budget or space (after a release).
+    void released()
+    {
+        {
+            std::lock_guard<std::mutex> lk(wait_mu);
+            gen.fetch_add(1, std::memory_order_release);
+        }
+        if (waiting.load(std::memory_order_acquire) > 0) cv.notify_all();
+    }
+    // Sleep until a completion after generation `seen` (bounded).
+    void wait_after(uint64_t seen)
+    {
+        std::unique_lock<std::mutex> lk(wait_mu);
+        waiting.fetch_add(1, std::memory_order_acq_rel);
+        cv.wait_for(lk, std::chrono::milliseconds(5), [&] { return gen.load(std::memory_order_acquire) != seen; });
+        waiting.fetch_sub(1, std::memory_order_acq_rel);
+    }
 };
 
 struct Slot {
@@ -286,9 +329,11 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
     // allocated so every request starts from zeroed counters.
     Admission adm;
     const uint64_t dst_bytes = (region_bytes / 4 * 3) & ~255ull;
-    adm.dst.resize(s.npes);
-    for (auto &a : adm.dst) a.reset(dst_bytes);
-    adm.ctr_next.assign(s.npes, 0);
+    adm.pe.resize(s.npes);
+    for (auto &a : adm.pe) {
+        a = std::make_unique<PeRegion>();
+        a->dst.reset(dst_bytes);
+    }
     adm.ctr_base = region_off + dst_bytes;
     adm.ctr_bytes = (region_bytes - dst_bytes) & ~255ull;
     adm.budget = budget_bytes;
@@ -309,47 +354,46 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
             const uint64_t need = round_up(r.nbytes, 256);
             const int dpe = r.op == SHMEMX_OP_PUT ? r.target_pe : r.issuer_pe;   // GET and AMO results land on the issuer
             {
-                std::unique_lock<std::mutex> lk(adm.mu);
+                const bool amo = r.op == SHMEMX_OP_AMO_FETCH_ADD;
+                const uint64_t extra = need + (amo ? need : 0);
+                if (extra > adm.budget || need > dst_bytes) {   // could never be admitted
+                    failed.store(SHMEMX_ERR_NOMEM);
+                    adm.released();
+                    return;
+                }
                 bool waited = false;
                 for (;;) {
                     if (failed.load()) return;
-                    const uint64_t extra = need + (r.op == SHMEMX_OP_AMO_FETCH_ADD ? need : 0);
-                    if (extra > adm.budget) {          // could never be admitted
-                        failed.store(SHMEMX_ERR_NOMEM);
-                        adm.cv.notify_all();
-                        return;
-                    }
-                    if (adm.reserved + extra <= adm.budget) {
-                        if (r.op == SHMEMX_OP_AMO_FETCH_ADD &&
-                            adm.ctr_next[r.target_pe] + need > adm.ctr_bytes) {
-                            failed.store(SHMEMX_ERR_NOMEM);
-                            adm.cv.notify_all();
-                            return;
+                    const uint64_t seen = adm.gen.load(std::memory_order_acquire);
+                    if (adm.reserve(extra)) {
+                        PeRegion &pr = *adm.pe[dpe];
+                        uint64_t off;
+                        {
+                            std::lock_guard<std::mutex> lk(pr.mu);
+                            off = pr.dst.alloc(need, 256);
                         }
-                        const uint64_t off = adm.dst[dpe].alloc(need, 256);
                         if (off != UINT64_MAX) {
                             sl.dst = region_off + off;
                             sl.dst_pe = dpe;
-                            if (r.op == SHMEMX_OP_AMO_FETCH_ADD) {
-                                sl.ctr = adm.ctr_base + adm.ctr_next[r.target_pe];
-                                adm.ctr_next[r.target_pe] += need;
-                            }
                             sl.bytes = extra;
-                            adm.reserved += extra;
-                            adm.max_reserved = std::max(adm.max_reserved, adm.reserved);
+                            if (amo) {
+                                const uint64_t c = adm.pe[r.target_pe]->ctr_next.fetch_add(need);
+                                if (c + need > adm.ctr_bytes) {
+                                    failed.store(SHMEMX_ERR_NOMEM);
+                                    adm.released();
+                                    return;
+                                }
+                                sl.ctr = adm.ctr_base + c;
+                            }
                             break;
                         }
-                        if (need > dst_bytes) {
-                            failed.store(SHMEMX_ERR_NOMEM);
-                            adm.cv.notify_all();
-                            return;
-                        }
+                        adm.reserved.fetch_sub(extra, std::memory_order_relaxed);   // no space on the PE yet
                     }
                     if (!waited) {
-                        adm.waits++;
+                        adm.waits.fetch_add(1, std::memory_order_relaxed);
                         waited = true;
                     }
-                    adm.cv.wait_for(lk, std::chrono::milliseconds(5));
+                    adm.wait_after(seen);
                 }
             }
             shmemx_desc_t d{};
@@ -402,11 +446,12 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
                     if (completions) completions[i] = c;
                     if (dst_off_out) dst_off_out[i] = sl.dst;
                     {
-                        std::lock_guard<std::mutex> lk(adm.mu);
-                        adm.dst[sl.dst_pe].free(sl.dst - region_off);
-                        adm.reserved -= sl.bytes;
+                        PeRegion &pr = *adm.pe[sl.dst_pe];
+                        std::lock_guard<std::mutex> lk(pr.mu);
+                        pr.dst.free(sl.dst - region_off);
                     }
-                    adm.cv.notify_all();
+                    adm.reserved.fetch_sub(sl.bytes, std::memory_order_relaxed);
+                    adm.released();
                     sl.state.store(2, std::memory_order_release);
                     ndone.fetch_add(1);
                     any = true;
@@ -435,8 +480,8 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
             if (reqs[i].op == SHMEMX_OP_AMO_FETCH_ADD) stats->amo_ops += reqs[i].nbytes / 8;
             else stats->bytes += reqs[i].nbytes;
         }
-        stats->max_reserved_bytes = adm.max_reserved;
-        stats->admission_waits = adm.waits;
+        stats->max_reserved_bytes = adm.max_reserved.load();
+        stats->admission_waits = adm.waits.load();
         stats->ring_full_retries = be.busy_retries.load();
     }
     return failed.load();
