@@ -62,6 +62,7 @@ struct ProgArgs {
     uint64_t slots, qsize;
     uint64_t chunk;
     uint64_t idle_ticks;
+    uint64_t hold_ticks;          // longest a finished item waits for its work-group's release
     int verify;
 };
 
@@ -346,15 +347,51 @@ struct ClaimedItem {
     int state;   // 0 run, 1 stop, 2 skip
 };
 
-// Thread 0 of the work-group: claim the next item and fill `ci`.
-__device__ void claim_item(const ProgArgs &a, ClaimedItem &ci)
+// Finished items whose completion waits for the work-group's next release.
+// One agent release covers every item the work-group finished before it, so
+// a worker that goes straight on to the next ready item defers the release
+// and the request counts it owes (at most kMaxHold items, at most
+// hold_ticks old), and settles them before any wait.  Thread 0 owns it.
+constexpr uint32_t kMaxHold = 4;
+struct Held {
+    uint64_t parent[kMaxHold];
+    uint64_t t_first;
+    uint32_t n;
+};
+
+// Thread 0: one release for all held items, then their request counts; the
+// last item of a request posts its completion.
+__device__ void settle(const ProgArgs &a, Held &h)
+{
+    if (h.n == 0) return;
+    vshmem_detail::release_agent();   // the work-group's stores of every held item, device-wide
+    for (uint32_t k = 0; k < h.n; ++k) {
+        Parent &P = a.parents[h.parent[k]];
+        const uint64_t left = __hip_atomic_fetch_sub(&P.remaining, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (left == 1) {
+            vshmem_detail::acquire_agent();
+            post_completion(a, (uint32_t)h.parent[k], P, 0);
+        }
+    }
+    h.n = 0;
+}
+
+// Thread 0 of the work-group: claim the next item and fill `ci`.  Held
+// items are settled first unless the next item is already published, and
+// whenever the claimed item has to be waited for.
+__device__ void claim_item(const ProgArgs &a, ClaimedItem &ci, Held &h)
 {
     const uint64_t qmask = a.qsize - 1;
+    if (h.n) {
+        const uint64_t c = __hip_atomic_load(a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ldr_dev(&a.items[c & qmask].seq) != c + 1 || wall_clock64() - h.t_first > a.hold_ticks) settle(a, h);
+    }
     const uint64_t t = __hip_atomic_fetch_add(a.claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     Item *it = a.items + (t & qmask);
     const uint64_t t0 = wall_clock64();
     bool ready = true;
     while (ldr_dev(&it->seq) != t + 1) {
+        settle(a, h);   // no-op once nothing is held
         __builtin_amdgcn_s_sleep(2);
         if (wall_clock64() - t0 > 2 * a.idle_ticks) {
             ready = false;
@@ -369,7 +406,10 @@ __device__ void claim_item(const ProgArgs &a, ClaimedItem &ci)
     ci.lo = ldr_dev(&it->lo);
     ci.hi = ldr_dev(&it->hi);
     st_dev(&it->seq, t + a.qsize);   // the slot is free again
-    if (parent == kItemPoison) return;
+    if (parent == kItemPoison) {
+        settle(a, h);
+        return;
+    }
     Parent &P = a.parents[parent];
     load_desc(ci.d, &P.d, false);
     ci.parent = parent;
@@ -407,10 +447,12 @@ __device__ __forceinline__ void uniform_copy(void *dst, const void *src, size_t 
 __device__ void worker(const ProgArgs &a)
 {
     __shared__ ClaimedItem ci;
+    __shared__ Held held;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    if (threadIdx.x == 0) held.n = 0;
     for (;;) {
         if (wave == 0) {
-            if (__lane_id() == 0) claim_item(a, ci);
+            if (__lane_id() == 0) claim_item(a, ci, held);
         }
         __syncthreads();
         const int state = __builtin_amdgcn_readfirstlane(ci.state);
@@ -424,13 +466,10 @@ __device__ void worker(const ProgArgs &a)
             vshmem_detail::wait_vm_complete();   // this thread's stores of the item reached L2
             __syncthreads();
             if (threadIdx.x == 0) {
-                vshmem_detail::release_agent();   // the work-group's stores are visible device-wide
-                const uint64_t left = __hip_atomic_fetch_sub(&P.remaining, 1ull, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-                if (left == 1) {
-                    vshmem_detail::acquire_agent();
-                    post_completion(a, (uint32_t)parent, P, 0);
-                }
+                // Held until thread 0's next release (see Held).
+                if (held.n == 0) held.t_first = wall_clock64();
+                held.parent[held.n++] = parent;
+                if (held.n == kMaxHold) settle(a, held);
             }
         }
         __syncthreads();   // every thread is done with `ci` before the next claim
@@ -609,6 +648,7 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     a.qsize = qsize;
     a.chunk = cfg.chunk_bytes;
     a.idle_ticks = cfg.idle_timeout_ms * (s.wallclock_hz / 1000);
+    a.hold_ticks = s.wallclock_hz / 50000;   // 20 us
     a.verify = cfg.verify;
     p.slots = slots;
     p.head.store(0);

@@ -291,3 +291,43 @@ def test_progress_request_larger_than_item_queue():
             assert comps[tk].status == 0 and comps[tk].hash == out_hash(ref[out_pe, d:d + n])
             assert comps[tk].t_queued > 0 and comps[tk].t_end >= comps[tk].t_start >= comps[tk].t_queued
         assert_no_device_errors()
+
+
+def test_completed_request_is_visible_while_the_kernel_runs():
+    """A request's completion means its bytes are visible device-wide: with
+    the progress kernel still running (on few work-groups, so other kernels
+    get CUs), each completed put is read back at once by a separate copy and
+    equals its source.  Every put rewrites the same destination from another
+    source range, so a stale or late write would show.  Items are small
+    (16 KiB), so each request is split over several workers, which hold
+    finished items for a later release."""
+    npes = 6
+    with heap(npes, 8 << 20) as v:
+        t = torch()
+        region = 4 << 20
+        init = W.heap_fill(0xD0D0, npes, region)
+        upload(init)
+        side, reader = t.cuda.Stream(), t.cuda.Stream()
+        t.cuda.synchronize()
+        v.progress_start(nwg=8, wg_size=256, ring_slots=64, chunk_bytes=16 << 10, idle_timeout_ms=5000,
+                         stream=side)
+        h = v.heap_view()
+        dst = 3 << 20
+        try:
+            for k in range(40):
+                n = 200_000 + 4093 * k
+                src_pe, tgt = k % npes, (k + 1) % npes
+                src = (k * 24_577) % (dst - n)
+                tk = v.progress_submit(_desc(W.OP_PUT, src_pe, tgt, src, dst, n))
+                t0 = time.time()
+                c = None
+                while c is None and time.time() - t0 < 20:
+                    c = v.progress_poll(tk)
+                assert c is not None and c.status == 0, k
+                with t.cuda.stream(reader):                    # a copy on a stream of its own
+                    got = h[tgt, dst:dst + n].cpu().numpy()
+                assert np.array_equal(got, init[src_pe, src:src + n]), k
+        finally:
+            v.progress_stop(10000)
+            side.synchronize()
+        assert_no_device_errors()
