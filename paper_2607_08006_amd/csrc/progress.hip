@@ -9,7 +9,8 @@
 // frees the slot for ticket t + slots, so a record is never overwritten
 // before it was read.  On the device one front-end wavefront (the first of
 // work-group 0) reads published descriptors in ticket order and expands
-// each into work items of at most chunk_bytes in a device-memory queue;
+// each into work items of at most chunk_bytes (4 * chunk_bytes while every
+// worker already has an item queued) in a device-memory queue;
 // every other work-group claims items from that queue one at a time and
 // executes each with all its threads, and the work-group that finishes a
 // request's last item writes its completion record to host memory and then
@@ -60,7 +61,8 @@ struct ProgArgs {
     Parent *parents;
     uint64_t *claim;              // device: next item ticket for workers
     uint64_t slots, qsize;
-    uint64_t chunk;
+    uint64_t chunk;               // item size while workers keep up
+    uint64_t chunk_big;           // item size once every worker has an item queued
     uint64_t idle_ticks;
     uint64_t hold_ticks;          // longest a finished item waits for its work-group's release
     int verify;
@@ -224,6 +226,13 @@ __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
             continue;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // system scope: descriptors after their sequence words
+        // Backlog-adaptive split: while published items wait for fewer
+        // claims than there are workers, small items spread a request over
+        // many work-groups (latency); once every worker has one queued,
+        // larger items cut the per-item claim, drain and release costs
+        // (throughput).  One decision per round, uniform over the lanes.
+        const uint64_t claimed = __shfl(lane == 0 ? ldr_dev(a.claim) : 0ull, 0, 64);
+        const uint64_t chunk = pub > claimed && pub - claimed >= nworkers ? a.chunk_big : a.chunk;
         uint64_t pos0 = pub;                            // next free item position
         uint64_t invalid = 0;                           // bit r: this lane's request of batch r is invalid
         for (int r = 0; r * 64ull < c_total; ++r) {
@@ -242,7 +251,7 @@ __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
                 for (int i = 0; i < 4; ++i) w[i] = q[i];
                 memcpy(&d, w, sizeof(d));
                 valid = valid_request(a.c, d);
-                nitems = valid ? (d.nbytes == 0 ? 1 : (d.nbytes + a.chunk - 1) / a.chunk) : 0;
+                nitems = valid ? (d.nbytes == 0 ? 1 : (d.nbytes + chunk - 1) / chunk) : 0;
                 if (!valid) invalid |= 1ull << r;
             }
             uint64_t incl = nitems;
@@ -297,8 +306,8 @@ __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
                     if (ok) {
                         it->parent = o_slot;
                         it->ticket = o_ticket;
-                        it->lo = k * a.chunk;
-                        it->hi = min(o_bytes, (k + 1) * a.chunk);
+                        it->lo = k * chunk;
+                        it->hi = min(o_bytes, (k + 1) * chunk);
                     }
                 }
             }
@@ -351,8 +360,11 @@ struct ClaimedItem {
 // One agent release covers every item the work-group finished before it, so
 // a worker that goes straight on to the next ready item defers the release
 // and the request counts it owes (at most kMaxHold items, at most
-// hold_ticks old), and settles them before any wait.  Thread 0 owns it.
+// hold_ticks old), and settles them before any wait and before an item of
+// more than kHoldSpanBytes, whose copy would hold them back for longer than
+// the release saves.  Thread 0 owns it.
 constexpr uint32_t kMaxHold = 4;
+constexpr uint64_t kHoldSpanBytes = 64u << 10;
 struct Held {
     uint64_t parent[kMaxHold];
     uint64_t t_first;
@@ -406,10 +418,8 @@ __device__ void claim_item(const ProgArgs &a, ClaimedItem &ci, Held &h)
     ci.lo = ldr_dev(&it->lo);
     ci.hi = ldr_dev(&it->hi);
     st_dev(&it->seq, t + a.qsize);   // the slot is free again
-    if (parent == kItemPoison) {
-        settle(a, h);
-        return;
-    }
+    if (parent == kItemPoison || ci.hi - ci.lo > kHoldSpanBytes) settle(a, h);
+    if (parent == kItemPoison) return;
     Parent &P = a.parents[parent];
     load_desc(ci.d, &P.d, false);
     ci.parent = parent;
@@ -647,6 +657,7 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     a.slots = slots;
     a.qsize = qsize;
     a.chunk = cfg.chunk_bytes;
+    a.chunk_big = cfg.chunk_bytes <= (UINT64_MAX >> 2) ? cfg.chunk_bytes * 4 : cfg.chunk_bytes;
     a.idle_ticks = cfg.idle_timeout_ms * (s.wallclock_hz / 1000);
     a.hold_ticks = s.wallclock_hz / 50000;   // 20 us
     a.verify = cfg.verify;

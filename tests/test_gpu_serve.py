@@ -71,6 +71,76 @@ def test_progress_submit_poll_matches_oracle():
         assert_no_device_errors()
 
 
+def test_backlog_split_matches_oracle():
+    """One worker and many queued requests: the front-end switches to the
+    larger split while the worker is backlogged; every output (ragged
+    tails, unaligned, AMO counters) still equals the oracle's."""
+    npes = 4
+    with heap(npes, 8 << 20) as v:
+        t = torch()
+        region = 7 << 20
+        init = W.heap_fill(0xB4C106, npes, region)
+        init[:, 6 << 20:] = 0                             # counters start at zero
+        upload(init)
+        side = t.cuda.Stream()
+        t.cuda.synchronize()
+        v.progress_start(nwg=2, wg_size=256, ring_slots=64, verify=True, chunk_bytes=4 << 10, stream=side)
+        rng = np.random.default_rng(17)
+        reqs, dst = [], 2 << 20
+        for k in range(40):
+            n = int(rng.integers(1, 100_000))
+            op = (W.OP_PUT, W.OP_GET, W.OP_AMO_FETCH_ADD)[k % 3]
+            i, tg = int(rng.integers(npes)), int(rng.integers(npes))
+            if op == W.OP_AMO_FETCH_ADD:
+                n = (n // 8 + 1) * 8
+                src = (6 << 20) + 8 * int(rng.integers(0, 1000))
+            else:
+                src = int(rng.integers(0, 1 << 20))
+            reqs.append((op, i, tg, src, dst + (0 if op == W.OP_AMO_FETCH_ADD else k % 5), n))
+            dst += ((n + 4096) // 4096 + 1) * 4096
+        assert dst + 8 < (6 << 20)
+        tickets = [v.progress_submit(_desc(*r, value=3 if r[0] == W.OP_AMO_FETCH_ADD else 0)) for r in reqs]
+        comps, t0 = {}, time.time()
+        while len(comps) < len(tickets) and time.time() - t0 < 30:
+            for tk in tickets:
+                if tk not in comps:
+                    c = v.progress_poll(tk)
+                    if c is not None:
+                        comps[tk] = c
+        v.progress_stop(10000)
+        side.synchronize()
+        assert len(comps) == len(tickets)
+        got = download(region)
+        # AMO results depend on the order of requests on shared counters;
+        # the counters' final values and every copy do not.
+        ref = init.copy()
+        recs = []
+        for op, i, tg, s, d, n in reqs:
+            if op == W.OP_AMO_FETCH_ADD:
+                for w in range(n // 8):
+                    recs.append((op, 0, 0, i, tg, W.NO_RESULT, s + 8 * w, 0, 8, 3, 0))
+            else:
+                recs.append((op, 0, 0, i, tg, W.NO_RESULT, s, d, n, 0, 0))
+        oracle.run_program(ref, W.descs(recs))
+        amo_out = np.zeros(got.shape, dtype=bool)
+        for op, i, tg, s, d, n in reqs:
+            if op == W.OP_AMO_FETCH_ADD:
+                amo_out[i, d:d + n] = True
+        assert np.array_equal(got[~amo_out], ref[~amo_out])
+        for tk, (op, i, tg, s, d, n) in zip(tickets, reqs):
+            c = comps[tk]
+            assert c.status == 0 and c.t_end >= c.t_start > 0
+            if op != W.OP_AMO_FETCH_ADD:
+                out_pe = tg if op == W.OP_PUT else i
+                assert c.hash == out_hash(ref[out_pe, d:d + n])
+            else:
+                # fetched values: multiples of 3 below each counter's final value
+                fetched = got[i, d:d + n].view(np.uint64)
+                final = ref[tg, s:s + n].view(np.uint64)
+                assert ((fetched % 3) == 0).all() and (fetched < final).all()
+        assert_no_device_errors()
+
+
 def _trace(npes, n, rate, src_bytes, seed, max_log2=14):
     rs = W.serve_requests(seed, n, npes, rate_per_s=rate, lanes=8, size_log2_span=max_log2)
     from paper_2607_08006_amd import Request
