@@ -23,7 +23,21 @@ __device__ __forceinline__ uint8_t *exec_request_range(const shmemx_dctx_pub_t &
     if (d.op == SHMEMX_OP_AMO_FETCH_ADD) {
         uint64_t *ctr = (uint64_t *)(pe_slice(c, d.target_pe) + d.src);
         uint64_t *res = (uint64_t *)(pe_slice(c, d.issuer_pe) + d.dst);
-        for (uint64_t k = lo / 8 + lane; k < hi / 8; k += nl)
+        // kAmoBatch atomics in flight per lane, then their results: a result
+        // store may alias a later counter, so one atomic per store would
+        // cost a full round trip each.
+        constexpr int kAmoBatch = 8;
+        uint64_t k = lo / 8 + lane;
+        const uint64_t end = hi / 8;
+        for (; k + (kAmoBatch - 1) * nl < end; k += kAmoBatch * nl) {
+            uint64_t old[kAmoBatch];
+#pragma unroll
+            for (int j = 0; j < kAmoBatch; ++j)
+                old[j] = __hip_atomic_fetch_add(ctr + k + j * nl, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int j = 0; j < kAmoBatch; ++j) res[k + j * nl] = old[j];
+        }
+        for (; k < end; k += nl)
             res[k] = __hip_atomic_fetch_add(ctr + k, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return (uint8_t *)res;
     }
