@@ -754,8 +754,10 @@ def run_serve(v, torch, args):
 
     def summary(reqs, lat, stats, warm=0):
         pay = sum(r.nbytes for r in reqs)
+        amo = sum(r.nbytes // 8 for r in reqs if r.op == W.OP_AMO_FETCH_ADD)
         l = lat[warm:] / 1e3
         return {"GB_s": round(pay / stats.wall_s / 1e9, 2), "req_s": round(len(reqs) / stats.wall_s, 1),
+                "amo_Mops_s": round(amo / stats.wall_s / 1e6, 1),
                 "p50_us": round(percentile(l, 50), 1), "p99_us": round(percentile(l, 99), 1),
                 "admission_waits": int(stats.admission_waits), "max_reserved_bytes": int(stats.max_reserved_bytes)}
 

@@ -667,8 +667,8 @@ int shmemx_tune_load(shmemx_tune_t *tune, const char *path);
  * (PUT, GET, AMO_FETCH_ADD with nbytes/8 counters) into a ring in pinned
  * host memory.  Work-group 0's first wavefront is the front-end: it takes
  * published requests in ticket order and splits each into chunks of at most
- * chunk_bytes, or of at most 4 * chunk_bytes while every worker already has
- * a chunk queued; every other work-group is a worker that claims one chunk
+ * chunk_bytes, or of at most 16 * chunk_bytes while every worker already
+ * has a chunk queued; every other work-group is a worker that claims one chunk
  * at a time and executes it with all its threads.  The worker finishing a
  * request's last chunk quiets and posts the completion record.  The kernel
  * exits when stopped or after idle_timeout_ms without work.
@@ -679,7 +679,7 @@ typedef struct shmemx_progress_cfg {
     int32_t ring_slots;       /* power of two */
     int32_t verify;           /* 1: completion carries a hash of the output */
     uint64_t chunk_bytes;     /* split unit for large requests, multiple of 16 (0 = 256 KiB);
-                                 4x under backlog */
+                                 16x under backlog */
     uint64_t idle_timeout_ms; /* 0 = 30000 */
 } shmemx_progress_cfg_t;
 

@@ -9,7 +9,7 @@
 // frees the slot for ticket t + slots, so a record is never overwritten
 // before it was read.  On the device one front-end wavefront (the first of
 // work-group 0) reads published descriptors in ticket order and expands
-// each into work items of at most chunk_bytes (4 * chunk_bytes while every
+// each into work items of at most chunk_bytes (16 * chunk_bytes while every
 // worker already has an item queued) in a device-memory queue;
 // every other work-group claims items from that queue one at a time and
 // executes each with all its threads, and the work-group that finishes a
@@ -193,6 +193,11 @@ __device__ bool wait_item_free(const ProgArgs &a, Item *it, uint64_t pos)
 }
 
 constexpr int kFrontBatches = 4;   // a round takes up to 4 x 64 published tickets
+// Item size under backlog, in units of chunk_bytes.  On a burst of 10^4
+// log-uniform requests (64 B - 16 MiB) with 256 KiB chunks, 4, 8, 16, 32
+// and 64 gave 1.29, 1.39, 1.59, 1.44 and 1.39 TB/s of payload: larger
+// items cut per-item costs until too few remain to balance the tail.
+constexpr uint64_t kBacklogSplit = 16;
 
 __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
 {
@@ -657,7 +662,7 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     a.slots = slots;
     a.qsize = qsize;
     a.chunk = cfg.chunk_bytes;
-    a.chunk_big = cfg.chunk_bytes <= (UINT64_MAX >> 2) ? cfg.chunk_bytes * 4 : cfg.chunk_bytes;
+    a.chunk_big = cfg.chunk_bytes <= (UINT64_MAX >> 4) ? cfg.chunk_bytes * kBacklogSplit : cfg.chunk_bytes;
     a.idle_ticks = cfg.idle_timeout_ms * (s.wallclock_hz / 1000);
     a.hold_ticks = s.wallclock_hz / 50000;   // 20 us
     a.verify = cfg.verify;
