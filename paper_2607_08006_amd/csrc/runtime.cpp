@@ -511,10 +511,11 @@ int shmem_team_split_strided(shmem_team_t parent, int start, int stride, int siz
     t.stride = p.stride * stride;
     t.size = size;
     t.slot = idx;
-    // Clear the new team's barrier words in its first member's scratch.
-    uint64_t *slot = (uint64_t *)(s.base + (uint64_t)t.start * s.stride + s.user_bytes +
-                                  (uint64_t)t.slot * VSHMEM_SYNC_SLOT_BYTES);
-    if (VSHMEM_HIP_FAILED(hipMemset(slot, 0, VSHMEM_SYNC_SLOT_BYTES))) {
+    // Clear the new team's barrier words (count and generation) in its
+    // first member's scratch.
+    uint8_t *slot = s.base + (uint64_t)t.start * s.stride + s.user_bytes + (uint64_t)t.slot * VSHMEM_SYNC_SLOT_BYTES;
+    if (VSHMEM_HIP_FAILED(hipMemset(slot, 0, VSHMEM_SYNC_SLOT_BYTES)) ||
+        VSHMEM_HIP_FAILED(hipMemset(slot + VSHMEM_SYNC_GEN_OFF, 0, VSHMEM_SYNC_SLOT_BYTES))) {
         t.live = false;
         return SHMEMX_ERR_HIP;
     }
