@@ -908,7 +908,14 @@ __device__ __forceinline__ void fcollect(const shmem_dctx_t &ctx, const shmemx_d
     shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
 }
 
-// Member p's dest[q*n, (q+1)*n) <- member q's src[p*n, (p+1)*n).
+// Member p's dest[q*n, (q+1)*n) <- member q's src[p*n, (p+1)*n).  A task is
+// one chunk of one block.  A task shorter than half of one pass of the
+// work-group (U 16-byte vectors per lane) goes to a group of g lanes: the
+// smallest power of two, at most a wavefront, that covers it in one pass.
+// A work-group then copies blockDim/g small blocks at once; one task per
+// work-group would leave most lanes idle and pay a memory round trip per
+// block.  Consecutive tasks go to different work-groups first, so a few
+// tiny blocks per member still spread over every work-group.
 template <bool NT, int U>
 __device__ __forceinline__ void alltoall(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
                                          const void *src, uint64_t n, int rank, int nwgs, uint64_t chunk)
@@ -921,13 +928,24 @@ __device__ __forceinline__ void alltoall(const shmem_dctx_t &ctx, const shmemx_d
     const uint64_t P = (uint64_t)team.size;
     const uint64_t nch = (n + chunk - 1) / chunk;
     const uint64_t ntask = nch * P * P;
-    for (uint64_t t = W.w; t < ntask; t += W.n) {
-        const uint64_t blk = t / nch;
-        const uint64_t p = blk / P;   // destination member
-        const uint64_t q = blk % P;   // source member
-        const uint64_t off = (t - blk * nch) * chunk;
-        copy_bytes<U, NT>(D0 + p * ps + q * n + off, S0 + q * ps + p * n + off, min(chunk, n - off), threadIdx.x,
-                          blockDim.x);
+    constexpr uint64_t kPass = 16ull * U;   // bytes per lane per pass
+    const uint64_t task = min(chunk, n);
+    uint32_t g = blockDim.x;
+    if (task * 2 < kPass * blockDim.x) {
+        const uint64_t need = (task + kPass - 1) / kPass;
+        g = 1;
+        while (g < 64 && g < need) g <<= 1;
+    }
+    const uint32_t groups = blockDim.x / g;   // threads past groups * g stay idle
+    if (threadIdx.x < groups * g) {
+        const uint64_t lane = threadIdx.x % g;
+        for (uint64_t t = (uint64_t)(threadIdx.x / g) * W.n + W.w; t < ntask; t += (uint64_t)W.n * groups) {
+            const uint64_t blk = t / nch;
+            const uint64_t p = blk / P;   // destination member
+            const uint64_t q = blk % P;   // source member
+            const uint64_t off = (t - blk * nch) * chunk;
+            copy_bytes<U, NT>(D0 + p * ps + q * n + off, S0 + q * ps + p * n + off, min(chunk, n - off), lane, g);
+        }
     }
     shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
 }

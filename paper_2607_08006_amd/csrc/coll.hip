@@ -86,11 +86,20 @@ int check_coresident(K kernel, int grid, int wg)
     return SHMEMX_OK;
 }
 
+// Bytes a member writes per automatically added work-group: below this a
+// second work-group per member costs more in barrier arrivals than it saves
+// in copying (64 PEs: alltoall of 4 KiB blocks took 16 us with one
+// work-group per member and 25 us with four; 16 KiB blocks 41 us with two,
+// 47 with four and 56 with one).
+constexpr uint64_t kAutoBytesPerWg = 512ull << 10;
+
 // Launch a kernel whose work-groups synchronise with each other.  When the
-// caller left wgs_per_pe at 0, fill the device: as many work-groups per
-// member as stay co-resident (at most 16).
+// caller left wgs_per_pe at 0, about one work-group per CU over the team,
+// fewer when each member writes little (bytes_per_member), and never more
+// than stay co-resident.
 template <typename K, typename... Args>
-int launch_team_kernel(K kernel, Geo &g, int wg, hipStream_t s, bool auto_wgs, Args... args)
+int launch_team_kernel(K kernel, Geo &g, int wg, hipStream_t s, bool auto_wgs, uint64_t bytes_per_member,
+                       Args... args)
 {
     if (auto_wgs) {
         // About one work-group per CU: in measurements on MI355X, streaming
@@ -99,7 +108,9 @@ int launch_team_kernel(K kernel, Geo &g, int wg, hipStream_t s, bool auto_wgs, A
         int per_cu = 0;
         if (int rc = blocks_per_cu(kernel, wg, &per_cu)) return rc;
         const int64_t cap = (int64_t)per_cu * st().num_cus;
-        const int64_t want = std::max<int64_t>(1, st().num_cus / g.team.size);
+        const uint64_t by_bytes = (bytes_per_member + kAutoBytesPerWg - 1) / kAutoBytesPerWg;
+        const int64_t want = std::max<int64_t>(
+            1, std::min<int64_t>(st().num_cus / g.team.size, (int64_t)std::min<uint64_t>(by_bytes, 1u << 20)));
         g.wgs_per_pe = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap / g.team.size));
     }
     const int grid = g.wgs_per_pe * g.team.size;
@@ -149,8 +160,8 @@ int shmemx_broadcastmem_launch(shmem_team_t team, void *dest, const void *src, s
     g.n = n;
     const bool aw = !launch || launch->wgs_per_pe == 0;
     if (L.flags & SHMEMX_LAUNCH_NONTEMPORAL)
-        return launch_team_kernel(k_broadcast<true>, g, L.wg_size, (hipStream_t)stream, aw, root);
-    return launch_team_kernel(k_broadcast<false>, g, L.wg_size, (hipStream_t)stream, aw, root);
+        return launch_team_kernel(k_broadcast<true>, g, L.wg_size, (hipStream_t)stream, aw, (uint64_t)n, root);
+    return launch_team_kernel(k_broadcast<false>, g, L.wg_size, (hipStream_t)stream, aw, (uint64_t)n, root);
 }
 
 int shmemx_fcollectmem_launch(shmem_team_t team, void *dest, const void *src, size_t n, const shmemx_launch_t *launch,
@@ -171,8 +182,8 @@ int shmemx_fcollectmem_launch(shmem_team_t team, void *dest, const void *src, si
     g.n = n;
     const bool aw = !launch || launch->wgs_per_pe == 0;
     if (L.flags & SHMEMX_LAUNCH_NONTEMPORAL)
-        return launch_team_kernel(k_fcollect<true>, g, L.wg_size, (hipStream_t)stream, aw);
-    return launch_team_kernel(k_fcollect<false>, g, L.wg_size, (hipStream_t)stream, aw);
+        return launch_team_kernel(k_fcollect<true>, g, L.wg_size, (hipStream_t)stream, aw, (uint64_t)n * tsize);
+    return launch_team_kernel(k_fcollect<false>, g, L.wg_size, (hipStream_t)stream, aw, (uint64_t)n * tsize);
 }
 
 int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, size_t n, const shmemx_launch_t *launch,
@@ -195,10 +206,11 @@ int shmemx_alltoallmem_launch(shmem_team_t team, void *dest, const void *src, si
     const bool aw = !launch || launch->wgs_per_pe == 0;
     const bool nt = (L.flags & SHMEMX_LAUNCH_NONTEMPORAL) != 0, deep = (L.flags & SHMEMX_LAUNCH_DEEP) != 0;
     hipStream_t hs = (hipStream_t)stream;
-    if (nt && deep) return launch_team_kernel(k_alltoall<true, 8>, g, L.wg_size, hs, aw);
-    if (nt) return launch_team_kernel(k_alltoall<true, 4>, g, L.wg_size, hs, aw);
-    if (deep) return launch_team_kernel(k_alltoall<false, 8>, g, L.wg_size, hs, aw);
-    return launch_team_kernel(k_alltoall<false, 4>, g, L.wg_size, hs, aw);
+    const uint64_t wb = (uint64_t)n * tsize;
+    if (nt && deep) return launch_team_kernel(k_alltoall<true, 8>, g, L.wg_size, hs, aw, wb);
+    if (nt) return launch_team_kernel(k_alltoall<true, 4>, g, L.wg_size, hs, aw, wb);
+    if (deep) return launch_team_kernel(k_alltoall<false, 8>, g, L.wg_size, hs, aw, wb);
+    return launch_team_kernel(k_alltoall<false, 4>, g, L.wg_size, hs, aw, wb);
 }
 
 int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const void *src, size_t nreduce,
@@ -225,12 +237,13 @@ int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const
     const bool aw = !launch || launch->wgs_per_pe == 0;
     hipStream_t s = (hipStream_t)stream;
     const bool nt = (L.flags & SHMEMX_LAUNCH_NONTEMPORAL) != 0;
+    const uint64_t wb = nreduce * es;
 #define VSHMEM_RED(CODEC)                                                                                   \
     if (op == SHMEMX_RED_SUM)                                                                               \
-        return nt ? launch_team_kernel(k_reduce<CODEC, OpSum, true>, g, L.wg_size, s, aw)                   \
-                  : launch_team_kernel(k_reduce<CODEC, OpSum, false>, g, L.wg_size, s, aw);                 \
-    return nt ? launch_team_kernel(k_reduce<CODEC, OpMax, true>, g, L.wg_size, s, aw)                       \
-              : launch_team_kernel(k_reduce<CODEC, OpMax, false>, g, L.wg_size, s, aw);
+        return nt ? launch_team_kernel(k_reduce<CODEC, OpSum, true>, g, L.wg_size, s, aw, wb)               \
+                  : launch_team_kernel(k_reduce<CODEC, OpSum, false>, g, L.wg_size, s, aw, wb);             \
+    return nt ? launch_team_kernel(k_reduce<CODEC, OpMax, true>, g, L.wg_size, s, aw, wb)                   \
+              : launch_team_kernel(k_reduce<CODEC, OpMax, false>, g, L.wg_size, s, aw, wb);
     if (dtype == SHMEMX_DT_INT64) {
         VSHMEM_RED(CodecI64)
     } else if (dtype == SHMEMX_DT_FP32) {

@@ -49,6 +49,34 @@ def test_data_movement_collectives(npes):
         assert_no_device_errors()
 
 
+def test_alltoall_small_blocks_lane_groups():
+    """Blocks (or chunks) shorter than half a work-group pass go to groups of
+    1 to 64 lanes; sizes between those powers, chunked blocks, work-group
+    sizes that are not powers of two and both unroll depths must all give
+    the oracle's transpose."""
+    npes = 7
+    with heap(npes, 4 << 20) as v:
+        src = v.malloc(1 << 20)
+        dst = v.malloc(1 << 20)
+        so, do = v.offset(src), v.offset(dst)
+        region = do + (1 << 20)
+        init = W.heap_fill(W.SEED_COLL + 4242, npes, region)
+        cases = [(dict(wgs_per_pe=2, wg_size=192, flags=0), (17, 129, 300, 1000, 2049, 8191)),
+                 (dict(wgs_per_pe=1, wg_size=1024, flags=v.LAUNCH_DEEP), (16, 128, 129, 4096, 8200, 65_537)),
+                 (dict(wgs_per_pe=3, wg_size=256, chunk_bytes=256), (1000, 4099)),
+                 (dict(wgs_per_pe=1, wg_size=64, chunk_bytes=48, flags=v.LAUNCH_NONTEMPORAL), (200, 1001))]
+        for L, sizes in cases:
+            launch = v.launch_cfg(**L)
+            for n in sizes:
+                upload(init)
+                v.alltoallmem(dst, src, n, launch=launch)
+                got = download(region)
+                ref = init.copy()
+                oracle.alltoall(ref, do, so, n)
+                assert np.array_equal(got, ref), ("alltoall", n, L)
+        assert_no_device_errors()
+
+
 def test_alltoall_tags_transpose_and_involution():
     npes, n = 6, 1000
     with heap(npes, 1 << 20) as v:
