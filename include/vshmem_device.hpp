@@ -1114,7 +1114,11 @@ __device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dtea
     const uint64_t nbytes = nelem * CODEC::ES;
     const bool vec = (((uintptr_t)s0 | (uintptr_t)d0 | pstride) & 15) == 0;
     const uint64_t nvec = vec ? nbytes / 16 : 0;
-    const uint64_t vpt = chunk / 16;   // vectors per task
+    // Vectors per task: the chunk, or an even share per worker when that is
+    // smaller, so a small reduction still spreads over every work-group
+    // (each element's order over the members does not depend on who runs it).
+    const uint64_t share = (nvec + W.n - 1) / W.n;
+    const uint64_t vpt = max<uint64_t>(1, min<uint64_t>(chunk / 16, share));
     const uint64_t ntask = (nvec + vpt - 1) / vpt;
     for (uint64_t t = W.w; t < ntask; t += W.n) {
         const uint64_t v1 = min(nvec, (t + 1) * vpt);
