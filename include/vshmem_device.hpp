@@ -588,6 +588,43 @@ __device__ __forceinline__ void shmemx_getmem_grid(const shmem_dctx_t &ctx, void
                                                          (uint64_t)nwgs * blockDim.x);
 }
 
+/* GPU-space names.  The paper's GPU-space usage example (Section 6.1) writes
+ * a device-initiated put to an object from shmemg_malloc as shmemg_put and
+ * marks its names as illustrative.  Here the GPU space is the default heap,
+ * so these are the put and get above under that prefix. */
+__device__ __forceinline__ void shmemg_putmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
+{
+    shmem_putmem(ctx, dest, src, n, pe);
+}
+__device__ __forceinline__ void shmemg_putmem_nbi(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
+{
+    shmem_putmem_nbi(ctx, dest, src, n, pe);
+}
+__device__ __forceinline__ void shmemg_putmem_wave(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
+{
+    shmem_putmem_wave(ctx, dest, src, n, pe);
+}
+__device__ __forceinline__ void shmemg_putmem_wg(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
+{
+    shmem_putmem_wg(ctx, dest, src, n, pe);
+}
+__device__ __forceinline__ void shmemg_getmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
+{
+    shmem_getmem(ctx, dest, src, n, pe);
+}
+__device__ __forceinline__ void shmemg_getmem_nbi(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
+{
+    shmem_getmem_nbi(ctx, dest, src, n, pe);
+}
+__device__ __forceinline__ void shmemg_getmem_wave(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
+{
+    shmem_getmem_wave(ctx, dest, src, n, pe);
+}
+__device__ __forceinline__ void shmemg_getmem_wg(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
+{
+    shmem_getmem_wg(ctx, dest, src, n, pe);
+}
+
 /* -------------------------------------------------------- fence / quiet */
 __device__ __forceinline__ void shmem_fence(const shmem_dctx_t &) { vshmem_detail::release_agent(); }
 __device__ __forceinline__ void shmem_quiet(const shmem_dctx_t &) { vshmem_detail::release_agent(); }

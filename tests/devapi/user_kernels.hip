@@ -133,6 +133,24 @@ __global__ void __launch_bounds__(256) k_user_ctx(const shmemx_dctx_rec_t *rec, 
     shmem_quiet_wg(ctx);
 }
 
+// The GPU-space usage example, one work-group per PE on objects from
+// shmemg_malloc: put the local block to PE me + 1 at work-group scope, fence
+// and quiet, barrier; then wave 0 gets the block back from PE me + 1 and
+// thread 0 gets `tail` bytes of it at offset `at` with a thread-scope get.
+__global__ void __launch_bounds__(256) k_user_gspace(const shmemx_dctx_pub_t *pub, const uint8_t *src, uint8_t *dst,
+                                                     uint8_t *back, uint8_t *part, size_t n, size_t at, size_t tail)
+{
+    const shmem_dctx_t ctx = shmemx_dctx_bind(*pub, (int)blockIdx.x);
+    const int me = shmem_my_pe(ctx), np = shmem_n_pes(ctx);
+    shmemg_putmem_wg(ctx, dst, src, n, (me + 1) % np);
+    shmem_fence_wg(ctx);
+    shmem_quiet_wg(ctx);
+    shmem_barrier_all_wg(ctx);
+    if (threadIdx.x < 64) shmemg_getmem_wave(ctx, back, dst, n, (me + 1) % np);
+    if (threadIdx.x == 0) shmemg_getmem(ctx, part, dst + at, tail, (me + 1) % np);
+    shmem_quiet_wg(ctx);
+}
+
 // Ordering by fence: the producer (work-group 0, PE prod) fills its local
 // block with the round number, puts it to the consumer, fences, and sets the
 // consumer's flag to round + 1; the consumer (work-group 1, PE cons) waits
@@ -252,6 +270,15 @@ int usertest_barrier(const void *dctx, const shmemx_dteam_t *team, int scope, in
         return -1;
     hipLaunchKernelGGL(k_user_barrier, dim3(team->size), dim3(wg), 0, (hipStream_t)stream,
                        (const shmemx_dctx_pub_t *)dctx, *team, scope, world, iters, tok, bad);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int usertest_gspace(const void *dctx, int npes, const void *src, void *dst, void *back, void *part, size_t n,
+                    size_t at, size_t tail, void *stream)
+{
+    if (!dctx || npes < 1 || npes > 64 || at > n || tail > n - at) return -1;
+    hipLaunchKernelGGL(k_user_gspace, dim3(npes), dim3(256), 0, (hipStream_t)stream, (const shmemx_dctx_pub_t *)dctx,
+                       (const uint8_t *)src, (uint8_t *)dst, (uint8_t *)back, (uint8_t *)part, n, at, tail);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

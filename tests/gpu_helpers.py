@@ -95,6 +95,7 @@ def user_lib():
         "usertest_pipeline": [vp, vp, vp, vp, vp, vp, sz, sz, i32, i32, vp],
         "usertest_barrier": [vp, vp, i32, i32, i32, vp, vp, i32, vp],
         "usertest_ctx": [vp, i32, vp, vp, vp, sz, vp, vp, vp, i32, vp],
+        "usertest_gspace": [vp, i32, vp, vp, vp, vp, sz, sz, sz, vp],
         "usertest_fence": [vp, i32, i32, vp, sz, vp, i32, vp, vp],
         "usertest_debug": [vp, vp, vp, i32, vp, vp, vp, i32, vp],
     }

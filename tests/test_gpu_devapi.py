@@ -262,3 +262,32 @@ def test_debug_checks_refuse_bad_calls(monkeypatch):
                 assert int(out[0].item()) == 0
             if which == 6:
                 assert out[:2].cpu().tolist() == [v.ERR_ARG, v.ERR_ARG]
+
+
+def test_gpu_space_put_get_names():
+    """The GPU-space usage example on objects from shmemg_malloc: a
+    work-group-scope shmemg_putmem to the next PE, fence, quiet, barrier,
+    then a wavefront-scope shmemg_getmem of the whole block and a
+    thread-scope one of an unaligned piece from the next PE.  The heap
+    follows the oracle's put and get programs."""
+    lib = _lib()
+    npes, n, at, tail = 6, 5000, 13, 777
+    with heap(npes, 2 << 20) as v:
+        src, dst, back, part = (v.shmemg_malloc(n) for _ in range(4))
+        so, do, bo, po = (v.offset(a) for a in (src, dst, back, part))
+        region = max(so, do, bo, po) + n
+        init = W.heap_fill(W.SEED_SMALL + 606, npes, region)
+        upload(init)
+        assert lib.usertest_gspace(v.device_ctx(), npes, src, dst, back, part, n, at, tail, None) == 0
+        got = download(region)
+        ref = init.copy()
+        oracle.run_program(ref, np.concatenate([
+            W.descs([(W.OP_PUT, W.SCOPE_WG, 0, k, (k + 1) % npes, W.NO_RESULT, so, do, n, 0, 0)]) for k in range(npes)]))
+        oracle.run_program(ref, np.concatenate(
+            [W.descs([(W.OP_GET, W.SCOPE_WAVE, 0, k, (k + 1) % npes, W.NO_RESULT, do, bo, n, 0, 0)]) for k in range(npes)]
+            + [W.descs([(W.OP_GET, W.SCOPE_THREAD, 0, k, (k + 1) % npes, W.NO_RESULT, do + at, po, tail, 0, 0)])
+               for k in range(npes)]))
+        assert np.array_equal(got, ref)
+        for k in range(npes):      # each PE got its own block back
+            assert np.array_equal(got[k, bo:bo + n], init[k, so:so + n])
+        assert_no_device_errors()
