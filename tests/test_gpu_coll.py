@@ -77,6 +77,31 @@ def test_alltoall_small_blocks_lane_groups():
         assert_no_device_errors()
 
 
+def test_shared_team_spans_every_pe():
+    """On one GPU every virtual PE shares the node, so the shared teams (host
+    and device) have the world's members: size, capabilities, the device
+    descriptor, barriers and an alltoall on them match the world's."""
+    npes, n = 5, 3000
+    with heap(npes, 2 << 20) as v:
+        for tm in (v.TEAM_SHARED, v.DEVICE_TEAM_SHARED):
+            assert v.team_n_pes(tm) == npes
+            d = v.team_device(tm)
+            assert (d.start, d.stride, d.size) == (0, 1, npes)
+            caps = v.query_capabilities(tm)
+            assert caps["team_npes"] == npes and caps["team_start"] == 0 and caps["team_stride"] == 1
+        src, dst = v.malloc(n * npes), v.malloc(n * npes)
+        so, do = v.offset(src), v.offset(dst)
+        region = do + n * npes
+        init = W.heap_fill(W.SEED_COLL + 515, npes, region)
+        upload(init)
+        v.barrier(v.DEVICE_TEAM_SHARED, iters=20)
+        v.alltoallmem(dst, src, n, team=v.DEVICE_TEAM_SHARED)
+        ref = init.copy()
+        oracle.alltoall(ref, do, so, n)
+        assert np.array_equal(download(region), ref)
+        assert_no_device_errors()
+
+
 def test_alltoall_tags_transpose_and_involution():
     npes, n = 6, 1000
     with heap(npes, 1 << 20) as v:
