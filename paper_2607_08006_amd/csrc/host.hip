@@ -4,6 +4,7 @@
 // device moves, one-thread kernels built from the device API for AMOs,
 // signal updates and waits, and the collective launchers.
 #include <algorithm>
+#include <chrono>
 
 #include "runtime.hpp"
 
@@ -22,10 +23,18 @@ enum HostAmo : int {
     HA_SIGNAL_ADD,
 };
 
+// A blocking host call's completion word: after the call's effect and
+// result, `seq` is stored to pinned host memory with a system-scope release.
+__device__ __forceinline__ void post_done(uint64_t *done, uint64_t seq)
+{
+    if (done) __hip_atomic_store(done, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // One atomic on PE pe's copy of the canonical word `sym`, issued as PE 0
-// through the device API; the previous value goes to *out when out is set.
+// through the device API; the previous value goes to *out when out is set,
+// then the completion word when done is set.
 __global__ void __launch_bounds__(64) k_host_amo(shmemx_dctx_pub_t c, int op, uint64_t *sym, int pe, uint64_t v,
-                                                 uint64_t cond, uint64_t *out)
+                                                 uint64_t cond, uint64_t *out, uint64_t *done, uint64_t seq)
 {
     if (threadIdx.x != 0) return;
     const shmem_dctx_t ctx = shmemx_dctx_bind(c, 0);
@@ -42,16 +51,19 @@ __global__ void __launch_bounds__(64) k_host_amo(shmemx_dctx_pub_t c, int op, ui
     default: vshmemx_signal_update(ctx, sym, v, SHMEM_SIGNAL_ADD, pe); break;
     }
     if (out) *out = old;
+    post_done(done, seq);
 }
 
-// Wait on PE 0's copy of `sym`; writes the value seen to *out when set.
+// Wait on PE 0's copy of `sym`; writes the value seen to *out when set,
+// then the completion word when done is set.
 __global__ void __launch_bounds__(64) k_host_wait(shmemx_dctx_pub_t c, uint64_t *sym, int cmp, uint64_t v,
-                                                  int is_signed, uint64_t *out)
+                                                  int is_signed, uint64_t *out, uint64_t *done, uint64_t seq)
 {
     if (threadIdx.x != 0) return;
     const uint64_t x = is_signed ? vshmem_detail::spin_until<true>(c, sym, cmp, v)
                                  : vshmem_detail::spin_until<false>(c, sym, cmp, v);
     if (out) *out = x;
+    post_done(done, seq);
 }
 
 // Device-to-device copy striped over the whole grid (lane i moves 16-byte
@@ -127,11 +139,13 @@ int rma(bool is_put, void *dest, const void *source, size_t n, int pe, hipStream
     return rc ? fail(rc) : SHMEMX_OK;
 }
 
-int amo_enqueue(int op, void *sym, int pe, uint64_t v, uint64_t cond, uint64_t *out, hipStream_t stream)
+int amo_enqueue(int op, void *sym, int pe, uint64_t v, uint64_t cond, uint64_t *out, hipStream_t stream,
+                uint64_t *done = nullptr, uint64_t seq = 0)
 {
     if (int rc = check_ready()) return rc;
     if (!sym_word(sym) || pe < 0 || pe >= st().npes) return fail(SHMEMX_ERR_ARG);
-    hipLaunchKernelGGL(k_host_amo, dim3(1), dim3(64), 0, stream, pub(), op, (uint64_t *)sym, pe, v, cond, out);
+    hipLaunchKernelGGL(k_host_amo, dim3(1), dim3(64), 0, stream, pub(), op, (uint64_t *)sym, pe, v, cond, out, done,
+                       seq);
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
 }
@@ -140,6 +154,35 @@ int host_sync()
 {
     VSHMEM_HIP(hipStreamSynchronize(st().host_stream));
     return SHMEMX_OK;
+}
+
+// Blocking one-kernel calls (AMOs, signal reads, waits) end with a
+// completion word instead of a stream synchronisation: the kernel stores the
+// call's sequence number to pinned host memory after its result, and the
+// host spins on that word.  The spin stops after kDoneSpin (a wait that
+// lasts longer then sleeps in the stream synchronisation) or when the
+// stream reports an error.  Host words: [0] AMO result, [1] wait result,
+// [2] completion.  Calls through the host context are serialised by their
+// caller, as the host context's other blocking calls are.
+constexpr int kDoneWord = 2;
+constexpr auto kDoneSpin = std::chrono::microseconds(200);
+uint64_t g_done_seq = 0;
+
+int wait_done(uint64_t seq)
+{
+    State &s = st();
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t k = 1;; ++k) {
+        if (__atomic_load_n(&s.host_words[kDoneWord], __ATOMIC_ACQUIRE) == seq) return SHMEMX_OK;
+        if ((k & 255) == 0) {
+            const hipError_t e = hipStreamQuery(s.host_stream);
+            if (e != hipErrorNotReady || std::chrono::steady_clock::now() - t0 > kDoneSpin) break;
+        }
+        __builtin_ia32_pause();
+    }
+    if (int rc = host_sync()) return rc;
+    // The kernel ended, so its completion word is in place.
+    return __atomic_load_n(&s.host_words[kDoneWord], __ATOMIC_ACQUIRE) == seq ? SHMEMX_OK : fail(SHMEMX_ERR_HIP);
 }
 
 // Blocking AMO through the host context; the fetched value lands in the
@@ -152,7 +195,10 @@ uint64_t amo_blocking(int op, void *sym, int pe, uint64_t v, uint64_t cond)
         return 0;
     }
     s.host_words[0] = 0;
-    if (amo_enqueue(op, sym, pe, v, cond, s.host_words_dev, s.host_stream) || host_sync()) return 0;
+    const uint64_t seq = ++g_done_seq;
+    if (amo_enqueue(op, sym, pe, v, cond, s.host_words_dev, s.host_stream, s.host_words_dev + kDoneWord, seq) ||
+        wait_done(seq))
+        return 0;
     return __atomic_load_n(&s.host_words[0], __ATOMIC_ACQUIRE);
 }
 
@@ -165,9 +211,14 @@ uint64_t wait_blocking(void *sym, int cmp, uint64_t v, int is_signed)
         return 0;
     }
     s.host_words[1] = 0;
+    const uint64_t seq = ++g_done_seq;
     hipLaunchKernelGGL(k_host_wait, dim3(1), dim3(64), 0, s.host_stream, pub(), (uint64_t *)sym, cmp, v, is_signed,
-                       s.host_words_dev + 1);
-    if (VSHMEM_HIP_FAILED(hipGetLastError()) || host_sync()) return 0;
+                       s.host_words_dev + 1, s.host_words_dev + kDoneWord, seq);
+    if (VSHMEM_HIP_FAILED(hipGetLastError())) {
+        set_last_error(SHMEMX_ERR_HIP);
+        return 0;
+    }
+    if (wait_done(seq)) return 0;
     return __atomic_load_n(&s.host_words[1], __ATOMIC_ACQUIRE);
 }
 
@@ -384,7 +435,7 @@ int shmemx_signal_wait_until_on_stream(uint64_t *sig_addr, int cmp, uint64_t cmp
     if (int rc = check_ready()) return rc;
     if (!sym_word(sig_addr) || cmp < SHMEM_CMP_EQ || cmp > SHMEM_CMP_LE) return fail(SHMEMX_ERR_ARG);
     hipLaunchKernelGGL(k_host_wait, dim3(1), dim3(64), 0, (hipStream_t)stream, pub(), sig_addr, cmp, cmp_value, 0,
-                       nullptr);
+                       nullptr, nullptr, 0ull);
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
 }

@@ -228,7 +228,9 @@ static int finish_init(void *heap, size_t heap_bytes, int npes, hipStream_t stre
     VSHMEM_HIP(hipMalloc((void **)&s.d_ctx, sizeof(shmemx_dctx_pub_t)));
     VSHMEM_HIP(hipMalloc((void **)&s.d_ctx_recs, sizeof(shmemx_dctx_rec_t) * SHMEMX_MAX_DEVICE_CTX));
     VSHMEM_HIP(hipStreamCreateWithFlags(&s.host_stream, hipStreamNonBlocking));
-    VSHMEM_HIP(hipHostMalloc((void **)&s.host_words, kHostWords * sizeof(uint64_t), hipHostMallocMapped));
+    // Coherent: blocking host calls spin on a completion word kernels store here.
+    VSHMEM_HIP(hipHostMalloc((void **)&s.host_words, kHostWords * sizeof(uint64_t),
+                             hipHostMallocMapped | hipHostMallocCoherent));
     VSHMEM_HIP(hipHostGetDevicePointer((void **)&s.host_words_dev, s.host_words, 0));
     s.heap.reset(s.user_bytes);
     reset_teams();
