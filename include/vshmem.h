@@ -666,10 +666,10 @@ int shmemx_tune_load(shmemx_tune_t *tune, const char *path);
  * progress, Section 6.4 and Section 7).  Host threads submit descriptors
  * (PUT, GET, AMO_FETCH_ADD with nbytes/8 counters) into a ring in pinned
  * host memory.  Work-group 0's first wavefront is the front-end: it takes
- * published requests in ticket order and splits each into chunks of at most
- * chunk_bytes, or of at most 16 * chunk_bytes while every worker already
- * has a chunk queued; every other work-group is a worker that claims one chunk
- * at a time and executes it with all its threads.  The worker finishing a
+ * published requests in ticket order and splits each into chunks of
+ * chunk_bytes times the number of chunks queued per worker (at least 1, at
+ * most 16); every other work-group is a worker that claims one chunk at a
+ * time and executes it with all its threads.  The worker finishing a
  * request's last chunk quiets and posts the completion record.  The kernel
  * exits when stopped or after idle_timeout_ms without work.
  */
@@ -678,8 +678,8 @@ typedef struct shmemx_progress_cfg {
     int32_t wg_size;          /* threads per work-group (0 = 1024) */
     int32_t ring_slots;       /* power of two */
     int32_t verify;           /* 1: completion carries a hash of the output */
-    uint64_t chunk_bytes;     /* split unit for large requests, multiple of 16 (0 = 256 KiB);
-                                 16x under backlog */
+    uint64_t chunk_bytes;     /* split unit for large requests, multiple of 16, at most
+                                 2^40 (0 = 256 KiB); up to 16x under backlog */
     uint64_t idle_timeout_ms; /* 0 = 30000 */
 } shmemx_progress_cfg_t;
 

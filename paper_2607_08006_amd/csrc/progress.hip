@@ -9,8 +9,8 @@
 // frees the slot for ticket t + slots, so a record is never overwritten
 // before it was read.  On the device one front-end wavefront (the first of
 // work-group 0) reads published descriptors in ticket order and expands
-// each into work items of at most chunk_bytes (16 * chunk_bytes while every
-// worker already has an item queued) in a device-memory queue;
+// each into work items of chunk_bytes times the queued items per worker
+// (at least 1, at most 16) in a device-memory queue;
 // every other work-group claims items from that queue one at a time and
 // executes each with all its threads, and the work-group that finishes a
 // request's last item writes its completion record to host memory and then
@@ -62,7 +62,6 @@ struct ProgArgs {
     uint64_t *claim;              // device: next item ticket for workers
     uint64_t slots, qsize;
     uint64_t chunk;               // item size while workers keep up
-    uint64_t chunk_big;           // item size once every worker has an item queued
     uint64_t idle_ticks;
     uint64_t hold_ticks;          // longest a finished item waits for its work-group's release
     int verify;
@@ -193,10 +192,10 @@ __device__ bool wait_item_free(const ProgArgs &a, Item *it, uint64_t pos)
 }
 
 constexpr int kFrontBatches = 4;   // a round takes up to 4 x 64 published tickets
-// Item size under backlog, in units of chunk_bytes.  On a burst of 10^4
-// log-uniform requests (64 B - 16 MiB) with 256 KiB chunks, 4, 8, 16, 32
-// and 64 gave 1.29, 1.39, 1.59, 1.44 and 1.39 TB/s of payload: larger
-// items cut per-item costs until too few remain to balance the tail.
+// Largest item size under backlog, in units of chunk_bytes.  On a burst of
+// 10^4 log-uniform requests (64 B - 16 MiB) with 256 KiB chunks, a fixed 4,
+// 8, 16, 32 and 64 gave 1.29, 1.39, 1.59, 1.44 and 1.39 TB/s of payload:
+// larger items cut per-item costs until too few remain to balance the tail.
 constexpr uint64_t kBacklogSplit = 16;
 
 __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
@@ -231,13 +230,16 @@ __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
             continue;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // system scope: descriptors after their sequence words
-        // Backlog-adaptive split: while published items wait for fewer
-        // claims than there are workers, small items spread a request over
-        // many work-groups (latency); once every worker has one queued,
-        // larger items cut the per-item claim, drain and release costs
-        // (throughput).  One decision per round, uniform over the lanes.
+        // Backlog-adaptive split: the item size is chunk_bytes times the
+        // number of queued items per worker (published, not yet claimed),
+        // at least 1 and at most kBacklogSplit.  A short queue keeps small
+        // items that spread a request over many work-groups (latency); a
+        // deep one gets large items that cut the per-item claim, drain and
+        // release costs (throughput).  One decision per round, uniform over
+        // the lanes.
         const uint64_t claimed = __shfl(lane == 0 ? ldr_dev(a.claim) : 0ull, 0, 64);
-        const uint64_t chunk = pub > claimed && pub - claimed >= nworkers ? a.chunk_big : a.chunk;
+        const uint64_t per_worker = pub > claimed ? (pub - claimed) / nworkers : 0;
+        const uint64_t chunk = per_worker <= 1 ? a.chunk : a.chunk * min<uint64_t>(per_worker, kBacklogSplit);
         uint64_t pos0 = pub;                            // next free item position
         uint64_t invalid = 0;                           // bit r: this lane's request of batch r is invalid
         for (int r = 0; r * 64ull < c_total; ++r) {
@@ -609,7 +611,7 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     const State &s = st();
     if (cfg.nwg == 0) cfg.nwg = s.num_cus;
     if (!valid_wg_size(cfg.wg_size) || cfg.nwg < 2 || cfg.nwg > 8 * s.num_cus || cfg.ring_slots < 2 ||
-        (cfg.ring_slots & (cfg.ring_slots - 1)) || (cfg.chunk_bytes & 15))
+        (cfg.ring_slots & (cfg.ring_slots - 1)) || (cfg.chunk_bytes & 15) || cfg.chunk_bytes > (1ull << 40))
         return SHMEMX_ERR_ARG;
     const uint64_t slots = (uint64_t)cfg.ring_slots;
     const uint64_t qsize = 1ull << 16;
@@ -662,7 +664,6 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     a.slots = slots;
     a.qsize = qsize;
     a.chunk = cfg.chunk_bytes;
-    a.chunk_big = cfg.chunk_bytes <= (UINT64_MAX >> 4) ? cfg.chunk_bytes * kBacklogSplit : cfg.chunk_bytes;
     a.idle_ticks = cfg.idle_timeout_ms * (s.wallclock_hz / 1000);
     a.hold_ticks = s.wallclock_hz / 50000;   // 20 us
     a.verify = cfg.verify;

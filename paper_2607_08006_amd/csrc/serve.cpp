@@ -11,6 +11,8 @@
 #include <thread>
 #include <vector>
 
+#include <sys/prctl.h>
+
 #include "serving.hpp"
 
 using namespace vshmem;
@@ -342,13 +344,22 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
     std::atomic<size_t> ndone{0};
     const Clock::time_point start = Clock::now() + std::chrono::milliseconds(2);
 
+    // Arrivals are replayed on time: a sleeping thread wakes up to the
+    // timer slack late (50 us by default), which the latency would count,
+    // so producers take a 1 us slack and spin through the last 50 us.
+    auto wait_until = [](Clock::time_point due) {
+        const auto spin = std::chrono::microseconds(50);
+        if (Clock::now() + spin < due) std::this_thread::sleep_until(due - spin);
+        while (Clock::now() < due) std::this_thread::yield();
+    };
     auto producer = [&](int lane) {
+        (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
         for (size_t i = 0; i < n && !failed.load(); ++i) {
             const shmemx_request_t &r = reqs[i];
             if (r.lane != lane) continue;
             const Clock::time_point due = start + std::chrono::duration_cast<Clock::duration>(
                                                       std::chrono::duration<double>(r.arrival_s));
-            std::this_thread::sleep_until(due);
+            wait_until(due);
             Slot &sl = slots[i];
             sl.arrival = due;
             const uint64_t need = round_up(r.nbytes, 256);
