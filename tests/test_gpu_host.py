@@ -2,6 +2,8 @@
 (the host acting for PE 0) and stream-triggered operations, against the CPU
 oracle.  Private host buffers follow the oracle's host put/get; heap-to-heap
 moves and atomics follow PE 0's program in the oracle."""
+import time
+
 import numpy as np
 import pytest
 
@@ -197,6 +199,35 @@ def test_host_signals_waits_and_tests():
             host.putmem(data, payload, 8, npes)                              # PE out of range
         with pytest.raises(v.VshmemError):
             host.putmem(t.zeros(8, dtype=t.uint8, device="cuda").data_ptr(), payload, 8, 0)   # not symmetric
+        assert_no_device_errors()
+
+
+def test_host_wait_outlasts_the_spin():
+    """A blocking host wait whose signal arrives only after several
+    milliseconds of device work on another stream: the host's spin on the
+    completion word runs out and it falls back to the stream
+    synchronisation, and it still returns the value that ended the wait and
+    the data put before the signal."""
+    from paper_2607_08006_amd import host
+    t = torch()
+    npes = 4
+    with heap(npes, 2 << 20) as v:
+        sig = v.calloc(1, 8)
+        data = v.malloc(4096)
+        region = v.offset(data) + 4096
+        upload(np.zeros((npes, region), dtype=np.uint8))
+        payload = t.from_numpy(W.heap_fill(31, 1, 4096)[0].copy()).pin_memory()
+        other = t.cuda.Stream()
+        t.cuda.synchronize()
+        v.barrier(v.DEVICE_TEAM_WORLD, iters=4000, stream=other)          # milliseconds of device work
+        host.putmem_signal_on_stream(data, payload, 4096, sig, 9, v.SIGNAL_SET, 0, stream=other)
+        t0 = time.perf_counter()
+        assert host.signal_wait_until(sig, v.CMP_EQ, 9) == 9
+        waited = time.perf_counter() - t0
+        other.synchronize()
+        assert waited > 0.5e-3, waited        # longer than the spin
+        got = download(region)
+        assert np.array_equal(got[0, v.offset(data):region], payload.numpy())
         assert_no_device_errors()
 
 

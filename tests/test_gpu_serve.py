@@ -218,6 +218,8 @@ def test_progress_rejects_bad_config_and_busy_ring():
             v.progress_start(nwg=1, wg_size=64)                 # no worker wavefronts
         with pytest.raises(v.VshmemError):
             v.progress_start(ring_slots=3)                      # not a power of two
+        with pytest.raises(v.VshmemError):
+            v.progress_start(chunk_bytes=(1 << 40) + 16)        # items up to 16x must not overflow
         side = t.cuda.Stream()
         v.progress_start(nwg=8, wg_size=128, ring_slots=4, stream=side, idle_timeout_ms=5000)
         with pytest.raises(v.VshmemError):
