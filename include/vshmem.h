@@ -333,8 +333,9 @@ int shmemx_set_wait_timeout_ns(uint64_t ns);
  * wg_size: threads per work-group (multiple of 64, <= 1024).  chunk_bytes:
  * unit of work handed to one work-group when a message or collective is
  * split across work-groups (multiple of 16).  Zero fields take defaults;
- * for the team collectives wgs_per_pe = 0 means as many work-groups per
- * member as stay co-resident on the device (at most 16). */
+ * for the team collectives wgs_per_pe = 0 means one work-group per member
+ * per 512 KiB the member writes, at most one per CU over the team and never
+ * more than stay co-resident. */
 typedef struct shmemx_launch {
     int32_t wgs_per_pe;
     int32_t wg_size;
@@ -668,7 +669,7 @@ int shmemx_tune_load(shmemx_tune_t *tune, const char *path);
  * host memory.  Work-group 0's first wavefront is the front-end: it takes
  * published requests in ticket order and splits each into chunks of
  * chunk_bytes times the number of chunks queued per worker (at least 1, at
- * most 16); every other work-group is a worker that claims one chunk at a
+ * most 8); every other work-group is a worker that claims one chunk at a
  * time and executes it with all its threads.  The worker finishing a
  * request's last chunk quiets and posts the completion record.  The kernel
  * exits when stopped or after idle_timeout_ms without work.
@@ -679,7 +680,7 @@ typedef struct shmemx_progress_cfg {
     int32_t ring_slots;       /* power of two */
     int32_t verify;           /* 1: completion carries a hash of the output */
     uint64_t chunk_bytes;     /* split unit for large requests, multiple of 16, at most
-                                 2^40 (0 = 256 KiB); up to 16x under backlog */
+                                 2^40 (0 = 256 KiB); up to 8x under backlog */
     uint64_t idle_timeout_ms; /* 0 = 30000 */
 } shmemx_progress_cfg_t;
 

@@ -10,7 +10,7 @@
 // before it was read.  On the device one front-end wavefront (the first of
 // work-group 0) reads published descriptors in ticket order and expands
 // each into work items of chunk_bytes times the queued items per worker
-// (at least 1, at most 16) in a device-memory queue;
+// (at least 1, at most 8) in a device-memory queue;
 // every other work-group claims items from that queue one at a time and
 // executes each with all its threads, and the work-group that finishes a
 // request's last item writes its completion record to host memory and then
@@ -193,10 +193,11 @@ __device__ bool wait_item_free(const ProgArgs &a, Item *it, uint64_t pos)
 
 constexpr int kFrontBatches = 4;   // a round takes up to 4 x 64 published tickets
 // Largest item size under backlog, in units of chunk_bytes.  On a burst of
-// 10^4 log-uniform requests (64 B - 16 MiB) with 256 KiB chunks, a fixed 4,
-// 8, 16, 32 and 64 gave 1.29, 1.39, 1.59, 1.44 and 1.39 TB/s of payload:
-// larger items cut per-item costs until too few remain to balance the tail.
-constexpr uint64_t kBacklogSplit = 16;
+// 10^4 log-uniform requests (64 B - 16 MiB) with 256 KiB chunks, items in
+// proportion to the backlog capped at 4, 8 and 16 gave 1.35, 1.59 and 1.47
+// TB/s of payload: larger items cut per-item costs until too few remain to
+// balance the tail.
+constexpr uint64_t kBacklogSplit = 8;
 
 __device__ void front_end(const ProgArgs &a, uint64_t nworkers)
 {
