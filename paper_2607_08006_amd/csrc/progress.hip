@@ -505,6 +505,18 @@ __global__ void __launch_bounds__(1024) k_progress(ProgArgs a)
     worker(a);
 }
 
+// Start-up state of a run: item k free for ticket k (seq = k, the rest
+// zero), every request record and the claim counter zero.  Grid-stride.
+static_assert(sizeof(Parent) % 8 == 0, "request records are whole words");
+__global__ void __launch_bounds__(256) k_progress_init(Item *items, uint64_t qsize, uint64_t *parent_words,
+                                                        uint64_t nwords, uint64_t *claim)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = g; k < qsize; k += stride) items[k] = Item{k, 0, 0, 0, 0, {0, 0, 0}};
+    for (uint64_t k = g; k < nwords; k += stride) parent_words[k] = 0;
+    if (g < 256 / 8) claim[g] = 0;
+}
+
 // One request executed by a launch of its own (the per-op serving form):
 // work-group b handles bytes [b*chunk, (b+1)*chunk) of the request.
 __global__ void __launch_bounds__(1024) k_request(shmemx_dctx_pub_t c, shmemx_desc_t d, uint64_t chunk)
@@ -639,12 +651,11 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     }
     memset(p.comp, 0, slots * sizeof(shmemx_completion_t));
     *p.stop = 0;
-    std::vector<Item> init(qsize);
-    for (uint64_t i = 0; i < qsize; ++i) init[i] = Item{i, 0, 0, 0, 0, {0, 0, 0}};
     hipStream_t hs = (hipStream_t)stream;
-    if (VSHMEM_HIP_FAILED(hipMemcpyAsync(p.items, init.data(), qsize * sizeof(Item), hipMemcpyHostToDevice, hs)) ||
-        VSHMEM_HIP_FAILED(hipMemsetAsync(p.claim, 0, 256, hs)) || VSHMEM_HIP_FAILED(hipMemsetAsync(p.parents, 0, slots * sizeof(Parent), hs)) ||
-        VSHMEM_HIP_FAILED(hipStreamSynchronize(hs))) {
+    // Device-side reset, ordered before the kernel on the same stream.
+    hipLaunchKernelGGL(k_progress_init, dim3(256), dim3(256), 0, hs, p.items, qsize, (uint64_t *)p.parents,
+                       slots * sizeof(Parent) / 8, p.claim);
+    if (VSHMEM_HIP_FAILED(hipGetLastError())) {
         release_progress();
         return SHMEMX_ERR_HIP;
     }

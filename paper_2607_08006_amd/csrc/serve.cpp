@@ -342,7 +342,9 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
     std::vector<Slot> slots(n);
     std::atomic<int> failed{0};
     std::atomic<size_t> ndone{0};
-    const Clock::time_point start = Clock::now() + std::chrono::milliseconds(2);
+    // Arrival times count from `start`, a short lead after this point that
+    // lets the producer and completion threads start first.
+    const Clock::time_point start = Clock::now() + std::chrono::microseconds(200);
 
     // Arrivals are replayed on time: a sleeping thread wakes up to the
     // timer slack late (50 us by default), which the latency would count,
