@@ -369,28 +369,38 @@ __device__ __forceinline__ uint64_t *sync_slot(const shmemx_dctx_pub_t &c, int p
     return (uint64_t *)(c.base + (uint64_t)pe * c.stride + c.scratch_off + (uint64_t)slot * VSHMEM_SYNC_SLOT_BYTES);
 }
 
-/* Sense-reversing counter barrier among `units` arriving work-groups; one
- * thread per work-group calls it.  Release before arriving, acquire after
- * leaving (in both the last arrival and the waiters), so it also completes
- * (quiets) the arrivals' stores.  Called after the work-group's threads
- * waited for their own operations and synchronised, the release and
- * acquire of this one thread cover the whole work-group: they write back
- * and invalidate the caches the work-group's wavefronts share.  With the
- * generation word on a line of its own (VSHMEM_SYNC_GEN_OFF) a 64-PE
- * barrier took 3.2 us instead of 5.9, a 256-PE one 9.5 instead of 21.5. */
+/* Counter barrier among `units` arriving work-groups; one thread per
+ * work-group calls it.  The arrival word holds the phase number (high 32
+ * bits) and the arrivals of the phase so far (low 32 bits); the generation
+ * word, VSHMEM_SYNC_GEN_OFF further on a line of its own, holds the number
+ * of completed phases.  An arrival learns its phase from its own fetch_add
+ * and waits until the generation reaches phase + 1; the last arrival
+ * resets the count with the next phase number and then releases the
+ * generation.  No separate read of the generation precedes the arrival: on
+ * a line of its own such a read can complete after the arrival, see the
+ * next generation, and wait for a phase that needs its own arrival.
+ * Release before arriving, acquire after leaving (in both the last arrival
+ * and the waiters), so it also completes (quiets) the arrivals' stores.
+ * Called after the work-group's threads waited for their own operations
+ * and synchronised, the release and acquire of this one thread cover the
+ * whole work-group: they write back and invalidate the caches the
+ * work-group's wavefronts share.  With the generation word on a line of
+ * its own a 64-PE barrier took 3.2 us instead of 5.9, a 256-PE one 9.5
+ * instead of 21.5 (waiters' polls no longer queue with the arrivals'
+ * atomics). */
 __device__ __forceinline__ void counter_barrier(const shmemx_dctx_pub_t &c, uint64_t *slot, uint64_t units)
 {
     uint64_t *cnt = slot;
     uint64_t *gen = (uint64_t *)((uint8_t *)slot + VSHMEM_SYNC_GEN_OFF);
     release_agent();
-    uint64_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t old = __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == units - 1) {
+    const uint64_t old = __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t next = (uint64_t)((uint32_t)(old >> 32) + 1u);
+    if ((old & 0xffffffffull) == units - 1) {
         acquire_agent();   // the other arrivals' releases
-        __hip_atomic_store(cnt, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(cnt, next << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(gen, next, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-        spin_until<false>(c, gen, 1 /*NE*/, g);
+        spin_until<false>(c, gen, 0 /*EQ*/, next);
     }
     acquire_agent();
 }

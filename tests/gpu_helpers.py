@@ -56,7 +56,8 @@ def device_array(a: np.ndarray):
 
 
 def assert_no_device_errors():
-    assert vs().device_errors() == 0
+    e = vs().device_errors()
+    assert e == 0, f"device error word {e:#x}"
 
 
 GOLD = 0x9E3779B97F4A7C15
