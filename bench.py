@@ -143,14 +143,14 @@ def build_rows(v, torch, L: Layout, npes: int, want):
     big = int(16 * MiB * min(1.0, scale))
     deep = v.LAUNCH_NONTEMPORAL | v.LAUNCH_DEEP
     f, b = rma(v.OP_PUT, v.SCOPE_WG, ring, big, 4, 1024, flags=deep)
-    add("put_wg_16MiB_ring", f, b, kernel="k_rma_pattern<2,true,true,8>")
+    add("put_wg_16MiB_ring", f, b, kernel="k_rma_pattern<2,true,true,8,1024>")
     f, b = rma(v.OP_GET, v.SCOPE_WG, perm, big, 4, 1024, flags=deep)
-    add("get_wg_16MiB_perm", f, b, kernel="k_rma_pattern<2,false,true,8>")
+    add("get_wg_16MiB_perm", f, b, kernel="k_rma_pattern<2,false,true,8,1024>")
     huge = int(64 * MiB * min(1.0, scale))
     f, b = rma(v.OP_PUT, v.SCOPE_GRID, perm, huge, 4, 256, flags=deep)
-    add("put_grid_64MiB_perm", f, b, kernel="k_rma_pattern<3,true,true,8>")
+    add("put_grid_64MiB_perm", f, b, kernel="k_rma_pattern<3,true,true,8,256>")
     f, b = rma(v.OP_PUT, v.SCOPE_WAVE, perm, 4096, 4, 256, flags=v.LAUNCH_NONTEMPORAL)
-    add("put_wave_4KiB_perm", f, b, kernel="k_rma_pattern<1,true,true,4>")
+    add("put_wave_4KiB_perm", f, b, kernel="k_rma_pattern<1,true,true,4,256>")
     f, b = rma(v.OP_GET, v.SCOPE_THREAD, ring, 64, 4, 256)
     add("get_thread_64B_ring", f, b)
     f, b = rma(v.OP_PUT, v.SCOPE_THREAD, perm, 8, 4, 1024)

@@ -319,7 +319,13 @@ void shmemx_clear_last_error(void);
  * <source>:<line>: <call>" for a failed call. */
 int shmemx_last_hip_error(char *buf, size_t len);
 /* Read and clear the device error word (SHMEMX_DEVERR_* bits); waits for
- * the device.  Returns the bits, or a negative code if not initialised. */
+ * the device.  Returns the bits, or a negative code if not initialised.
+ * When SHMEMX_DEVERR_WAIT_TIMEOUT was latched, a barrier may have been left
+ * with arrivals that never completed its phase, which would let the next
+ * barrier on those words release one arrival early.  So, with the device
+ * idle, the call then also clears every PE's scratch tail: every team's and
+ * plan's barrier words restart at phase 0.  Calls waiting in other
+ * processes' streams are not affected (one process owns the heap). */
 int shmemx_device_errors(void);
 /* Spin limit of device-side waits in nanoseconds (default 10 s).  A wait
  * that exceeds it gives up, latches SHMEMX_DEVERR_WAIT_TIMEOUT and returns,

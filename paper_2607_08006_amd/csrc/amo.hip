@@ -179,6 +179,10 @@ int shmemx_pingpong(uint64_t data_off, uint64_t sig_off, const int32_t *pairs, i
     // never satisfy a wait.
     const uint64_t tag = (g_pingpong_calls.fetch_add(1) & 0xFFFFFFFFull) << 32;
     const unsigned grid = same_xcd ? (unsigned)(((npairs + 7) / 8) * 16) : (unsigned)(2 * npairs);
+    if (int rc = check_coresident(k_pingpong, grid, 64, "pingpong")) {
+        set_last_error(rc);
+        return rc;
+    }
     hipLaunchKernelGGL(k_pingpong, dim3(grid), dim3(64), 0, (hipStream_t)stream, pub(), data_off, sig_off, pairs,
                        npairs, rounds, payload_bytes, same_xcd, tag, rtt_cycles);
     VSHMEM_HIP(hipGetLastError());
@@ -209,10 +213,7 @@ int shmemx_barrier_launch(shmem_team_t team, int iters, uint64_t tokens_off, uin
         set_last_error(SHMEMX_ERR_ARG);
         return SHMEMX_ERR_ARG;
     }
-    if (t.size > st().num_cus * 8) {
-        set_last_error(SHMEMX_ERR_ARG);
-        return SHMEMX_ERR_ARG;
-    }
+    if (int rc = check_coresident(k_barrier, t.size, 256, "barrier")) return rc;
     hipLaunchKernelGGL(k_barrier, dim3(t.size), dim3(256), 0, (hipStream_t)stream, pub(), t, iters, tokens_off, bad,
                        cycles);
     VSHMEM_HIP(hipGetLastError());

@@ -72,20 +72,6 @@ __global__ void __launch_bounds__(256) k_reduce(Geo g)
 }
 
 // ------------------------------------------------------------- launching
-template <typename K>
-int check_coresident(K kernel, int grid, int wg)
-{
-    int per_cu = 0;
-    if (int rc = blocks_per_cu(kernel, wg, &per_cu)) return rc;
-    if ((int64_t)per_cu * st().num_cus < grid) {
-        set_error_detail(SHMEMX_ERR_ARG, "%d work-groups of %d threads cannot be co-resident (%d per CU x %d CUs)", grid,
-                         wg, per_cu, st().num_cus);
-        if (st().debug) fprintf(stderr, "vshmem: %s\n", "collective work-groups cannot be co-resident");
-        return SHMEMX_ERR_ARG;
-    }
-    return SHMEMX_OK;
-}
-
 // Bytes a member writes per automatically added work-group: below this a
 // second work-group per member costs more in barrier arrivals than it saves
 // in copying (64 PEs: alltoall of 4 KiB blocks took 16 us with one
@@ -105,16 +91,17 @@ int launch_team_kernel(K kernel, Geo &g, int wg, hipStream_t s, bool auto_wgs, u
         // About one work-group per CU: in measurements on MI355X, streaming
         // kernels reached higher HBM bandwidth with one wide work-group per
         // CU than with the grid filled to its occupancy limit.
-        int per_cu = 0;
-        if (int rc = blocks_per_cu(kernel, wg, &per_cu)) return rc;
-        const int64_t cap = (int64_t)per_cu * st().num_cus;
+        // Only the CUs the progress kernel leaves free count.
+        int64_t cap = 0;
+        if (int rc = coresident_capacity(kernel, wg, &cap)) return rc;
+        const int64_t free_cus = st().num_cus - progress_reserved_cus();
         const uint64_t by_bytes = (bytes_per_member + kAutoBytesPerWg - 1) / kAutoBytesPerWg;
         const int64_t want = std::max<int64_t>(
-            1, std::min<int64_t>(st().num_cus / g.team.size, (int64_t)std::min<uint64_t>(by_bytes, 1u << 20)));
+            1, std::min<int64_t>(free_cus / g.team.size, (int64_t)std::min<uint64_t>(by_bytes, 1u << 20)));
         g.wgs_per_pe = (int)std::max<int64_t>(1, std::min<int64_t>(want, cap / g.team.size));
     }
     const int grid = g.wgs_per_pe * g.team.size;
-    if (int rc = check_coresident(kernel, grid, wg)) return rc;
+    if (int rc = check_coresident(kernel, grid, wg, "team collective")) return rc;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wg), 0, s, g, args...);
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;

@@ -559,6 +559,7 @@ struct Progress {
     uint64_t *claim = nullptr;         // device
     uint64_t slots = 0;
     std::atomic<uint64_t> head{0};
+    int reserved_cus = 0;   // CUs its work-groups hold while it runs
 };
 
 Progress g_prog;
@@ -606,6 +607,7 @@ T *dev_view(T *host)
 namespace vshmem {
 bool progress_running() { return g_prog.running; }
 void progress_release() { release_progress(); }
+int progress_reserved_cus() { return g_prog.running ? g_prog.reserved_cus : 0; }
 }  // namespace vshmem
 
 extern "C" {
@@ -682,6 +684,14 @@ int shmemx_progress_start(const shmemx_progress_cfg_t *cfg_in, void *stream)
     p.slots = slots;
     p.head.store(0);
     p.stream = hs;
+    // The CUs its work-groups occupy (per_cu of them fit a CU; a CU that
+    // holds any is taken as full by the co-residency checks).
+    int per_cu = 0;
+    if (int rc2 = blocks_per_cu(k_progress, cfg.wg_size, &per_cu)) {
+        release_progress();
+        return rc2;
+    }
+    p.reserved_cus = per_cu > 0 ? std::min(s.num_cus, (cfg.nwg + per_cu - 1) / per_cu) : s.num_cus;
     hipLaunchKernelGGL(k_progress, dim3(cfg.nwg), dim3(cfg.wg_size), 0, hs, a);
     if (VSHMEM_HIP_FAILED(hipGetLastError())) {
         release_progress();

@@ -8,9 +8,13 @@ using namespace vshmem;
 namespace {
 
 // Every virtual PE p issues nmsg messages to targets[p] at the given scope,
-// then quiets.  Work-group w acts for PE w / wgs_per_pe.
-template <int SCOPE, bool IS_PUT, bool NT, int U>
-__global__ void __launch_bounds__(1024) k_rma_pattern(shmemx_dctx_pub_t c, const int32_t *__restrict__ targets,
+// then quiets.  Work-group w acts for PE w / wgs_per_pe.  MAXT is the
+// largest work-group the instance accepts: launches of at most 256 threads
+// take an instance compiled for that size, whose register budget (up to 512
+// per lane) holds the 8-deep grid-scope body without spilling; under the
+// 1024-thread bound the same body needs 60 bytes of scratch per lane.
+template <int SCOPE, bool IS_PUT, bool NT, int U, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_rma_pattern(shmemx_dctx_pub_t c, const int32_t *__restrict__ targets,
                                                       uint64_t src_off, uint64_t dst_off, uint64_t msg, uint64_t nmsg,
                                                       uint64_t sstep, uint64_t dstep, int wgs_per_pe)
 {
@@ -49,9 +53,15 @@ void launch_pattern(int flags, int grid, int wg, hipStream_t s, const shmemx_dct
                     uint64_t so, uint64_t d, uint64_t m, uint64_t n, uint64_t ss, uint64_t ds, int wgs)
 {
     const bool nt = (flags & SHMEMX_LAUNCH_NONTEMPORAL) != 0, deep = (flags & SHMEMX_LAUNCH_DEEP) != 0;
-#define VSHMEM_PAT_K(NT, U)                                                                                      \
-    hipLaunchKernelGGL((k_rma_pattern<SCOPE, IS_PUT, NT, U>), dim3(grid), dim3(wg), 0, s, c, targets, so, d, m, n, ss, \
-                       ds, wgs)
+#define VSHMEM_PAT_K(NT, U)                                                                                        \
+    do {                                                                                                           \
+        if (wg <= 256)                                                                                             \
+            hipLaunchKernelGGL((k_rma_pattern<SCOPE, IS_PUT, NT, U, 256>), dim3(grid), dim3(wg), 0, s, c, targets, so, \
+                               d, m, n, ss, ds, wgs);                                                              \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_rma_pattern<SCOPE, IS_PUT, NT, U, 1024>), dim3(grid), dim3(wg), 0, s, c, targets,    \
+                               so, d, m, n, ss, ds, wgs);                                                          \
+    } while (0)
     if (nt && deep) VSHMEM_PAT_K(true, 8);
     else if (nt) VSHMEM_PAT_K(true, 4);
     else if (deep) VSHMEM_PAT_K(false, 8);

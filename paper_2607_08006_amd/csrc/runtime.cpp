@@ -582,10 +582,19 @@ void shmemx_clear_last_error(void) { vshmem::set_last_error(SHMEMX_OK); }
 int shmemx_device_errors(void)
 {
     if (int rc = check_ready()) return rc;
+    State &s = st();
     uint32_t v = 0;
     VSHMEM_HIP(hipDeviceSynchronize());
-    VSHMEM_HIP(hipMemcpy(&v, st().d_err, 4, hipMemcpyDeviceToHost));
-    VSHMEM_HIP(hipMemset(st().d_err, 0, 4));
+    VSHMEM_HIP(hipMemcpy(&v, s.d_err, 4, hipMemcpyDeviceToHost));
+    VSHMEM_HIP(hipMemset(s.d_err, 0, 4));
+    if (v & SHMEMX_DEVERR_WAIT_TIMEOUT) {
+        // A barrier that timed out keeps the arrivals it got; with the device
+        // idle, every barrier word (the scratch tail holds nothing else)
+        // restarts at phase 0, count 0.
+        for (int p = 0; p < s.npes; ++p)
+            VSHMEM_HIP(hipMemsetAsync(s.base + (uint64_t)p * s.stride + s.user_bytes, 0, VSHMEM_SCRATCH_BYTES, nullptr));
+        VSHMEM_HIP(hipStreamSynchronize(nullptr));
+    }
     return (int)(v & 0x7fffffffu);
 }
 

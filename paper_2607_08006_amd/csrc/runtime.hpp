@@ -117,6 +117,51 @@ int blocks_per_cu(K kernel, int wg, int *per_cu)
 
 bool progress_running();
 void progress_release();
+// CUs the running persistent progress kernel holds (0 when it is not
+// running).  Its work-groups never leave until it stops, so a CU that holds
+// one is counted as full.
+int progress_reserved_cus();
+
+// Work-groups of `kernel` at `wg` threads that can be resident at once on
+// the CUs the progress kernel leaves free.
+template <typename K>
+int coresident_capacity(K kernel, int wg, int64_t *cap)
+{
+    int per_cu = 0;
+    if (int rc = blocks_per_cu(kernel, wg, &per_cu)) return rc;
+    const int free_cus = st().num_cus - progress_reserved_cus();
+    *cap = (int64_t)per_cu * (free_cus > 0 ? free_cus : 0);
+    return SHMEMX_OK;
+}
+
+// Check before launching a kernel whose `grid` work-groups wait for each
+// other (team and plan barriers, paired signal waits): all of them must be
+// resident together, or the waits can only end at the spin limit.  Returns
+// SHMEMX_ERR_BUSY when they would fit an idle device but not next to the
+// running progress kernel, SHMEMX_ERR_ARG when they never fit.  Only the
+// library's own persistent kernel is accounted for; kernels the caller runs
+// on other streams at the same time are the caller's to keep apart.
+template <typename K>
+int check_coresident(K kernel, int64_t grid, int wg, const char *what)
+{
+    int per_cu = 0;
+    if (int rc = blocks_per_cu(kernel, wg, &per_cu)) return rc;
+    const int reserved = progress_reserved_cus();
+    const int64_t idle_cap = (int64_t)per_cu * st().num_cus;
+    const int64_t cap = (int64_t)per_cu * (st().num_cus > reserved ? st().num_cus - reserved : 0);
+    if (grid <= cap) return SHMEMX_OK;
+    if (grid <= idle_cap) {
+        set_error_detail(SHMEMX_ERR_BUSY,
+                         "%s: %lld work-groups of %d threads cannot be co-resident next to the progress kernel "
+                         "(%d per CU x %d free CUs of %d)",
+                         what, (long long)grid, wg, per_cu, st().num_cus - reserved, st().num_cus);
+        return SHMEMX_ERR_BUSY;
+    }
+    set_error_detail(SHMEMX_ERR_ARG, "%s: %lld work-groups of %d threads cannot be co-resident (%d per CU x %d CUs)",
+                     what, (long long)grid, wg, per_cu, st().num_cus);
+    if (st().debug) fprintf(stderr, "vshmem: %s: work-groups cannot be co-resident\n", what);
+    return SHMEMX_ERR_ARG;
+}
 
 }  // namespace vshmem
 

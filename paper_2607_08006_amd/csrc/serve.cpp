@@ -197,8 +197,13 @@ struct WindowBackend final : Backend {
     WindowBatcher *wb = nullptr;
     std::mutex mu;
     std::condition_variable cv;
-    std::vector<std::pair<shmemx_desc_t, size_t>> pending;
-    Clock::time_point oldest;
+    struct Pending {
+        shmemx_desc_t d;
+        size_t index;
+        Clock::time_point enqueued;
+    };
+    std::vector<Pending> pending;
+    Clock::time_point oldest;   // enqueue time of pending.front()
     std::vector<std::atomic<int64_t>> batch_of;   // request -> batch, -1 before launch
     std::vector<hipEvent_t> batch_done;           // batch -> event (grows; guarded by events_mu)
     std::mutex events_mu;
@@ -247,11 +252,13 @@ struct WindowBackend final : Backend {
                 d.clear();
                 idx.clear();
                 for (size_t i = 0; i < take; ++i) {
-                    d.push_back(pending[i].first);
-                    idx.push_back(pending[i].second);
+                    d.push_back(pending[i].d);
+                    idx.push_back(pending[i].index);
                 }
                 pending.erase(pending.begin(), pending.begin() + (ptrdiff_t)take);
-                if (!pending.empty()) oldest = Clock::now();
+                // The window of what is left runs from its own oldest arrival,
+                // not from this dispatch.
+                if (!pending.empty()) oldest = pending.front().enqueued;
             }
             const int slot = (int)(batches % kWindowSlots);
             if (slot_event[slot] && VSHMEM_HIP_FAILED(hipEventSynchronize(slot_event[slot]))) {
@@ -282,8 +289,9 @@ struct WindowBackend final : Backend {
         if (int rc = error.load()) return rc;
         {
             std::lock_guard<std::mutex> lk(mu);
-            if (pending.empty()) oldest = Clock::now();
-            pending.emplace_back(d, index);
+            const Clock::time_point now = Clock::now();
+            if (pending.empty()) oldest = now;
+            pending.push_back(Pending{d, index, now});
         }
         cv.notify_all();
         *ticket = index;

@@ -31,13 +31,13 @@ class Memory:
         return idx, self.gen_hist[idx]
 
 
-def run_model(units_per_phase, seed):
+def run_model(units_per_phase, seed, mem=None):
     """Consecutive phases with the same member count are barriers inside one
     launch: members run ahead into the next phase freely.  A phase with a
     different member count is a later launch in stream order: it starts
     only after every member of the previous phase has left it."""
     rng = random.Random(seed)
-    mem = Memory()
+    mem = Memory() if mem is None else mem
     arrived, left = {}, {}
     nagents = max(units_per_phase)
     nph = len(units_per_phase)
@@ -97,6 +97,36 @@ def test_barrier_phases_hold_under_any_interleaving(seed):
     units = [rng.choice([1, 2, 3, 5, 8]) for _ in range(12)]
     mem = run_model(units, seed)
     assert mem.gen_hist[-1] == len(units) and mem.cnt == len(units) << 32
+
+
+def timed_out_phase(units):
+    """Memory after a barrier phase in which one of `units` members never
+    arrived: the others added themselves, waited out the spin limit and left
+    (the kernel latches a timeout and ends), so the count still holds
+    units - 1 arrivals of phase 0 and the generation never moved."""
+    mem = Memory()
+    for _ in range(units - 1):
+        mem.fetch_add_cnt()
+    return mem
+
+
+@pytest.mark.parametrize("units", [2, 3, 8])
+def test_stale_words_after_a_timeout_release_the_next_barrier_early(units):
+    """Left as they are, the words of a timed-out phase make the next
+    barrier's first arrival the "last" one: it leaves before the others
+    arrive.  Clearing them (what the host does once it reads a latched
+    timeout with the device idle) gives a barrier that holds again."""
+    early = 0
+    for seed in range(30):
+        try:
+            run_model([units] * 4, seed, mem=timed_out_phase(units))
+        except AssertionError as e:
+            assert "before every arrival" in str(e) or "wrong phase" in str(e)
+            early += 1
+    assert early == 30
+    for seed in range(30):
+        mem = run_model([units] * 4, seed, mem=Memory())   # the cleared words
+        assert mem.gen_hist[-1] == 4 and mem.cnt == 4 << 32
 
 
 def run_old_model(units, nphases, seed, limit=20_000):
