@@ -222,3 +222,58 @@ def test_strided_team_collectives():
         with pytest.raises(v.VshmemError):
             v.alltoallmem(dst, dst + 8, 64)                  # overlapping ranges
         assert_no_device_errors()
+
+
+_ES = {oracle.DT_INT64: 8, oracle.DT_FP32: 4, oracle.DT_BF16: 2}
+_BITS = {oracle.DT_INT64: np.int64, oracle.DT_FP32: np.uint32, oracle.DT_BF16: np.uint16}
+
+
+def _same_results(got, ref, dt):
+    """Bit-identical, except that a NaN result only has to be a NaN: IEEE-754
+    fixes neither the sign nor the payload of the NaN an invalid operation
+    (inf + -inf) produces, and x86 and gfx950 pick different ones."""
+    g, r = got.view(_BITS[dt]), ref.view(_BITS[dt])
+    if dt == oracle.DT_INT64:
+        return np.array_equal(g, r)
+    if dt == oracle.DT_FP32:
+        rn, gn = np.isnan(r.view(np.float32)), np.isnan(g.view(np.float32))
+    else:
+        rn = ((r & 0x7F80) == 0x7F80) & ((r & 0x7F) != 0)
+        gn = ((g & 0x7F80) == 0x7F80) & ((g & 0x7F) != 0)
+    return np.array_equal(rn, gn) and np.array_equal(g[~rn], r[~rn])
+
+
+@pytest.mark.parametrize("npes", [13, 64, 130])
+@pytest.mark.parametrize("dt", [oracle.DT_INT64, oracle.DT_FP32, oracle.DT_BF16])
+def test_reduction_edge_values_bit_exact(npes, dt):
+    """Edge-case columns against the oracle, sum and max: signed zeros at
+    every TREE position (max ties keep the lower PE), fp32/bf16 subnormal
+    inputs and sums that stay subnormal or cross into the normal range,
+    one infinity, both infinities, values near the largest finite one
+    (overflow in fp32, or at the final bf16 rounding), NaN inputs, bf16
+    rounding ties, and int64 MIN/MAX.  Aligned bases take the vector path,
+    a base one element past a 16-byte boundary the scalar path."""
+    es = _ES[dt]
+    K = 4099                                   # several tiles and a ragged tail
+    cols = W.reduce_edge_columns(dt, npes, K, W.subseed(W.SEED_COLL, 0xED6E + 131 * npes + dt))
+    with heap(npes, 1 << 20) as v:
+        src = v.malloc(K * es + 64)
+        dst = v.malloc(K * es + 64)
+        so, do = v.offset(src), v.offset(dst)
+        region = do + K * es + 64
+        for shift in (0, es):
+            init = np.zeros((npes, region), dtype=np.uint8)
+            init[:, so + shift:so + shift + K * es] = np.ascontiguousarray(cols).view(np.uint8).reshape(npes, K * es)
+            for rop in (oracle.RO_SUM, oracle.RO_MAX):
+                upload(init)
+                v.reduce(dt, rop, dst + shift, src + shift, K)
+                got = download(region)
+                ref = init.copy()
+                oracle.reduce(ref, dt, rop, do + shift, so + shift, K)
+                lo, hi = do + shift, do + shift + K * es
+                assert np.array_equal(got[:, :lo], ref[:, :lo]) and np.array_equal(got[:, hi:], ref[:, hi:])
+                for p in (0, npes // 2, npes - 1):
+                    assert np.array_equal(got[p, lo:hi], got[0, lo:hi])
+                g, r = got[0, lo:hi].copy(), ref[0, lo:hi].copy()
+                assert _same_results(g, r, dt), (npes, dt, rop, shift)
+        assert_no_device_errors()

@@ -223,6 +223,30 @@ def test_serving_128pes_full_size_sampled_hashes():
                 spe = r.issuer_pe if r.op == W.OP_PUT else r.target_pe
                 want = out_hash(W.payload(seed_of(spe), r.src_off, r.nbytes))
             assert comps[i].hash == want, (i, r.op, r.nbytes)
+        # The bytes themselves: read back the destination of every sampled
+        # request whose range no request completing after it overlapped
+        # (admission hands freed ranges out again), and compare them with the
+        # generator's source bytes (or the zero values fresh counters held).
+        out_pe = [r.target_pe if r.op == W.OP_PUT else r.issuer_pe for r in reqs]
+        on_pe = {}
+        for j in range(n):
+            on_pe.setdefault(out_pe[j], []).append(j)
+        h = v.heap_view()
+        checked = 0
+        for i in pick:
+            r = reqs[i]
+            lo, hi = int(dst[i]), int(dst[i]) + r.nbytes
+            if any(j != i and int(dst[j]) < hi and lo < int(dst[j]) + reqs[j].nbytes
+                   and comps[j].t_end >= comps[i].t_end for j in on_pe[out_pe[i]]):
+                continue
+            got = h[out_pe[i], lo:hi].cpu().numpy()
+            if r.op == W.OP_AMO_FETCH_ADD:
+                assert not got.any(), (i, r.nbytes)
+            else:
+                spe = r.issuer_pe if r.op == W.OP_PUT else r.target_pe
+                assert np.array_equal(got, W.payload(seed_of(spe), r.src_off, r.nbytes)), (i, r.op, r.nbytes)
+            checked += 1
+        assert checked >= 50, checked
         assert_no_device_errors()
 
 

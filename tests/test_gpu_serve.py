@@ -127,6 +127,8 @@ def test_backlog_split_matches_oracle():
             if op == W.OP_AMO_FETCH_ADD:
                 amo_out[i, d:d + n] = True
         assert np.array_equal(got[~amo_out], ref[~amo_out])
+        ctr0, ctr_words = 6 << 20, (1 << 20) // 8          # every counter lies in [6 MiB, 7 MiB)
+        words, fetched = [], []
         for tk, (op, i, tg, s, d, n) in zip(tickets, reqs):
             c = comps[tk]
             assert c.status == 0 and c.t_end >= c.t_start > 0
@@ -134,10 +136,19 @@ def test_backlog_split_matches_oracle():
                 out_pe = tg if op == W.OP_PUT else i
                 assert c.hash == out_hash(ref[out_pe, d:d + n])
             else:
-                # fetched values: multiples of 3 below each counter's final value
-                fetched = got[i, d:d + n].view(np.uint64)
-                final = ref[tg, s:s + n].view(np.uint64)
-                assert ((fetched % 3) == 0).all() and (fetched < final).all()
+                assert ctr0 <= s and s + n <= ctr0 + 8 * ctr_words
+                words.append(tg * ctr_words + (s - ctr0) // 8 + np.arange(n // 8, dtype=np.uint64))
+                fetched.append(got[i, d:d + n].view(np.uint64))
+        # Requests share counters, so the fetched values depend on the order
+        # the device applied them in: witness replay must find, for every
+        # counter, a serial order of its fetch_add(+3)s that explains each
+        # fetched value and the final value (untouched counters stay zero).
+        words, fetched = np.concatenate(words), np.concatenate(fetched)
+        init_w = init[:, ctr0:ctr0 + 8 * ctr_words].copy().view(np.uint64).ravel()
+        final_w = got[:, ctr0:ctr0 + 8 * ctr_words].copy().view(np.uint64).ravel()
+        assert oracle.witness_check(words, np.full(len(words), oracle.KIND_FETCH_ADD, dtype=np.uint8),
+                                    np.full(len(words), 3, dtype=np.uint64), fetched, init_w, final_w) == 0
+        assert np.array_equal(final_w, ref[:, ctr0:ctr0 + 8 * ctr_words].copy().view(np.uint64).ravel())
         assert_no_device_errors()
 
 

@@ -478,6 +478,104 @@ def test_max_matches_numpy_and_tie_keeps_left_operand():
     assert np.signbit(_reduce_cols(z, oracle.DT_FP32, oracle.RO_MAX)[0]) == True
 
 
+def _f32(bits):
+    return np.asarray(bits, dtype=np.uint32).view(np.float32)
+
+
+def test_signed_zero_sums_and_max_closed_forms():
+    """Sums of signed zeros: RNE gives -0 only for (-0) + (-0), so any order
+    yields -0 iff every input is -0.  max of equal values keeps the left
+    operand at every pairing, so TREE returns PE 0's element."""
+    for P in (2, 3, 13, 64, 130):
+        K = 300
+        signs = (W.splitmix64(900 + P, 0, P * K) >> np.uint64(63)).reshape(P, K)
+        signs[:, 0] = 1                                   # a column of -0 only
+        signs[:, 1] = 0                                   # and one of +0 only
+        cols = _f32((signs.astype(np.uint32) << 31))
+        s = _reduce_cols(cols, oracle.DT_FP32, oracle.RO_SUM)
+        assert np.array_equal(np.signbit(s), signs.all(axis=0)), P
+        assert np.all(s == 0)
+        m = _reduce_cols(cols, oracle.DT_FP32, oracle.RO_MAX)
+        assert np.array_equal(np.signbit(m), signs[0].astype(bool)), P
+        b = (signs.astype(np.uint16) << 15)
+        sb = _reduce_cols(b, oracle.DT_BF16, oracle.RO_SUM)
+        assert np.array_equal(sb, np.where(signs.all(axis=0), 0x8000, 0).astype(np.uint16))
+        mb = _reduce_cols(b, oracle.DT_BF16, oracle.RO_MAX)
+        assert np.array_equal(mb, b[0])
+
+
+def test_subnormal_sums_are_exact():
+    """Inputs that are integer multiples of 2^-149 (fp32 subnormals) or of
+    2^-133 (bf16 subnormals): every partial sum is an integer multiple of the
+    same unit below 2^24 units, so each fp32 add is exact and TREE equals the
+    exact sum, which Python integers give."""
+    for P in (2, 13, 64, 130):
+        K = 200
+        x = W.splitmix64(700 + P, 0, P * K).reshape(P, K)
+        m = (x & np.uint64(0xFFFF)).astype(np.int64)           # |m| < 2^16: P * 2^16 < 2^24
+        neg = (x >> np.uint64(63)).astype(bool)
+        bits = (m.astype(np.uint32) | (neg.astype(np.uint32) << 31))
+        got = _reduce_cols(_f32(bits), oracle.DT_FP32, oracle.RO_SUM)
+        for k in range(K):
+            exact = sum((-int(m[p, k]) if neg[p, k] else int(m[p, k])) for p in range(P))
+            assert Fraction(float(got[k])) == Fraction(exact, 1 << 149), (P, k)
+        # bf16 subnormals: mantissa m < 128, value m * 2^-133; the fp32 sum is
+        # exact, and the result is that sum rounded once (torch's RNE).
+        torch = pytest.importorskip("torch")
+        mb = (x & np.uint64(0x7F)).astype(np.int64)
+        bb = (mb.astype(np.uint16) | (neg.astype(np.uint16) << 15))
+        gotb = _reduce_cols(bb, oracle.DT_BF16, oracle.RO_SUM)
+        exact = np.array([sum((-int(mb[p, k]) if neg[p, k] else int(mb[p, k])) for p in range(P)) for k in range(K)])
+        f = np.ldexp(exact.astype(np.float64), -133).astype(np.float32)
+        assert np.array_equal(f.astype(np.float64), np.ldexp(exact.astype(np.float64), -133))  # exact in fp32
+        want = torch.from_numpy(f).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+        assert np.array_equal(gotb, want), P
+
+
+def test_infinities_and_overflow_closed_forms():
+    """IEEE-754 facts: x + inf = inf for finite x; inf + (-inf) is NaN (and
+    NaN + x stays NaN); FLT_MAX + FLT_MAX overflows to inf under RNE, while
+    FLT_MAX + (-FLT_MAX) = +0; max with an infinity is +inf (or the largest
+    finite value when only -inf is present)."""
+    inf, ninf, fmax = 0x7F800000, 0xFF800000, 0x7F7FFFFF
+    u = W.uniform_f32(W.splitmix64(31, 0, 64)).view(np.uint32)
+    for P in (2, 5, 13, 64):
+        base = np.resize(u, P).astype(np.uint32)
+        col = base.copy(); col[P // 2] = inf
+        assert _reduce_cols(_f32(col)[:, None], oracle.DT_FP32, oracle.RO_SUM)[0] == np.inf
+        assert _reduce_cols(_f32(col)[:, None], oracle.DT_FP32, oracle.RO_MAX)[0] == np.inf
+        col = base.copy(); col[0] = ninf
+        assert _reduce_cols(_f32(col)[:, None], oracle.DT_FP32, oracle.RO_SUM)[0] == -np.inf
+        assert _reduce_cols(_f32(col)[:, None], oracle.DT_FP32, oracle.RO_MAX)[0] == _f32(base[1:]).max()
+        col = base.copy(); col[0] = inf; col[P - 1] = ninf
+        assert np.isnan(_reduce_cols(_f32(col)[:, None], oracle.DT_FP32, oracle.RO_SUM)[0])
+        col = np.full(P, fmax, dtype=np.uint32)
+        assert _reduce_cols(_f32(col)[:, None], oracle.DT_FP32, oracle.RO_SUM)[0] == np.inf
+        colb = np.full(P, 0x7F7F, dtype=np.uint16)                 # bf16 max finite: overflows in fp32
+        assert _reduce_cols(colb[:, None], oracle.DT_BF16, oracle.RO_SUM)[0] == 0x7F80
+    pair = np.array([fmax, fmax | 0x80000000], dtype=np.uint32)
+    r = _reduce_cols(_f32(pair)[:, None], oracle.DT_FP32, oracle.RO_SUM)[0]
+    assert r == 0 and not np.signbit(r)
+    # bf16 max finite plus a value that moves the fp32 sum past the midpoint
+    # to the next (infinite) bf16 value rounds to inf once at the end.
+    half_ulp = np.float32(2.0 ** (127 - 8))
+    top = np.uint32(0x7F7F) << 16
+    s = np.float32(_f32(top)) + half_ulp
+    assert W.f32_to_bf16_bits(np.array([s]))[0] == 0x7F80
+
+
+def test_int64_extremes_max_and_wrapping_sum():
+    ext = np.array([-(1 << 63), (1 << 63) - 1, -1, 0, 1], dtype=np.int64)
+    for P in (2, 13, 64, 130):
+        K = 100
+        cols = ext[W.bounded(W.splitmix64(50 + P, 0, P * K), 0, 4)].reshape(P, K)
+        assert np.array_equal(_reduce_cols(cols, oracle.DT_INT64, oracle.RO_MAX), cols.max(axis=0))
+        got = _reduce_cols(cols, oracle.DT_INT64, oracle.RO_SUM)
+        for k in range(K):
+            exact = sum(int(v) for v in cols[:, k]) % (1 << 64)
+            assert int(got[k]) % (1 << 64) == exact
+
+
 # -------------------------------------------------------- GUPS and witness
 def test_gups_closed_forms_for_single_kind_words():
     log2 = 10

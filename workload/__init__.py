@@ -356,6 +356,89 @@ def coll_bf16(seed: int, pe: int, count: int) -> np.ndarray:
     return f32_to_bf16_bits(coll_f32(seed, pe, count))
 
 
+# Edge-case inputs of the reductions.  Column k of the (npes, count) array
+# belongs to category k mod (number of categories); each element is a bit
+# pattern drawn from its category's set with SplitMix64 draws.  The arrays
+# are storage bits: int64 values, fp32 bits (uint32) or bf16 bits (uint16).
+EDGE_I64_CATS = ("extremes", "min_max_only", "full_range", "equal")
+EDGE_F32_CATS = ("signed_zeros", "subnormals", "subnormal_boundary", "one_inf", "both_infs",
+                 "near_max", "nan", "mixed", "uniform")
+EDGE_BF16_CATS = ("signed_zeros", "subnormals", "subnormal_boundary", "one_inf", "both_infs",
+                  "near_max", "nan", "final_tie", "uniform")
+
+
+def reduce_edge_columns(dt: int, npes: int, count: int, seed: int) -> np.ndarray:
+    """dt: 0 int64, 1 fp32, 2 bf16 (the reductions' datatype codes)."""
+    x = splitmix64(seed, 0, 4 * npes * count).reshape(npes, count, 4)
+    a, b, c, d = (x[..., i] for i in range(4))
+    col = np.arange(count)[None, :].repeat(npes, 0)
+    pe = np.arange(npes)[:, None].repeat(count, 1)
+    sign = (a >> np.uint64(63)).astype(np.uint64)
+    # one position per column, for the categories that plant a special value
+    pick = bounded(splitmix64(seed ^ 0x51, 0, count), 0, npes - 1)[None, :].repeat(npes, 0)
+    pick2 = bounded(splitmix64(seed ^ 0x52, 0, count), 0, npes - 1)[None, :].repeat(npes, 0)
+    if dt == 0:
+        cat = col % len(EDGE_I64_CATS)
+        ext = np.array([-(1 << 63), (1 << 63) - 1, -1, 0, 1, -(1 << 63) + 1, (1 << 63) - 2], dtype=np.int64)
+        out = np.where(cat == 0, ext[bounded(b, 0, len(ext) - 1)], 0)
+        out = np.where(cat == 1, np.where(sign == 1, ext[0], ext[1]), out)
+        out = np.where(cat == 2, c.view(np.int64), out)
+        out = np.where(cat == 3, (d[0:1, :].view(np.int64)).repeat(npes, 0), out)
+        return out.astype(np.int64)
+    if dt == 1:
+        ncat = len(EDGE_F32_CATS)
+        cat = col % ncat
+        sbit = sign << np.uint64(31)
+        uni = uniform_f32(b).view(np.uint32).astype(np.uint64)
+        sub_small = sbit | np.maximum(c & np.uint64(0xFFFF), np.uint64(1))      # 0 < |x| < 2^-133
+        sub_any = sbit | (c & np.uint64(0x7FFFFF))                              # any subnormal
+        near_min = sbit | (bounded(d, 1, 2).astype(np.uint64) << np.uint64(23)) | (c & np.uint64(0x7FFFFF))
+        near_max = sbit | np.uint64(0x7F7FFFFF) - (c & np.uint64(0xFFFF))
+        qnan = np.uint64(0x7FC00000) | (c & np.uint64(0x3FFFFF)) | sbit
+        inf = sbit | np.uint64(0x7F800000)
+        out = np.zeros((npes, count), dtype=np.uint64)
+        out = np.where(cat == 0, sbit, out)
+        out = np.where(cat == 1, sub_small, out)
+        out = np.where(cat == 2, np.where((d & np.uint64(1)) == 0, sub_any, near_min), out)
+        out = np.where(cat == 3, np.where(pe == pick, inf, uni), out)
+        out = np.where(cat == 4, np.where(pe == pick, np.uint64(0x7F800000),
+                                          np.where(pe == (pick + 1) % npes, np.uint64(0xFF800000), uni)), out)
+        out = np.where(cat == 5, near_max, out)
+        out = np.where(cat == 6, np.where(pe == pick, qnan, uni), out)
+        mix_set = np.stack([sbit, sub_any, near_min, uni, near_max, inf])
+        out = np.where(cat == 7, np.take_along_axis(mix_set, bounded(d, 0, 5)[None].astype(np.int64), 0)[0], out)
+        out = np.where(cat == 8, uni, out)
+        return out.astype(np.uint32)
+    ncat = len(EDGE_BF16_CATS)
+    cat = col % ncat
+    sbit = sign << np.uint64(15)
+    uni = f32_to_bf16_bits(uniform_f32(b)).astype(np.uint64)
+    sub = sbit | np.maximum(c & np.uint64(0x7F), np.uint64(1))
+    near_min = sbit | (bounded(d, 1, 2).astype(np.uint64) << np.uint64(7)) | (c & np.uint64(0x7F))
+    near_max = sbit | np.uint64(0x7F7F) - (c & np.uint64(0x3))
+    inf = sbit | np.uint64(0x7F80)
+    qnan = np.uint64(0x7FC0) | (c & np.uint64(0x3F)) | sbit
+    # final_tie: a normal value at `pick` and, at `pick2`, half of its unit in
+    # the last place (exponent 8 below, mantissa 0) with a random sign; every
+    # other element a signed zero, so the fp32 sum lies halfway between two
+    # bf16 values whenever pick != pick2.
+    exp = bounded(d, 20, 200).astype(np.uint64)
+    base_v = (exp << np.uint64(7)) | (c & np.uint64(0x7F))
+    half = sbit | ((exp - np.uint64(8)) << np.uint64(7))
+    out = np.zeros((npes, count), dtype=np.uint64)
+    out = np.where(cat == 0, sbit, out)
+    out = np.where(cat == 1, sub, out)
+    out = np.where(cat == 2, np.where((d & np.uint64(1)) == 0, sub, near_min), out)
+    out = np.where(cat == 3, np.where(pe == pick, inf, uni), out)
+    out = np.where(cat == 4, np.where(pe == pick, np.uint64(0x7F80),
+                                      np.where(pe == (pick + 1) % npes, np.uint64(0xFF80), uni)), out)
+    out = np.where(cat == 5, near_max, out)
+    out = np.where(cat == 6, np.where(pe == pick, qnan, uni), out)
+    out = np.where(cat == 7, np.where(pe == pick, base_v, np.where(pe == pick2, half, sbit)), out)
+    out = np.where(cat == 8, uni, out)
+    return out.astype(np.uint16)
+
+
 # --------------------------------------------------------------- serving
 @dataclasses.dataclass
 class ServeRequest:
