@@ -627,6 +627,23 @@ typedef struct shmemx_plan shmemx_plan_t;
 
 /* Fill a tune table with the built-in defaults. */
 void shmemx_tune_default(shmemx_tune_t *tune);
+
+/* The library's ACTIVE tune table: the work-group size and grid cap of the
+ * device-table launchers below, and the per-class scope and chunk they use
+ * when the caller passes no table of its own.  At initialisation it is the
+ * table that the file named by VSHMEM_TUNE_FILE holds, when that file loads
+ * (shmemx_tune_load: saved on this kind of device, valid), else the built-in
+ * defaults.  shmemx_tune_set waits for the device to go idle, then replaces
+ * it (SHMEMX_ERR_ARG for an invalid table: work-group size not a multiple of
+ * 64 in [64, 1024], negative grid cap, unknown scope).  shmemx_tune_get
+ * copies it out and returns where it came from (SHMEMX_TUNE_SRC_*), or a
+ * negative error. */
+#define SHMEMX_TUNE_SRC_DEFAULT 0
+#define SHMEMX_TUNE_SRC_FILE 1
+#define SHMEMX_TUNE_SRC_FILE_REFUSED 2   /* VSHMEM_TUNE_FILE was set but refused: defaults */
+#define SHMEMX_TUNE_SRC_SET 3
+int shmemx_tune_set(const shmemx_tune_t *tune);
+int shmemx_tune_get(shmemx_tune_t *tune);
 /* Build a plan from HOST descriptors (copied).  tune may be NULL.
  * Validates every descriptor (ranges inside the user heap, PEs, op codes,
  * equal barrier counts) and returns SHMEMX_ERR_ARG with no plan otherwise.
@@ -635,7 +652,12 @@ void shmemx_tune_default(shmemx_tune_t *tune);
  * why). */
 int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t *tune, shmemx_plan_t **plan);
 /* One fused launch of the whole plan.  results: DEVICE uint64 array with
- * room for every result index used, or NULL if none. */
+ * room for every result index used, or NULL if none.  Each plan has grid
+ * barrier words of its own, so fused launches of DIFFERENT plans may run at
+ * the same time on different streams, provided their grids fit the device
+ * together (cap them with tune->grid_wgs): work-groups of a multi-phase
+ * launch wait for each other.  Launches of ONE plan must be ordered (same
+ * stream, or synchronised): they share its barrier words. */
 int shmemx_plan_launch_fused(shmemx_plan_t *plan, uint64_t *results, void *stream);
 /* One kernel launch per operation, in program order. */
 int shmemx_plan_launch_per_op(shmemx_plan_t *plan, uint64_t *results, void *stream);
@@ -664,9 +686,63 @@ void shmemx_plan_destroy(shmemx_plan_t *plan);
  * the result to *tune.  Synchronous. */
 int shmemx_autotune(uint64_t scratch_off, uint64_t scratch_bytes, uint64_t min_bytes, uint64_t max_bytes,
                     int msgs, int reps, shmemx_tune_t *tune, void *stream);
-/* Save / load a tune table as JSON keyed by the device name. */
+/* Save / load a tune table as JSON keyed by the device name (the HIP
+ * architecture name, e.g. gfx950:sramecc+:xnack-).  Load refuses a file
+ * saved on another kind of device, or without a device key, and an invalid
+ * table (SHMEMX_ERR_ARG; *tune unchanged). */
 int shmemx_tune_save(const shmemx_tune_t *tune, const char *path);
 int shmemx_tune_load(shmemx_tune_t *tune, const char *path);
+
+/* ------------------------------------- batches over a DEVICE descriptor table
+ * The same program semantics as plans (each PE's program is the subsequence
+ * of descriptors it issues; an operation's phase is its issuer's count of
+ * barriers and of fences/quiets since the last barrier; phases run in
+ * order, operations inside one run concurrently and must not conflict), but
+ * the table is in DEVICE memory and is read on the device at every launch:
+ * a kernel may write it, and a graph replays whatever it holds when the
+ * replay runs.  Long-lived kernels that consume descriptor tables are the
+ * paper's Section 3 case for device-side batching; the launches are
+ * stream-ordered (Section 4.3).
+ *
+ *   d_descs   DEVICE array of n descriptors (caller-owned; it must not change
+ *             while a launch reading it runs).
+ *   d_results DEVICE uint64 array of n entries, or NULL: fetching atomics
+ *             write results[result_idx] (result_idx < n, or SHMEMX_NO_RESULT).
+ *   d_tune    DEVICE tune table for scope and chunk per size class, or NULL
+ *             for the active table (shmemx_tune_set).  Work-group size and
+ *             grid cap always come from the active table.
+ *
+ * Descriptors the device finds invalid (op code, PEs, ranges outside the
+ * user heap, misaligned words, WAIT_UNTIL, result index >= n) are skipped
+ * and latch SHMEMX_DEVERR_BAD_DESC; unequal barrier counts across the PEs'
+ * programs latch it and run nothing.  Host-side errors: SHMEMX_ERR_ARG
+ * (NULL table with n > 0, n > 2^26), SHMEMX_ERR_UNSUPPORTED (more than 4096
+ * PEs: the ordering state of the index kernel is per PE), SHMEMX_ERR_BUSY
+ * (no CU free next to the progress kernel), SHMEMX_ERR_HIP.
+ *
+ * shmemx_launch_batch: the fused form.  An index kernel (one work-group)
+ * derives phases, scopes, chunks and a counting sort by (phase, kind) in a
+ * workspace the library keeps per stream (grown on demand; growing
+ * synchronises that stream); an executor of up to grid-cap work-groups pops
+ * tasks from an atomic cursor per phase, with a grid barrier between phases.
+ * Launches on one stream are ordered; launches on different streams use
+ * different workspaces and must fit the device together.
+ * shmemx_launch_per_op: one kernel launch per descriptor, in table order
+ * (stream order is the ordering; fence/quiet/barrier descriptors launch
+ * nothing).
+ * shmemx_graph_build: capture form 0 (per-op) or 1 (fused, with a workspace
+ * of the graph's own) into a graph; shmemx_graph_launch replays it on any
+ * stream (replays of one graph must be ordered); shmemx_graph_destroy frees
+ * it. */
+typedef struct shmemx_graph shmemx_graph_t;
+int shmemx_launch_batch(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
+                        void *stream);
+int shmemx_launch_per_op(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
+                         void *stream);
+int shmemx_graph_build(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
+                       int form, shmemx_graph_t **graph);
+int shmemx_graph_launch(shmemx_graph_t *graph, void *stream);
+void shmemx_graph_destroy(shmemx_graph_t *graph);
 
 /* ------------------------------------------------------------- serving
  * Persistent progress kernel (long-lived kernels, Section 3; GPU-driven
@@ -696,16 +772,22 @@ typedef struct shmemx_completion {
     uint64_t t_end;           /* device wall clock at completion */
     uint64_t hash;            /* output hash when verify is on */
     int32_t status;           /* 0 ok */
-    int32_t reserved;
+    int32_t lane;             /* producer lane the request was submitted on */
     uint64_t t_queued;        /* device wall clock when the front-end took it from the ring */
     uint64_t submit_ns;       /* serving runs: host ns from arrival to ring publish; else 0 */
 } shmemx_completion_t;
 
 int shmemx_progress_start(const shmemx_progress_cfg_t *cfg, void *stream);
-/* Multi-producer: enqueue one request; *ticket identifies it.  AMO fetch
- * results go to the issuer's [dst, dst + nbytes).  Returns
- * SHMEMX_ERR_BUSY when the ring is full. */
-int shmemx_progress_submit(const shmemx_desc_t *desc, uint64_t *ticket);
+/* Multi-producer: enqueue one request from producer lane `lane` (0 <= lane <
+ * SHMEMX_PROGRESS_LANES: the host streams of arrivals); *ticket identifies
+ * it and its completion record carries the lane.  Requests are independent
+ * (they must not overlap other requests in flight) and may complete in any
+ * order, also within one lane.  AMO fetch results go to the issuer's [dst,
+ * dst + nbytes).  The descriptor's `reserved` field is ignored.  Returns
+ * SHMEMX_ERR_BUSY when the ring is full, SHMEMX_ERR_ARG for a bad lane or
+ * NULL pointers, SHMEMX_ERR_STATE when the kernel is not running. */
+#define SHMEMX_PROGRESS_LANES 8
+int shmemx_progress_submit(int lane, const shmemx_desc_t *desc, uint64_t *ticket);
 /* 1 = complete (out filled), 0 = not yet, <0 = error.  The first poll that
  * sees a request complete consumes its completion record and frees its ring
  * slot; later polls of the same ticket return 1 with only `ticket` set.

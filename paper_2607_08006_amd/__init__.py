@@ -424,6 +424,60 @@ def tune_load(path: str) -> Tune:
     return t
 
 
+TUNE_SRC_DEFAULT, TUNE_SRC_FILE, TUNE_SRC_FILE_REFUSED, TUNE_SRC_SET = 0, 1, 2, 3
+
+
+def tune_set(t: Tune) -> None:
+    """Make `t` the library's active tune table."""
+    _check(lib.shmemx_tune_set(C.byref(t)), "shmemx_tune_set")
+
+
+def tune_get():
+    """(active tune table, where it came from: TUNE_SRC_*)."""
+    t = Tune()
+    rc = lib.shmemx_tune_get(C.byref(t))
+    if rc < 0:
+        raise VshmemError(rc, "shmemx_tune_get")
+    return t, rc
+
+
+# ------------------------------------------------- device descriptor tables
+def launch_batch(d_descs, n: int, results=None, d_tune=None, stream=None) -> None:
+    """Fused launch over a descriptor table in device memory (a uint8 or
+    64-byte-record tensor of at least n descriptors)."""
+    _check(lib.shmemx_launch_batch(_ptr(d_descs), n, _ptr(results), _ptr(d_tune), _stream(stream)),
+           "shmemx_launch_batch")
+
+
+def launch_per_op(d_descs, n: int, results=None, d_tune=None, stream=None) -> None:
+    _check(lib.shmemx_launch_per_op(_ptr(d_descs), n, _ptr(results), _ptr(d_tune), _stream(stream)),
+           "shmemx_launch_per_op")
+
+
+class Graph:
+    """A captured launch over a device descriptor table (form 0 per-op, 1 fused)."""
+
+    def __init__(self, d_descs, n: int, form: int, results=None, d_tune=None):
+        h = C.c_void_p()
+        _check(lib.shmemx_graph_build(_ptr(d_descs), n, _ptr(results), _ptr(d_tune), form, C.byref(h)),
+               "shmemx_graph_build")
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib.shmemx_graph_launch(self._h, _stream(stream)), "shmemx_graph_launch")
+
+    def destroy(self) -> None:
+        if self._h:
+            lib.shmemx_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 # --------------------------------------------------------------- serving
 def progress_start(nwg: int = 0, wg_size: int = 0, ring_slots: int = 4096, verify: bool = False,
                    chunk_bytes: int = 256 << 10, idle_timeout_ms: int = 30000, stream=None) -> None:
@@ -431,9 +485,12 @@ def progress_start(nwg: int = 0, wg_size: int = 0, ring_slots: int = 4096, verif
     _check(lib.shmemx_progress_start(C.byref(cfg), _stream(stream)), "shmemx_progress_start")
 
 
-def progress_submit(desc: Desc) -> int:
+PROGRESS_LANES = 8
+
+
+def progress_submit(desc: Desc, lane: int = 0) -> int:
     t = C.c_uint64()
-    _check(lib.shmemx_progress_submit(C.byref(desc), C.byref(t)), "shmemx_progress_submit")
+    _check(lib.shmemx_progress_submit(lane, C.byref(desc), C.byref(t)), "shmemx_progress_submit")
     return t.value
 
 

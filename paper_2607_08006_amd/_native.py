@@ -45,7 +45,7 @@ class ProgressCfg(C.Structure):
 
 class Completion(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("t_start", C.c_uint64), ("t_end", C.c_uint64), ("hash", C.c_uint64),
-                ("status", C.c_int32), ("reserved", C.c_int32), ("t_queued", C.c_uint64), ("submit_ns", C.c_uint64)]
+                ("status", C.c_int32), ("lane", C.c_int32), ("t_queued", C.c_uint64), ("submit_ns", C.c_uint64)]
 
 
 class DTeam(C.Structure):
@@ -121,8 +121,15 @@ SIGNATURES = {
     "shmemx_autotune": (i32, [u64, u64, u64, u64, i32, i32, P(Tune), vp]),
     "shmemx_tune_save": (i32, [P(Tune), C.c_char_p]),
     "shmemx_tune_load": (i32, [P(Tune), C.c_char_p]),
+    "shmemx_tune_set": (i32, [P(Tune)]),
+    "shmemx_tune_get": (i32, [P(Tune)]),
+    "shmemx_launch_batch": (i32, [vp, sz, vp, vp, vp]),
+    "shmemx_launch_per_op": (i32, [vp, sz, vp, vp, vp]),
+    "shmemx_graph_build": (i32, [vp, sz, vp, vp, i32, P(vp)]),
+    "shmemx_graph_launch": (i32, [vp, vp]),
+    "shmemx_graph_destroy": (None, [vp]),
     "shmemx_progress_start": (i32, [P(ProgressCfg), vp]),
-    "shmemx_progress_submit": (i32, [P(Desc), P(u64)]),
+    "shmemx_progress_submit": (i32, [i32, P(Desc), P(u64)]),
     "shmemx_progress_poll": (i32, [u64, P(Completion)]),
     "shmemx_progress_stop": (i32, [i32]),
     "shmemx_serve_run": (i32, [P(Request), sz, i32, u64, u64, u64, vp, vp, P(Completion), P(ServeStats)]),

@@ -8,6 +8,7 @@
 #include <map>
 #include <vector>
 
+#include "exec.hpp"
 #include "runtime.hpp"
 
 using namespace vshmem;
@@ -32,6 +33,7 @@ struct shmemx_plan {
     int wg = 256;
     int grid = 1;
     uint64_t *stamps = nullptr;             // optional per-op completion stamps (device)
+    uint64_t *d_bar = nullptr;              // the plan's own grid-barrier words (device)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -39,111 +41,9 @@ struct shmemx_plan {
 namespace {
 
 enum { TK_THREAD = 0, TK_WAVE = 1, TK_WG = 2 };
+constexpr size_t kPlanBarBytes = VSHMEM_SYNC_GEN_OFF + VSHMEM_SYNC_SLOT_BYTES;
 
-__device__ __forceinline__ uint64_t *amo_word(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d)
-{
-    return (uint64_t *)(c.base + (uint64_t)d.target_pe * c.stride + d.src);
-}
-
-// Atomics and signal-free single-lane work.
-__device__ __forceinline__ void exec_amo(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d, uint64_t *results)
-{
-    uint64_t *w = amo_word(c, d);
-    uint64_t old = 0;
-    bool fetch = true;
-    switch (d.op) {
-    case SHMEMX_OP_AMO_FETCH_ADD: old = __hip_atomic_fetch_add(w, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
-    case SHMEMX_OP_AMO_FETCH_XOR: old = __hip_atomic_fetch_xor(w, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
-    case SHMEMX_OP_AMO_COMPARE_SWAP: {
-        uint64_t e = d.cond;
-        __hip_atomic_compare_exchange_strong(w, &e, d.value, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        old = e;
-        break;
-    }
-    case SHMEMX_OP_AMO_ADD:
-        __hip_atomic_fetch_add(w, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        fetch = false;
-        break;
-    case SHMEMX_OP_AMO_XOR:
-        __hip_atomic_fetch_xor(w, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        fetch = false;
-        break;
-    case SHMEMX_OP_AMO_SET:
-        __hip_atomic_store(w, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        fetch = false;
-        break;
-    case SHMEMX_OP_AMO_FETCH: old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
-    case SHMEMX_OP_AMO_SWAP: old = __hip_atomic_exchange(w, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
-    default: fetch = false;
-    }
-    if (fetch && results && d.result_idx != SHMEMX_NO_RESULT) results[d.result_idx] = old;
-}
-
-__device__ __forceinline__ bool is_amo(uint8_t op) { return op >= SHMEMX_OP_AMO_FETCH_ADD && op <= SHMEMX_OP_AMO_SWAP; }
-
-// Byte range [lo, hi) of a put/get, copied by nl lanes.
-__device__ __forceinline__ void exec_copy(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d, uint64_t lo, uint64_t hi,
-                                          uint64_t lane, uint64_t nl)
-{
-    const bool get = d.op == SHMEMX_OP_GET;
-    const int spe = get ? d.target_pe : d.issuer_pe;
-    const int dpe = get ? d.issuer_pe : d.target_pe;
-    const uint8_t *S = c.base + (uint64_t)spe * c.stride + d.src + lo;
-    uint8_t *D = c.base + (uint64_t)dpe * c.stride + d.dst + lo;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(D, S, hi - lo, lane, nl);
-}
-
-__device__ __forceinline__ void signal_of(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d)
-{
-    uint64_t *s = (uint64_t *)(c.base + (uint64_t)d.target_pe * c.stride + d.cond);
-    if (d.aux == SHMEM_SIGNAL_ADD)
-        __hip_atomic_fetch_add(s, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        __hip_atomic_store(s, d.value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// One operation by a single lane.
-__device__ __forceinline__ void exec_thread(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d, uint64_t *results)
-{
-    if (is_amo(d.op)) {
-        exec_amo(c, d, results);
-    } else if (d.op == SHMEMX_OP_PUT || d.op == SHMEMX_OP_GET || d.op == SHMEMX_OP_PUT_SIGNAL) {
-        exec_copy(c, d, 0, d.nbytes, 0, 1);
-        if (d.op == SHMEMX_OP_PUT_SIGNAL) {
-            vshmem_detail::release_agent();
-            signal_of(c, d);
-        }
-    }
-}
-
-// One operation by a whole wavefront.
-__device__ __forceinline__ void exec_wave(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d, uint64_t *results)
-{
-    if (is_amo(d.op)) {
-        if (__lane_id() == 0) exec_amo(c, d, results);
-    } else if (d.op == SHMEMX_OP_PUT || d.op == SHMEMX_OP_GET || d.op == SHMEMX_OP_PUT_SIGNAL) {
-        exec_copy(c, d, 0, d.nbytes, __lane_id(), 64);
-        if (d.op == SHMEMX_OP_PUT_SIGNAL) {
-            vshmem_detail::release_agent();
-            if (__lane_id() == 0) signal_of(c, d);
-        }
-    }
-}
-
-// A byte range of one operation by a whole work-group.
-__device__ __forceinline__ void exec_wg(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d, uint64_t lo, uint64_t hi,
-                                        uint64_t *results)
-{
-    if (is_amo(d.op)) {
-        if (threadIdx.x == 0) exec_amo(c, d, results);
-    } else if (d.op == SHMEMX_OP_PUT || d.op == SHMEMX_OP_GET || d.op == SHMEMX_OP_PUT_SIGNAL) {
-        exec_copy(c, d, lo, hi, threadIdx.x, blockDim.x);
-        if (__builtin_amdgcn_readfirstlane(d.op) == SHMEMX_OP_PUT_SIGNAL) {   // uniform: a barrier follows
-            vshmem_detail::release_wg_at_exit();
-            if (threadIdx.x == 0) signal_of(c, d);
-        }
-    }
-}
+using namespace vshmem_exec;
 
 // Completion stamp of operation `idx` (measurement mode): the caller's
 // stores are completed first, then the device wall clock is recorded; when
@@ -187,7 +87,7 @@ __device__ __forceinline__ void run_task(const shmemx_dctx_pub_t &c, const shmem
 
 __global__ void __launch_bounds__(1024) k_plan_fused(shmemx_dctx_pub_t c, const shmemx_desc_t *__restrict__ D,
                                                      const PlanTask *__restrict__ T, const uint32_t *__restrict__ phase,
-                                                     int nphases, uint64_t *results, uint64_t *stamps)
+                                                     int nphases, uint64_t *results, uint64_t *stamps, uint64_t *bar)
 {
     // Loop bounds and task fields go through readfirstlane: the task loop
     // holds work-group barriers, and the compiler must see its exits (and
@@ -209,8 +109,7 @@ __global__ void __launch_bounds__(1024) k_plan_fused(shmemx_dctx_pub_t c, const 
             // acquire in the barrier cover its work-group).
             vshmem_detail::wait_vm_complete();
             __syncthreads();
-            if (threadIdx.x == 0)
-                vshmem_detail::counter_barrier(c, vshmem_detail::sync_slot(c, 0, kTeamSlotPlan), gridDim.x);
+            if (threadIdx.x == 0) vshmem_detail::counter_barrier(c, bar, gridDim.x);
             __syncthreads();
         }
     }
@@ -236,15 +135,6 @@ __global__ void __launch_bounds__(1024) k_plan_one(shmemx_dctx_pub_t c, shmemx_d
 
 __global__ void k_stamp(uint64_t *dst) { if (threadIdx.x == 0) *dst = wall_clock64(); }
 
-bool is_sync(uint8_t op) { return op == SHMEMX_OP_FENCE || op == SHMEMX_OP_QUIET || op == SHMEMX_OP_BARRIER_ALL; }
-bool is_amo_h(uint8_t op) { return op >= SHMEMX_OP_AMO_FETCH_ADD && op <= SHMEMX_OP_AMO_SWAP; }
-
-int size_class(uint64_t n)
-{
-    int c = 0;
-    while (c + 1 < SHMEMX_TUNE_CLASSES && (2ull << c) <= n) ++c;
-    return c;
-}
 
 int validate(const shmemx_desc_t &d)
 {
@@ -252,29 +142,13 @@ int validate(const shmemx_desc_t &d)
     if (d.op > SHMEMX_OP_BARRIER_ALL) return SHMEMX_ERR_ARG;
     if (d.op == SHMEMX_OP_WAIT_UNTIL) return SHMEMX_ERR_UNSUPPORTED;
     if (d.issuer_pe < 0 || d.issuer_pe >= s.npes) return SHMEMX_ERR_ARG;
-    if (d.op == SHMEMX_OP_NOP || is_sync(d.op)) return SHMEMX_OK;
+    if (d.op == SHMEMX_OP_NOP || is_sync_op(d.op)) return SHMEMX_OK;
     if (d.target_pe < 0 || d.target_pe >= s.npes) return SHMEMX_ERR_ARG;
     if (d.scope > SHMEMX_SCOPE_GRID && d.scope != SHMEMX_SCOPE_AUTO) return SHMEMX_ERR_ARG;
-    if (is_amo_h(d.op)) return (d.src & 7) == 0 && in_user_heap(d.src, 8) ? SHMEMX_OK : SHMEMX_ERR_ARG;
+    if (is_amo_op(d.op)) return (d.src & 7) == 0 && in_user_heap(d.src, 8) ? SHMEMX_OK : SHMEMX_ERR_ARG;
     if (!in_user_heap(d.src, d.nbytes) || !in_user_heap(d.dst, d.nbytes)) return SHMEMX_ERR_ARG;
     if (d.op == SHMEMX_OP_PUT_SIGNAL && ((d.cond & 7) || !in_user_heap(d.cond, 8))) return SHMEMX_ERR_ARG;
     return SHMEMX_OK;
-}
-
-int resolve_scope(const shmemx_desc_t &d, const shmemx_tune_t &tune)
-{
-    if (is_amo_h(d.op)) return d.scope == SHMEMX_SCOPE_AUTO ? SHMEMX_SCOPE_THREAD : d.scope;
-    if (d.scope != SHMEMX_SCOPE_AUTO) return d.scope;
-    return tune.scope[size_class(d.nbytes)];
-}
-
-uint64_t resolve_chunk(const shmemx_desc_t &d, int scope, const shmemx_tune_t &tune)
-{
-    if (d.op == SHMEMX_OP_PUT_SIGNAL || is_amo_h(d.op)) return d.nbytes ? d.nbytes : 1;   // never split
-    uint64_t ch = tune.chunk[size_class(d.nbytes)];
-    if (scope == SHMEMX_SCOPE_GRID && ch == 0) ch = 256ull << 10;
-    if (ch == 0 || ch >= d.nbytes) return d.nbytes ? d.nbytes : 1;
-    return (ch + 15) & ~15ull;
 }
 
 template <typename T>
@@ -430,6 +304,11 @@ int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t
     int rc = upload(&plan->d_descs, dd);
     if (!rc) rc = upload(&plan->d_tasks, tasks);
     if (!rc) rc = upload(&plan->d_phase, phase);
+    // Barrier words of the plan's own: launches of different plans never
+    // share an arrival count (count at 0, generation VSHMEM_SYNC_GEN_OFF on).
+    if (!rc && VSHMEM_HIP_FAILED(hipMalloc((void **)&plan->d_bar, kPlanBarBytes))) rc = SHMEMX_ERR_HIP;
+    if (!rc && VSHMEM_HIP_FAILED(hipMemset(plan->d_bar, 0, kPlanBarBytes))) rc = SHMEMX_ERR_HIP;
+    if (!rc) register_bar_block(plan->d_bar, kPlanBarBytes);
     if (rc) {
         shmemx_plan_destroy(plan);
         return rc;
@@ -444,7 +323,7 @@ int shmemx_plan_launch_fused(shmemx_plan_t *plan, uint64_t *results, void *strea
     if (!plan) return SHMEMX_ERR_ARG;
     if (plan->nphases == 0) return SHMEMX_OK;
     hipLaunchKernelGGL(k_plan_fused, dim3(plan->grid), dim3(plan->wg), 0, (hipStream_t)stream, pub(), plan->d_descs,
-                       plan->d_tasks, plan->d_phase, (int)plan->nphases, results, plan->stamps);
+                       plan->d_tasks, plan->d_phase, (int)plan->nphases, results, plan->stamps, plan->d_bar);
     VSHMEM_HIP(hipGetLastError());
     return SHMEMX_OK;
 }
@@ -456,7 +335,7 @@ int shmemx_plan_launch_per_op(shmemx_plan_t *plan, uint64_t *results, void *stre
     const shmemx_dctx_pub_t c = pub();
     for (size_t i = 0; i < plan->host.size(); ++i) {
         const shmemx_desc_t &d = plan->host[i];
-        if (d.op == SHMEMX_OP_NOP || is_sync(d.op)) continue;   // stream order provides the ordering
+        if (d.op == SHMEMX_OP_NOP || is_sync_op(d.op)) continue;   // stream order provides the ordering
         const int sc = plan->host_scope[i];
         unsigned grid = 1, block = 64;
         uint64_t ch = plan->host_chunk[i];
@@ -538,6 +417,10 @@ void shmemx_plan_destroy(shmemx_plan_t *plan)
     if (plan->d_descs) (void)hipFree(plan->d_descs);
     if (plan->d_tasks) (void)hipFree(plan->d_tasks);
     if (plan->d_phase) (void)hipFree(plan->d_phase);
+    if (plan->d_bar) {
+        unregister_bar_block(plan->d_bar);
+        (void)hipFree(plan->d_bar);
+    }
     delete plan;
 }
 

@@ -1,0 +1,703 @@
+// Batches over a descriptor table that lives in DEVICE memory.  The table is
+// read on the device at every launch, so a kernel (or a copy) may rewrite it
+// between launches; the host never sees its contents.
+//
+// The fused form runs two kernels on the caller's stream.  The index kernel
+// (one work-group) derives what the host plan builder derives: each
+// operation's phase from its issuer's ordering points (barriers seen, fences
+// and quiets since the last barrier), its scope and chunking from the tune
+// table, and a counting sort of the operations by (phase, kind).  The
+// executor then runs the phases in order; inside a phase its work-groups pop
+// tasks from an atomic cursor (work-group byte ranges first, then wavefront
+// packs, then single-lane packs) and a grid barrier separates the phases.
+// Long-lived kernels that consume descriptor tables are the paper's Section 3
+// case for device-side batching; the stream-ordered forms of Section 4.3 are
+// what the caller's stream gives.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "exec.hpp"
+#include "runtime.hpp"
+
+using namespace vshmem;
+using namespace vshmem_exec;
+
+namespace {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kIndexThreads = 1024;
+constexpr int kIndexMaxPes = 4096;          // per-issuer ordering state held in LDS
+constexpr uint64_t kMaxTable = 1ull << 26;  // descriptors per table
+
+// Control words of one workspace (written by the index kernel).
+struct Ctl {
+    uint32_t nphases;
+    uint32_t active;   // executor work-groups that take part (the rest leave at once)
+    uint32_t last;     // 1 + the last phase that has tasks (0: nothing to run)
+    uint32_t nvalid;   // operations that execute
+    uint32_t pad[12];
+};
+
+// Sections of a workspace for tables of up to `cap` descriptors.  The
+// barrier words come first: count at 0 and generation VSHMEM_SYNC_GEN_OFF
+// further, the layout counter_barrier expects.
+struct Ws {
+    uint64_t *bar;
+    Ctl *ctl;
+    uint32_t *eb;      // per op: barrier epoch (kNone: not executed)
+    uint32_t *ef;      // per op: fences since the epoch began
+    uint32_t *key;     // per op: bucket = 3 * phase + kind (kNone: not executed)
+    uint32_t *nch;     // per op: work-group tasks (0 for packed kinds)
+    uint32_t *sorted;  // op indices by bucket
+    uint32_t *maxf;    // per epoch: largest fence count of an op in it
+    uint32_t *base;    // per epoch: its first phase
+    uint32_t *cnt;     // per bucket: count, then scatter cursor
+    uint32_t *off;     // per bucket: first sorted position (one extra entry: the end)
+    uint32_t *cursor;  // per phase: next task
+    uint64_t *cs;      // per sorted position: first work-group task (one extra entry)
+};
+
+constexpr uint64_t kHeaderBytes = VSHMEM_SYNC_GEN_OFF + 256;
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+uint64_t phase_cap(uint64_t cap) { return 2 * cap + 1; }
+uint64_t bucket_cap(uint64_t cap) { return 3 * phase_cap(cap) + 1; }
+
+// Byte size of each section, in carve order.
+void sections(uint64_t cap, uint64_t out[12])
+{
+    const uint64_t c4 = cap * 4;
+    out[0] = c4;                              // eb
+    out[1] = c4;                              // ef
+    out[2] = c4;                              // key
+    out[3] = c4;                              // nch
+    out[4] = c4;                              // sorted
+    out[5] = (cap + 1) * 4;                   // maxf
+    out[6] = (cap + 1) * 4;                   // base
+    out[7] = bucket_cap(cap) * 4;             // cnt
+    out[8] = bucket_cap(cap) * 4;             // off
+    out[9] = phase_cap(cap) * 4;              // cursor
+    out[10] = (cap + 1) * 8;                  // cs
+    out[11] = 0;
+}
+
+uint64_t ws_bytes(uint64_t cap)
+{
+    uint64_t s[12], total = kHeaderBytes;
+    sections(cap, s);
+    for (int i = 0; i < 11; ++i) total += align256(s[i]);
+    return total;
+}
+
+// Largest table a workspace of `bytes` holds.
+uint64_t ws_capacity(uint64_t bytes)
+{
+    uint64_t lo = 0, hi = kMaxTable;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) / 2;
+        if (ws_bytes(mid) <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+Ws ws_carve(uint8_t *w, uint64_t cap)
+{
+    Ws r;
+    r.bar = (uint64_t *)w;
+    r.ctl = (Ctl *)(w + 128);
+    uint64_t s[12];
+    sections(cap, s);
+    uint8_t *p = w + kHeaderBytes;
+    void **dst[11] = {(void **)&r.eb,   (void **)&r.ef,  (void **)&r.key, (void **)&r.nch,
+                      (void **)&r.sorted, (void **)&r.maxf, (void **)&r.base, (void **)&r.cnt,
+                      (void **)&r.off,  (void **)&r.cursor, (void **)&r.cs};
+    for (int i = 0; i < 11; ++i) {
+        *dst[i] = p;
+        p += align256(s[i]);
+    }
+    return r;
+}
+
+struct BatchArgs {
+    shmemx_dctx_pub_t c;
+    const shmemx_desc_t *D;
+    uint32_t n;
+    uint32_t exec_wg;    // executor work-group size
+    uint32_t exec_grid;  // executor grid
+    uint32_t pad;
+    const shmemx_tune_t *tune;
+    uint64_t *results;
+    Ws w;
+};
+
+// ---------------------------------------------------------------- device
+__device__ __forceinline__ bool dev_in_heap(const shmemx_dctx_pub_t &c, uint64_t off, uint64_t n)
+{
+    return off <= c.user_bytes && n <= c.user_bytes - off;
+}
+
+// A data operation (put, get, signal-put, atomic) the batch can execute:
+// PEs, ranges inside the user heap, aligned words, a known scope, and a
+// result index inside the n-entry result array.
+__device__ __forceinline__ bool dev_valid(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d, uint32_t n,
+                                          const uint64_t *results)
+{
+    if (d.target_pe < 0 || d.target_pe >= c.npes) return false;
+    if (d.scope > SHMEMX_SCOPE_GRID && d.scope != SHMEMX_SCOPE_AUTO) return false;
+    if (is_amo_op(d.op)) {
+        const bool fetching = d.op != SHMEMX_OP_AMO_ADD && d.op != SHMEMX_OP_AMO_XOR && d.op != SHMEMX_OP_AMO_SET;
+        if (fetching && results && d.result_idx != SHMEMX_NO_RESULT && d.result_idx >= n) return false;
+        return (d.src & 7) == 0 && dev_in_heap(c, d.src, 8);
+    }
+    if (!dev_in_heap(c, d.src, d.nbytes) || !dev_in_heap(c, d.dst, d.nbytes)) return false;
+    if (d.op == SHMEMX_OP_PUT_SIGNAL && ((d.cond & 7) || !dev_in_heap(c, d.cond, 8))) return false;
+    return true;
+}
+
+__device__ __forceinline__ bool is_data_op(uint8_t op)
+{
+    return op == SHMEMX_OP_PUT || op == SHMEMX_OP_GET || op == SHMEMX_OP_PUT_SIGNAL || is_amo_op(op);
+}
+
+// Exclusive prefix sum over the work-group (blockDim.x a multiple of 64, at
+// most 1024); *total receives the sum.  Every thread calls it.
+template <typename T>
+__device__ __forceinline__ T block_scan(T x, T *total)
+{
+    __shared__ T wsum[16];
+    const uint32_t lane = __lane_id(), w = threadIdx.x / 64, nw = blockDim.x / 64;
+    T incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T y = __shfl_up(incl, off, 64);
+        if ((int)lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    T before = 0, all = 0;
+    for (uint32_t k = 0; k < nw; ++k) {
+        const T v = wsum[k];
+        if (k < w) before += v;
+        all += v;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - x;
+}
+
+__device__ __forceinline__ shmemx_desc_t load_desc(const shmemx_desc_t *p)
+{
+    shmemx_desc_t d;
+    const vshmem_detail::v4u *q = (const vshmem_detail::v4u *)p;
+    vshmem_detail::v4u w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = q[i];
+    memcpy(&d, w, sizeof(d));
+    return d;
+}
+
+__device__ __forceinline__ uint32_t ld_l2(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Index kernel: one work-group of kIndexThreads threads.
+__global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
+{
+    __shared__ uint32_t nbar[kIndexMaxPes], nfen[kIndexMaxPes];
+    __shared__ uint32_t lpos[kIndexThreads], liss[kIndexThreads];
+    __shared__ uint8_t ltyp[kIndexThreads];
+    __shared__ uint32_t s_flag, s_max, s_last, s_bad;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x, n = a.n;
+    const int npes = a.c.npes;
+    const Ws &w = a.w;
+    const shmemx_tune_t &tune = *a.tune;
+
+    for (int p = tid; p < npes; p += nt) nbar[p] = nfen[p] = 0;
+    for (uint32_t i = tid; i <= n; i += nt) w.maxf[i] = 0;
+    if (tid == 0) {
+        s_flag = 0;
+        s_max = 0;
+        s_last = 0;
+        s_bad = 0;
+    }
+    __syncthreads();
+
+    // Pass 1: each operation's (barrier epoch, fences since) from its issuer's
+    // ordering points, one chunk of the table at a time.  The chunk's ordering
+    // points are listed in table order; an operation starts from its issuer's
+    // state at the chunk's start and applies the listed points before it.
+    for (uint32_t c0 = 0; c0 < n; c0 += nt) {
+        const uint32_t i = c0 + tid;
+        uint32_t op = SHMEMX_OP_NOP;
+        int iss = -1;
+        if (i < n) {
+            const uint32_t w0 = ((const uint32_t *)(a.D + i))[0];
+            op = w0 & 0xFFu;
+            iss = ((const int32_t *)(a.D + i))[1];
+        }
+        const bool iss_ok = iss >= 0 && iss < npes;
+        const bool sync = i < n && iss_ok && is_sync_op((uint8_t)op);
+        const bool data = i < n && iss_ok && is_data_op((uint8_t)op);
+        if (i < n && op != SHMEMX_OP_NOP && !sync && !data) s_bad = 1;   // bad code, WAIT_UNTIL, or bad issuer
+        uint32_t nsync = 0;
+        const uint32_t pos = block_scan<uint32_t>(sync ? 1u : 0u, &nsync);
+        if (sync) {
+            lpos[pos] = tid;
+            liss[pos] = (uint32_t)iss;
+            ltyp[pos] = op == SHMEMX_OP_BARRIER_ALL ? 1 : 0;
+        }
+        __syncthreads();
+        if (data) {
+            uint32_t b = nbar[iss], f = nfen[iss];
+            for (uint32_t j = 0; j < nsync && lpos[j] < tid; ++j) {
+                if (liss[j] == (uint32_t)iss) {
+                    if (ltyp[j]) {
+                        ++b;
+                        f = 0;
+                    } else {
+                        ++f;
+                    }
+                }
+            }
+            w.eb[i] = b;
+            w.ef[i] = f;
+            atomicMax(&w.maxf[b], f);
+        } else if (i < n) {
+            w.eb[i] = kNone;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (uint32_t j = 0; j < nsync; ++j) {
+                const uint32_t p = liss[j];
+                if (ltyp[j]) {
+                    ++nbar[p];
+                    nfen[p] = 0;
+                } else {
+                    ++nfen[p];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // Every PE's program holds the same number of barriers.
+    for (int p = tid; p < npes; p += nt)
+        if (nbar[p] != nbar[0]) s_bad = 2;
+    __syncthreads();
+    if (s_bad == 2) {
+        if (tid == 0) {
+            vshmem_detail::latch_error(a.c, SHMEMX_DEVERR_BAD_DESC);
+            w.ctl->nphases = 0;
+            w.ctl->active = 0;
+            w.ctl->last = 0;
+            w.ctl->nvalid = 0;
+        }
+        return;
+    }
+    const uint32_t nepochs = nbar[0] + 1;
+
+    // Pass 2: first phase of each epoch (phases of epoch b: maxf[b] + 1).
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nepochs; b0 += nt) {
+        const uint32_t b = b0 + tid;
+        // maxf was built with atomics (performed in L2): read it the same way.
+        const uint32_t v = b < nepochs ? ld_l2(w.maxf + b) + 1 : 0;
+        uint32_t tot = 0;
+        const uint32_t ex = block_scan<uint32_t>(v, &tot);
+        if (b < nepochs) w.base[b] = carry + ex;
+        carry += tot;
+    }
+    const uint32_t nphases = carry;
+    const uint32_t nbk = 3 * nphases;
+    for (uint32_t k = tid; k <= nbk; k += nt) w.cnt[k] = 0;
+    __syncthreads();
+
+    // Pass 3: validate, resolve scope and chunks, count per bucket.  Kinds in
+    // bucket order: 0 work-group byte ranges, 1 wavefront, 2 single lane.
+    for (uint32_t i = tid; i < n; i += nt) {
+        uint32_t key = kNone, nch = 0;
+        const uint32_t b = w.eb[i];
+        if (b != kNone) {
+            const shmemx_desc_t d = load_desc(a.D + i);
+            if (dev_valid(a.c, d, n, a.results)) {
+                const int sc = resolve_scope(d, tune);
+                const uint32_t kind = sc == SHMEMX_SCOPE_THREAD ? 2u : (sc == SHMEMX_SCOPE_WAVE ? 1u : 0u);
+                if (kind == 0) {
+                    const uint64_t ch = resolve_chunk(d, sc, tune);
+                    const uint64_t k = d.nbytes ? (d.nbytes + ch - 1) / ch : 1;
+                    nch = k < 0xFFFFFFFFull ? (uint32_t)k : 0xFFFFFFFFu;
+                }
+                key = 3 * (w.base[b] + w.ef[i]) + kind;
+                atomicAdd(&w.cnt[key], 1u);
+            } else {
+                s_bad = 1;
+            }
+        }
+        w.key[i] = key;
+        w.nch[i] = nch;
+    }
+    __syncthreads();
+    if (tid == 0 && s_bad) vshmem_detail::latch_error(a.c, SHMEMX_DEVERR_BAD_DESC);
+
+    // Pass 4: bucket offsets; the counts become scatter cursors.
+    carry = 0;
+    for (uint32_t k0 = 0; k0 < nbk; k0 += nt) {
+        const uint32_t k = k0 + tid;
+        const uint32_t v = k < nbk ? ld_l2(w.cnt + k) : 0;
+        uint32_t tot = 0;
+        const uint32_t ex = block_scan<uint32_t>(v, &tot);
+        if (k < nbk) {
+            w.off[k] = carry + ex;
+            w.cnt[k] = carry + ex;
+        }
+        carry += tot;
+    }
+    const uint32_t nvalid = carry;
+    if (tid == 0) w.off[nbk] = nvalid;
+    __syncthreads();
+
+    // Pass 5: scatter.  The order inside a bucket is free: its operations run
+    // concurrently anyway.
+    for (uint32_t i = tid; i < n; i += nt) {
+        const uint32_t key = w.key[i];
+        if (key != kNone) {
+            const uint32_t pos = atomicAdd(&w.cnt[key], 1u);
+            w.sorted[pos] = i;
+            w.cs[pos] = w.nch[i];
+        }
+    }
+    __syncthreads();
+
+    // Pass 6: work-group task offsets over the sorted order.
+    uint64_t carry64 = 0;
+    for (uint32_t s0 = 0; s0 < nvalid; s0 += nt) {
+        const uint32_t s = s0 + tid;
+        const uint64_t v = s < nvalid ? w.cs[s] : 0;
+        uint64_t tot = 0;
+        const uint64_t ex = block_scan<uint64_t>(v, &tot);
+        __syncthreads();   // every read of this chunk precedes its writes
+        if (s < nvalid) w.cs[s] = carry64 + ex;
+        carry64 += tot;
+    }
+    if (tid == 0) w.cs[nvalid] = carry64;
+    __syncthreads();
+
+    // Pass 7: tasks per phase, the executor's active work-groups and the last
+    // phase with tasks.
+    const uint32_t bd = a.exec_wg, waves = bd / 64;
+    for (uint32_t ph = tid; ph < nphases; ph += nt) {
+        w.cursor[ph] = 0;
+        const uint32_t o0 = w.off[3 * ph], o1 = w.off[3 * ph + 1], o2 = w.off[3 * ph + 2], o3 = w.off[3 * ph + 3];
+        const uint64_t nt_ph = (w.cs[o1] - w.cs[o0]) + (o2 - o1 + waves - 1) / waves + (o3 - o2 + bd - 1) / bd;
+        if (nt_ph) {
+            atomicMax(&s_max, nt_ph < 0xFFFFFFFFull ? (uint32_t)nt_ph : 0xFFFFFFFFu);
+            atomicMax(&s_last, ph + 1);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        w.ctl->nphases = nphases;
+        w.ctl->active = s_max == 0 ? 0 : (s_max < a.exec_grid ? s_max : a.exec_grid);
+        w.ctl->last = s_last;
+        w.ctl->nvalid = nvalid;
+        w.bar[0] = 0;
+        *(uint64_t *)((uint8_t *)w.bar + VSHMEM_SYNC_GEN_OFF) = 0;
+    }
+}
+
+__device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t rfl64(uint64_t x) { return vshmem_detail::first_lane64(x); }
+
+// Last sorted position s in [lo, hi) with cs[s] <= target (cs strictly
+// increasing over work-group operations): a 64-way search by one wavefront.
+__device__ __forceinline__ uint32_t wave_search(const uint64_t *cs, uint32_t lo, uint32_t hi, uint64_t target)
+{
+    const uint32_t lane = __lane_id();
+    while (hi - lo > 1) {
+        const uint32_t span = hi - lo;
+        const uint32_t p = lo + (uint32_t)(((uint64_t)span * lane) / 64);
+        const bool le = cs[p] <= target;
+        const uint64_t m = __ballot(le);
+        const uint32_t k = 63 - (uint32_t)__builtin_clzll(m);   // lane 0 always holds
+        const uint32_t nlo = lo + (uint32_t)(((uint64_t)span * k) / 64);
+        const uint32_t nhi = k == 63 ? hi : lo + (uint32_t)(((uint64_t)span * (k + 1)) / 64);
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
+// Executor: up to exec_grid work-groups; those past ctl->active leave.
+__global__ void __launch_bounds__(1024) k_batch_exec(BatchArgs a)
+{
+    __shared__ uint32_t s_t[4];
+    const Ws &w = a.w;
+    const uint32_t active = rfl(w.ctl->active), last = rfl(w.ctl->last);
+    if (blockIdx.x >= active) return;
+    const shmemx_tune_t &tune = *a.tune;
+    const uint32_t bd = blockDim.x, waves = bd / 64;
+    for (uint32_t ph = 0; ph < last; ++ph) {
+        const uint32_t o0 = rfl(w.off[3 * ph]), o1 = rfl(w.off[3 * ph + 1]);
+        const uint32_t o2 = rfl(w.off[3 * ph + 2]), o3 = rfl(w.off[3 * ph + 3]);
+        const uint64_t c0 = rfl64(w.cs[o0]);
+        const uint64_t nwg = rfl64(w.cs[o1]) - c0;
+        const uint64_t nwv = (o2 - o1 + waves - 1) / waves;
+        const uint64_t ntask = nwg + nwv + (o3 - o2 + bd - 1) / bd;
+        if (ntask == 0) continue;
+        for (;;) {
+            if (threadIdx.x < 64) {
+                uint64_t t = 0;
+                if (threadIdx.x == 0) t = __hip_atomic_fetch_add(w.cursor + ph, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                t = __shfl(t, 0, 64);
+                uint32_t s = 0;
+                if (t < nwg) s = wave_search(w.cs, o0, o1, c0 + t);
+                if (threadIdx.x == 0) {
+                    s_t[0] = (uint32_t)t;
+                    s_t[1] = s;
+                }
+            }
+            __syncthreads();
+            const uint32_t t = rfl(s_t[0]), s = rfl(s_t[1]);
+            __syncthreads();   // s_t is rewritten by the next pop
+            if (t >= ntask) break;
+            if (t < nwg) {
+                const shmemx_desc_t d = load_desc(a.D + rfl(w.sorted[s]));
+                const int sc = resolve_scope(d, tune);
+                const uint64_t ch = resolve_chunk(d, sc, tune);
+                const uint64_t k = c0 + t - rfl64(w.cs[s]);
+                const uint64_t lo = k * ch;
+                const uint64_t hi = lo + ch < d.nbytes ? lo + ch : d.nbytes;
+                exec_wg(a.c, d, lo, hi, a.results);
+            } else if (t < nwg + nwv) {
+                const uint64_t first = o1 + (t - nwg) * waves + threadIdx.x / 64;
+                if (first < o2) exec_wave(a.c, load_desc(a.D + w.sorted[first]), a.results);
+            } else {
+                const uint64_t idx = o2 + (t - nwg - nwv) * bd + threadIdx.x;
+                if (idx < o3) exec_thread(a.c, load_desc(a.D + w.sorted[idx]), a.results);
+            }
+        }
+        if (ph + 1 < last) {
+            vshmem_detail::wait_vm_complete();
+            __syncthreads();
+            if (threadIdx.x == 0) vshmem_detail::counter_barrier(a.c, w.bar, active);
+            __syncthreads();
+        }
+    }
+    vshmem_detail::release_wg_at_exit();   // quiet
+}
+
+// Per-operation form: launch i executes descriptor i of the table.
+__global__ void __launch_bounds__(1024) k_batch_one(shmemx_dctx_pub_t c, const shmemx_desc_t *D, uint32_t i,
+                                                    uint32_t n, const shmemx_tune_t *tune, uint64_t *results)
+{
+    shmemx_desc_t d = load_desc(D + i);
+    uint32_t *dw = (uint32_t *)&d;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(d) / 4); ++k) dw[k] = rfl(dw[k]);
+    if (d.op == SHMEMX_OP_NOP || is_sync_op(d.op)) return;   // stream order is the ordering
+    if (!is_data_op(d.op) || d.issuer_pe < 0 || d.issuer_pe >= c.npes || !dev_valid(c, d, n, results)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) vshmem_detail::latch_error(c, SHMEMX_DEVERR_BAD_DESC);
+        return;
+    }
+    const int sc = resolve_scope(d, *tune);
+    if (sc == SHMEMX_SCOPE_THREAD) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) exec_thread(c, d, results);
+    } else if (sc == SHMEMX_SCOPE_WAVE) {
+        if (blockIdx.x == 0 && threadIdx.x < 64) exec_wave(c, d, results);
+    } else {
+        const uint64_t ch = resolve_chunk(d, sc, *tune);
+        const uint64_t nch = d.nbytes ? (d.nbytes + ch - 1) / ch : 1;
+        for (uint64_t k = blockIdx.x; k < nch; k += gridDim.x) {
+            const uint64_t lo = k * ch;
+            exec_wg(c, d, lo, lo + ch < d.nbytes ? lo + ch : d.nbytes, results);
+        }
+    }
+    vshmem_detail::release_wg_at_exit();   // quiet
+}
+
+// ------------------------------------------------------------------ host
+struct StreamWs {
+    uint8_t *buf = nullptr;
+    uint64_t cap = 0;
+};
+std::mutex g_ws_mu;
+std::map<hipStream_t, StreamWs> g_ws;      // fused-form workspaces, one per stream
+
+// Launch shape of the executor and the per-op kernel from the library's tune.
+int exec_shape(uint32_t *wg, uint32_t *grid)
+{
+    const shmemx_tune_t &t = st().tune;
+    int64_t cap = 0;
+    if (int rc = coresident_capacity(k_batch_exec, t.wg_size, &cap)) return rc;
+    if (cap <= 0) {
+        int per_cu = 0;
+        (void)blocks_per_cu(k_batch_exec, t.wg_size, &per_cu);
+        if (per_cu > 0) {
+            set_error_detail(SHMEMX_ERR_BUSY, "k_batch_exec: no CU is free next to the progress kernel");
+            return SHMEMX_ERR_BUSY;
+        }
+        set_error_detail(SHMEMX_ERR_UNSUPPORTED, "k_batch_exec: no work-group of %d threads can be resident",
+                         t.wg_size);
+        return SHMEMX_ERR_UNSUPPORTED;
+    }
+    if (t.grid_wgs > 0 && t.grid_wgs < cap) cap = t.grid_wgs;
+    *wg = (uint32_t)t.wg_size;
+    *grid = (uint32_t)cap;
+    return SHMEMX_OK;
+}
+
+int check_table(const shmemx_desc_t *d_descs, size_t n)
+{
+    if (int rc = check_ready()) return rc;
+    if ((!d_descs && n) || n > kMaxTable) return SHMEMX_ERR_ARG;
+    if (st().npes > kIndexMaxPes) {
+        set_error_detail(SHMEMX_ERR_UNSUPPORTED, "device descriptor tables support up to %d PEs", kIndexMaxPes);
+        return SHMEMX_ERR_UNSUPPORTED;
+    }
+    return SHMEMX_OK;
+}
+
+// Index + executor on `stream` over a workspace of capacity >= n.
+int launch_fused(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
+                 uint8_t *ws, uint64_t cap, hipStream_t stream)
+{
+    uint32_t wg = 0, grid = 0;
+    if (int rc = exec_shape(&wg, &grid)) return rc;
+    BatchArgs a{};
+    a.c = pub();
+    a.D = d_descs;
+    a.n = (uint32_t)n;
+    a.exec_wg = wg;
+    a.exec_grid = grid;
+    a.tune = d_tune ? d_tune : st().d_tune;
+    a.results = d_results;
+    a.w = ws_carve(ws, cap);
+    hipLaunchKernelGGL(k_batch_index, dim3(1), dim3(kIndexThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_batch_exec, dim3(grid), dim3(wg), 0, stream, a);
+    VSHMEM_HIP(hipGetLastError());
+    return SHMEMX_OK;
+}
+
+int launch_ops(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
+               hipStream_t stream)
+{
+    const shmemx_tune_t &t = st().tune;
+    const shmemx_tune_t *tp = d_tune ? d_tune : st().d_tune;
+    const unsigned grid = t.grid_wgs > 0 ? (unsigned)t.grid_wgs : (unsigned)st().num_cus;
+    const shmemx_dctx_pub_t c = pub();
+    for (size_t i = 0; i < n; ++i)
+        hipLaunchKernelGGL(k_batch_one, dim3(grid), dim3(t.wg_size), 0, stream, c, d_descs, (uint32_t)i, (uint32_t)n,
+                           tp, d_results);
+    VSHMEM_HIP(hipGetLastError());
+    return SHMEMX_OK;
+}
+
+}  // namespace
+
+struct shmemx_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint8_t *ws = nullptr;
+};
+
+namespace vshmem {
+void batch_release_workspaces()
+{
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto &kv : g_ws)
+        if (kv.second.buf) (void)hipFree(kv.second.buf);
+    g_ws.clear();
+}
+}  // namespace vshmem
+
+extern "C" {
+
+int shmemx_launch_batch(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
+                        void *stream)
+{
+    if (int rc = check_table(d_descs, n)) return rc;
+    if (n == 0) return SHMEMX_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    uint8_t *buf = nullptr;
+    uint64_t cap = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        StreamWs &sw = g_ws[hs];
+        if (sw.cap < n) {
+            // The stream's earlier launches may still read the old workspace.
+            VSHMEM_HIP(hipStreamSynchronize(hs));
+            if (sw.buf) (void)hipFree(sw.buf);
+            sw.buf = nullptr;
+            sw.cap = 0;
+            const uint64_t want = std::max<uint64_t>(n, 4096);
+            VSHMEM_HIP(hipMalloc((void **)&sw.buf, ws_bytes(want)));
+            sw.cap = want;
+        }
+        buf = sw.buf;
+        cap = sw.cap;
+    }
+    return launch_fused(d_descs, n, d_results, d_tune, buf, cap, hs);
+}
+
+int shmemx_launch_per_op(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
+                         void *stream)
+{
+    if (int rc = check_table(d_descs, n)) return rc;
+    return launch_ops(d_descs, n, d_results, d_tune, (hipStream_t)stream);
+}
+
+int shmemx_graph_build(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
+                       int form, shmemx_graph_t **out)
+{
+    if (int rc = check_table(d_descs, n)) return rc;
+    if (!out || (form != 0 && form != 1)) return SHMEMX_ERR_ARG;
+    *out = nullptr;
+    auto *g = new shmemx_graph();
+    int rc = SHMEMX_OK;
+    const uint64_t cap = std::max<uint64_t>(n, 1);
+    if (form == 1 && VSHMEM_HIP_FAILED(hipMalloc((void **)&g->ws, ws_bytes(cap)))) rc = SHMEMX_ERR_HIP;
+    hipStream_t cs = nullptr;
+    if (!rc && VSHMEM_HIP_FAILED(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking))) rc = SHMEMX_ERR_HIP;
+    if (!rc && VSHMEM_HIP_FAILED(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal))) rc = SHMEMX_ERR_HIP;
+    if (!rc) {
+        int lrc = SHMEMX_OK;
+        if (n) lrc = form == 1 ? launch_fused(d_descs, n, d_results, d_tune, g->ws, cap, cs)
+                               : launch_ops(d_descs, n, d_results, d_tune, cs);
+        hipGraph_t graph = nullptr;
+        if (VSHMEM_HIP_FAILED(hipStreamEndCapture(cs, &graph)) && !lrc) lrc = SHMEMX_ERR_HIP;
+        g->graph = graph;
+        rc = lrc;
+        if (!rc && VSHMEM_HIP_FAILED(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0))) rc = SHMEMX_ERR_HIP;
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc) {
+        shmemx_graph_destroy(g);
+        set_last_error(rc);
+        return rc;
+    }
+    *out = g;
+    return SHMEMX_OK;
+}
+
+int shmemx_graph_launch(shmemx_graph_t *g, void *stream)
+{
+    if (int rc = check_ready()) return rc;
+    if (!g || !g->exec) return SHMEMX_ERR_ARG;
+    VSHMEM_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return SHMEMX_OK;
+}
+
+void shmemx_graph_destroy(shmemx_graph_t *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ws) (void)hipFree(g->ws);
+    delete g;
+}
+
+}  // extern "C"

@@ -171,6 +171,7 @@ __device__ void post_completion(const ProgArgs &a, uint32_t slot, Parent &P, int
     cp->t_queued = ldr_dev(&P.t_queued);
     cp->submit_ns = 0;
     cp->status = status;
+    cp->lane = (int32_t)P.d.reserved;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: the record before the done word
     st_sys(a.ring_done + slot, cp->ticket + 1);
 }
@@ -713,11 +714,11 @@ int shmemx_launch_request(const shmemx_desc_t *desc, uint64_t chunk_bytes, int w
     return SHMEMX_OK;
 }
 
-int shmemx_progress_submit(const shmemx_desc_t *desc, uint64_t *ticket)
+int shmemx_progress_submit(int lane, const shmemx_desc_t *desc, uint64_t *ticket)
 {
     Progress &p = g_prog;
     if (!p.running) return SHMEMX_ERR_STATE;
-    if (!desc || !ticket) return SHMEMX_ERR_ARG;
+    if (!desc || !ticket || lane < 0 || lane >= SHMEMX_PROGRESS_LANES) return SHMEMX_ERR_ARG;
     const uint64_t mask = p.slots - 1;
     uint64_t t = p.head.load(std::memory_order_relaxed);
     for (;;) {
@@ -730,7 +731,9 @@ int shmemx_progress_submit(const shmemx_desc_t *desc, uint64_t *ticket)
             t = p.head.load(std::memory_order_relaxed);
         }
     }
-    p.ring[t & mask] = *desc;
+    shmemx_desc_t *slot = p.ring + (t & mask);
+    *slot = *desc;
+    slot->reserved = (uint64_t)lane;     // carried to the completion record
     __atomic_store_n(p.ring_seq + (t & mask), t + 1, __ATOMIC_RELEASE);
     *ticket = t;
     return SHMEMX_OK;

@@ -234,6 +234,22 @@ static int finish_init(void *heap, size_t heap_bytes, int npes, hipStream_t stre
     VSHMEM_HIP(hipHostGetDevicePointer((void **)&s.host_words_dev, s.host_words, 0));
     s.heap.reset(s.user_bytes);
     reset_teams();
+    // Active tune table: VSHMEM_TUNE_FILE when it names a table saved on
+    // this kind of device, else the built-in defaults.
+    shmemx_tune_default(&s.tune);
+    s.tune_source = SHMEMX_TUNE_SRC_DEFAULT;
+    if (const char *tf = getenv("VSHMEM_TUNE_FILE")) {
+        shmemx_tune_t t;
+        if (*tf && shmemx_tune_load(&t, tf) == SHMEMX_OK) {
+            s.tune = t;
+            s.tune_source = SHMEMX_TUNE_SRC_FILE;
+        } else if (*tf) {
+            s.tune_source = SHMEMX_TUNE_SRC_FILE_REFUSED;
+            if (s.debug) fprintf(stderr, "vshmem: VSHMEM_TUNE_FILE=%s refused; using the built-in table\n", tf);
+        }
+    }
+    VSHMEM_HIP(hipMalloc((void **)&s.d_tune, sizeof(shmemx_tune_t)));
+    VSHMEM_HIP(hipMemcpyAsync(s.d_tune, &s.tune, sizeof(shmemx_tune_t), hipMemcpyHostToDevice, stream));
     s.initialised = true;
     shmemx_dctx_pub_t c = pub();
     hipError_t e = hipMemcpyAsync(s.d_ctx, &c, sizeof(c), hipMemcpyHostToDevice, stream);
@@ -256,6 +272,26 @@ static int republish()
         s.ctx_recs[i].pub = c;
         VSHMEM_HIP(hipMemcpy(s.d_ctx_recs + i, &s.ctx_recs[i], sizeof(shmemx_dctx_rec_t), hipMemcpyHostToDevice));
     }
+    return SHMEMX_OK;
+}
+
+void register_bar_block(void *p, size_t bytes) { g_state.bar_blocks.push_back({p, bytes}); }
+
+void unregister_bar_block(void *p)
+{
+    auto &v = g_state.bar_blocks;
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i].first == p) {
+            v.erase(v.begin() + (long)i);
+            return;
+        }
+}
+
+int check_tune(const shmemx_tune_t &t)
+{
+    if (!valid_wg_size(t.wg_size) || t.grid_wgs < 0) return SHMEMX_ERR_ARG;
+    for (int c = 0; c < SHMEMX_TUNE_CLASSES; ++c)
+        if (t.scope[c] > SHMEMX_SCOPE_GRID) return SHMEMX_ERR_ARG;
     return SHMEMX_OK;
 }
 
@@ -318,6 +354,8 @@ void shmem_finalize(void)
     if (progress_running()) (void)shmemx_progress_stop(10000);
     (void)hipDeviceSynchronize();
     progress_release();
+    batch_release_workspaces();
+    if (s.d_tune) (void)hipFree(s.d_tune);
     if (s.d_ctx) (void)hipFree(s.d_ctx);
     if (s.d_ctx_recs) (void)hipFree(s.d_ctx_recs);
     if (s.d_err) (void)hipFree(s.d_err);
@@ -593,9 +631,32 @@ int shmemx_device_errors(void)
         // restarts at phase 0, count 0.
         for (int p = 0; p < s.npes; ++p)
             VSHMEM_HIP(hipMemsetAsync(s.base + (uint64_t)p * s.stride + s.user_bytes, 0, VSHMEM_SCRATCH_BYTES, nullptr));
+        for (const auto &b : s.bar_blocks) VSHMEM_HIP(hipMemsetAsync(b.first, 0, b.second, nullptr));
         VSHMEM_HIP(hipStreamSynchronize(nullptr));
     }
     return (int)(v & 0x7fffffffu);
+}
+
+int shmemx_tune_set(const shmemx_tune_t *tune)
+{
+    if (int rc = check_ready()) return rc;
+    if (!tune || check_tune(*tune)) return SHMEMX_ERR_ARG;
+    State &s = st();
+    // Kernels already queued read the device copy: replace it in stream order
+    // after everything issued so far.
+    VSHMEM_HIP(hipDeviceSynchronize());
+    VSHMEM_HIP(hipMemcpy(s.d_tune, tune, sizeof(*tune), hipMemcpyHostToDevice));
+    s.tune = *tune;
+    s.tune_source = SHMEMX_TUNE_SRC_SET;
+    return SHMEMX_OK;
+}
+
+int shmemx_tune_get(shmemx_tune_t *tune)
+{
+    if (int rc = check_ready()) return rc;
+    if (!tune) return SHMEMX_ERR_ARG;
+    *tune = st().tune;
+    return st().tune_source;
 }
 
 int shmemx_set_wait_timeout_ns(uint64_t ns)

@@ -15,8 +15,6 @@ namespace vshmem {
 
 constexpr uint64_t kSliceAlign = 2ull << 20;      // PE slices are 2 MiB aligned
 constexpr uint64_t kMinAlign = 256;               // default allocation alignment
-constexpr int kTeamSlotPlan = 250;                // grid barrier of fused plans
-constexpr int kTeamSlotColl = 251;                // spare
 
 struct Team {
     bool live = false;
@@ -67,6 +65,14 @@ struct State {
     shmemx_dctx_rec_t *d_ctx_recs = nullptr;
     shmemx_dctx_rec_t ctx_recs[SHMEMX_MAX_DEVICE_CTX] = {};
     bool ctx_live[SHMEMX_MAX_DEVICE_CTX] = {};
+    // Active tune table (batched forms without a table of their own): host
+    // copy, device copy, and where it came from (SHMEMX_TUNE_SRC_*).
+    shmemx_tune_t tune = {};
+    shmemx_tune_t *d_tune = nullptr;
+    int tune_source = 0;
+    // Grid-barrier words outside the heap (one block per live plan), cleared
+    // with the heap's barrier words after a wait timeout.
+    std::vector<std::pair<void *, size_t>> bar_blocks;
 };
 
 constexpr int kHostWords = 512;
@@ -114,6 +120,14 @@ int blocks_per_cu(K kernel, int wg, int *per_cu)
     }
     return SHMEMX_OK;
 }
+
+// Register / forget a block of grid-barrier words (cleared after a timeout).
+void register_bar_block(void *p, size_t bytes);
+void unregister_bar_block(void *p);
+// Free the per-stream workspaces of device-table batches (finalisation).
+void batch_release_workspaces();
+// Validate a tune table (work-group size, scopes); SHMEMX_OK or SHMEMX_ERR_ARG.
+int check_tune(const shmemx_tune_t &t);
 
 bool progress_running();
 void progress_release();

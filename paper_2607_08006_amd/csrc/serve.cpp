@@ -102,12 +102,12 @@ struct ProgressBackend final : Backend {
     std::condition_variable cv;
     std::atomic<uint64_t> gen{0};
 
-    int submit(const shmemx_desc_t &d, size_t, int, uint64_t *ticket) override
+    int submit(const shmemx_desc_t &d, size_t, int lane, uint64_t *ticket) override
     {
         const Clock::time_point t0 = Clock::now();
         for (;;) {
             const uint64_t seen = gen.load(std::memory_order_acquire);
-            const int rc = shmemx_progress_submit(&d, ticket);
+            const int rc = shmemx_progress_submit(lane % SHMEMX_PROGRESS_LANES, &d, ticket);
             if (rc != SHMEMX_ERR_BUSY) return rc;
             busy_retries.fetch_add(1, std::memory_order_relaxed);
             if (Clock::now() - t0 > std::chrono::seconds(30)) return rc;

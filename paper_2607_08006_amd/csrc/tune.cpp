@@ -75,6 +75,16 @@ int time_candidate(const Cand &c, uint64_t off, uint64_t span, uint64_t bytes, i
     return SHMEMX_OK;
 }
 
+// Key of the current device in saved tables: its architecture name, or
+// empty when no device is visible.
+std::string device_key()
+{
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    return std::string(prop.gcnArchName);
+}
+
 }  // namespace
 
 extern "C" {
@@ -125,14 +135,11 @@ int shmemx_autotune(uint64_t scratch_off, uint64_t scratch_bytes, uint64_t min_b
 int shmemx_tune_save(const shmemx_tune_t *t, const char *path)
 {
     if (!t || !path) return SHMEMX_ERR_ARG;
-    hipDeviceProp_t prop{};
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipGetDeviceProperties(&prop, dev);
+    const std::string key = device_key();
     FILE *f = fopen(path, "w");
     if (!f) return SHMEMX_ERR_ARG;
     fprintf(f, "{\n  \"device\": \"%s\",\n  \"wg_size\": %d,\n  \"grid_wgs\": %d,\n  \"classes\": [\n",
-            prop.gcnArchName, t->wg_size, t->grid_wgs);
+            key.c_str(), t->wg_size, t->grid_wgs);
     for (int c = 0; c < SHMEMX_TUNE_CLASSES; ++c)
         fprintf(f, "    {\"log2\": %d, \"scope\": %d, \"chunk\": %llu}%s\n", c, t->scope[c],
                 (unsigned long long)t->chunk[c], c + 1 < SHMEMX_TUNE_CLASSES ? "," : "");
@@ -141,9 +148,10 @@ int shmemx_tune_save(const shmemx_tune_t *t, const char *path)
     return SHMEMX_OK;
 }
 
-int shmemx_tune_load(shmemx_tune_t *t, const char *path)
+int shmemx_tune_load(shmemx_tune_t *out, const char *path)
 {
-    if (!t || !path) return SHMEMX_ERR_ARG;
+    if (!out || !path) return SHMEMX_ERR_ARG;
+    shmemx_tune_t *t = nullptr;
     FILE *f = fopen(path, "r");
     if (!f) return SHMEMX_ERR_ARG;
     std::string s;
@@ -151,7 +159,22 @@ int shmemx_tune_load(shmemx_tune_t *t, const char *path)
     size_t k;
     while ((k = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, k);
     fclose(f);
-    shmemx_tune_default(t);
+    // The table is only valid on the kind of device it was measured on.
+    const std::string here = device_key();
+    {
+        const size_t k0 = s.find("\"device\"");
+        const size_t q0 = k0 == std::string::npos ? k0 : s.find('"', s.find(':', k0));
+        const size_t q1 = q0 == std::string::npos ? q0 : s.find('"', q0 + 1);
+        const std::string saved = q1 == std::string::npos ? std::string() : s.substr(q0 + 1, q1 - q0 - 1);
+        if (k0 == std::string::npos || saved != here) {
+            set_error_detail(SHMEMX_ERR_ARG, "tune table %s was saved on device '%s', this is '%s'", path,
+                             saved.c_str(), here.c_str());
+            return SHMEMX_ERR_ARG;
+        }
+    }
+    shmemx_tune_t tmp;
+    shmemx_tune_default(&tmp);
+    t = &tmp;
     auto num_after = [&](const std::string &key, size_t from, long long *v) -> size_t {
         size_t p = s.find(key, from);
         if (p == std::string::npos) return p;
@@ -177,7 +200,9 @@ int shmemx_tune_load(shmemx_tune_t *t, const char *path)
         }
         pos = p3 + 1;
     }
-    return valid_wg_size(t->wg_size) ? SHMEMX_OK : SHMEMX_ERR_ARG;
+    if (check_tune(tmp)) return SHMEMX_ERR_ARG;
+    *out = tmp;
+    return SHMEMX_OK;
 }
 
 }  // extern "C"

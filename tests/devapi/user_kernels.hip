@@ -3,6 +3,7 @@
 // descriptor from the host, and call the device-side collectives and team
 // barriers themselves.  Built into its own shared library, apart from
 // libvshmem.so, so that the header-only device API is exercised on its own.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include "vshmem.h"
@@ -221,9 +222,49 @@ __global__ void __launch_bounds__(256) k_user_debug(const shmemx_dctx_pub_t *pub
     }
 }
 
+// A kernel that writes a descriptor table: record i is assembled from
+// column arrays (op, scope, aux and flags packed in one word per record).
+__global__ void k_user_write_table(shmemx_desc_t *out, size_t n, const uint32_t *code, const int32_t *issuer,
+                                   const int32_t *target, const uint32_t *ridx, const uint64_t *src,
+                                   const uint64_t *dst, const uint64_t *nbytes, const uint64_t *value,
+                                   const uint64_t *cond)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        shmemx_desc_t d;
+        d.op = (uint8_t)(code[i] & 0xFF);
+        d.scope = (uint8_t)((code[i] >> 8) & 0xFF);
+        d.aux = (uint8_t)((code[i] >> 16) & 0xFF);
+        d.flags = (uint8_t)(code[i] >> 24);
+        d.issuer_pe = issuer[i];
+        d.target_pe = target[i];
+        d.result_idx = ridx[i];
+        d.src = src[i];
+        d.dst = dst[i];
+        d.nbytes = nbytes[i];
+        d.value = value[i];
+        d.cond = cond[i];
+        d.reserved = 0;
+        out[i] = d;
+    }
+}
+
 }  // namespace
 
 extern "C" {
+
+int usertest_write_table(void *out, size_t n, const void *code, const void *issuer, const void *target,
+                         const void *ridx, const void *src, const void *dst, const void *nbytes, const void *value,
+                         const void *cond, void *stream)
+{
+    if (!out || (n && (!code || !issuer || !target || !ridx || !src || !dst || !nbytes || !value || !cond))) return -1;
+    if (n == 0) return 0;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_user_write_table, dim3(grid), dim3(256), 0, (hipStream_t)stream, (shmemx_desc_t *)out, n,
+                       (const uint32_t *)code, (const int32_t *)issuer, (const int32_t *)target,
+                       (const uint32_t *)ridx, (const uint64_t *)src, (const uint64_t *)dst, (const uint64_t *)nbytes,
+                       (const uint64_t *)value, (const uint64_t *)cond);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 // Each launcher checks what it can on the host and returns 0, or -1 for an
 // argument its kernel would not handle.

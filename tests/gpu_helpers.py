@@ -99,6 +99,7 @@ def user_lib():
         "usertest_gspace": [vp, i32, vp, vp, vp, vp, sz, sz, sz, vp],
         "usertest_fence": [vp, i32, i32, vp, sz, vp, i32, vp, vp],
         "usertest_debug": [vp, vp, vp, i32, vp, vp, vp, i32, vp],
+        "usertest_write_table": [vp, sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)

@@ -41,7 +41,9 @@ def test_header_declares_the_boundary():
                  "shmemx_broadcastmem_launch", "shmemx_fcollectmem_launch", "shmemx_alltoallmem_launch",
                  "shmemx_reduce_launch", "shmemx_plan_create", "shmemx_plan_launch_fused",
                  "shmemx_plan_launch_per_op", "shmemx_plan_graph_build", "shmemx_autotune",
-                 "shmemx_progress_start", "shmemx_progress_submit", "shmemx_serve_run"):
+                 "shmemx_progress_start", "shmemx_progress_submit", "shmemx_serve_run",
+                 "shmemx_launch_batch", "shmemx_launch_per_op", "shmemx_graph_build", "shmemx_graph_launch",
+                 "shmemx_graph_destroy", "shmemx_tune_set", "shmemx_tune_get"):
         assert must in names
 
 
@@ -146,3 +148,26 @@ def test_tune_table_json_round_trip(tmp_path):
     import json
     d = json.load(open(path))
     assert d["wg_size"] == 512 and len(d["classes"]) == 40
+
+
+def test_tune_load_refuses_other_devices_and_invalid_tables(tmp_path):
+    """A saved table names the device it was measured on; loading it where
+    another device (or none, or no key) is seen, or loading an invalid
+    table, fails with SHMEMX_ERR_ARG."""
+    _ensure_built()
+    import json
+    import paper_2607_08006_amd as v
+    path = str(tmp_path / "tune.json")
+    v.tune_save(v.default_tune(), path)
+    d = json.load(open(path))
+    for name, edit in [("other device", lambda x: x.update(device="gfx000:other")),
+                       ("no device key", lambda x: x.pop("device")),
+                       ("bad work-group size", lambda x: x.update(wg_size=100)),
+                       ("bad scope", lambda x: x["classes"][5].update(scope=9))]:
+        e = json.loads(json.dumps(d))
+        edit(e)
+        bad = str(tmp_path / "bad.json")
+        json.dump(e, open(bad, "w"))
+        with pytest.raises(v.VshmemError) as err:
+            v.tune_load(bad)
+        assert err.value.code == v.ERR_ARG, name

@@ -414,3 +414,45 @@ def test_completed_request_is_visible_while_the_kernel_runs():
             v.progress_stop(10000)
             side.synchronize()
         assert_no_device_errors()
+
+
+def test_progress_lanes_are_checked_and_recorded():
+    """Requests carry the producer lane they were submitted on into their
+    completion records; a lane outside [0, 8) is refused on the host."""
+    npes = 2
+    with heap(npes, 4 << 20) as v:
+        t = torch()
+        region = 2 << 20
+        init = W.heap_fill(0x1A7E, npes, region)
+        upload(init)
+        side = t.cuda.Stream()
+        t.cuda.synchronize()
+        v.progress_start(nwg=8, wg_size=256, ring_slots=64, stream=side)
+        reqs, tickets, comps = [], {}, {}
+        try:
+            for lane in (-1, v.PROGRESS_LANES):
+                with pytest.raises(v.VshmemError) as e:
+                    v.progress_submit(_desc(W.OP_PUT, 0, 1, 0, 1 << 20, 64), lane=lane)
+                assert e.value.code == v.ERR_ARG
+            for lane in range(v.PROGRESS_LANES):
+                r = (W.OP_PUT if lane % 2 else W.OP_GET, lane % 2, (lane + 1) % 2, 4096 * lane,
+                     (1 << 20) + 8192 * lane, 1000 + 7 * lane)
+                reqs.append(r)
+                tickets[v.progress_submit(_desc(*r), lane=lane)] = lane
+            t0 = time.time()
+            while len(comps) < len(tickets) and time.time() - t0 < 30:
+                for tk in tickets:
+                    if tk not in comps:
+                        c = v.progress_poll(tk)
+                        if c is not None:
+                            comps[tk] = c
+        finally:
+            v.progress_stop(10000)
+            side.synchronize()
+        assert len(comps) == len(tickets)
+        for tk, lane in tickets.items():
+            assert comps[tk].status == 0 and comps[tk].lane == lane
+        ref = init.copy()
+        oracle.run_program(ref, W.descs([(op, 0, 0, i, tg, W.NO_RESULT, s, d, n, 0, 0) for op, i, tg, s, d, n in reqs]))
+        assert np.array_equal(download(region), ref)
+        assert_no_device_errors()

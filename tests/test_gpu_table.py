@@ -1,0 +1,246 @@
+"""GPU parity: batches over a descriptor table in DEVICE memory, written by a
+kernel (the test's own user kernel assembles it from column arrays), in the
+fused form (index kernel + cursor executor), the per-operation form and
+graphs of both, against the oracle run on the same program.  Also: graphs
+replay what the table holds at replay time, invalid descriptors are skipped
+and reported, plans launched together on two streams keep their barriers
+apart, and the active tune table comes from VSHMEM_TUNE_FILE."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import workload as W
+from tests.gpu_helpers import assert_no_device_errors, download, heap, torch, upload, user_lib
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype):
+    return torch().from_numpy(np.ascontiguousarray(a).astype(dtype)).to("cuda")
+
+
+def write_table(descs: np.ndarray, out=None):
+    """Have a kernel write `descs` into a device table (a uint8 tensor of
+    64 bytes per record); returns the table."""
+    t = torch()
+    n = len(descs)
+    if out is None:
+        out = t.zeros(max(1, n) * 64, dtype=t.uint8, device="cuda")
+    code = (descs["op"].astype(np.uint32) | (descs["scope"].astype(np.uint32) << 8) |
+            (descs["aux"].astype(np.uint32) << 16) | (descs["flags"].astype(np.uint32) << 24))
+    cols = [_dev(code.view(np.int32), np.int32), _dev(descs["issuer"], np.int32), _dev(descs["target"], np.int32),
+            _dev(descs["result_idx"].view(np.int32), np.int32)]
+    cols += [_dev(descs[f].view(np.int64), np.int64) for f in ("src", "dst", "nbytes", "value", "cond")]
+    rc = user_lib().usertest_write_table(out.data_ptr(), n, *[c.data_ptr() for c in cols], None)
+    assert rc == 0
+    t.cuda.synchronize()
+    return out
+
+
+def _program(seed, npes=4, heap_bytes=1 << 20, base_off=0, n_rma=600, n_amo=3000, fences=40):
+    """The 4-PE mixed workload (put/get epochs separated by barriers, then
+    contended fetch_add) with per-PE fences inserted at seeded positions."""
+    wl = W.small_workload(seed=seed, npes=npes, heap_bytes=heap_bytes, n_rma=n_rma, epoch_ops=100, n_amo=n_amo,
+                          base_off=base_off)
+    d = wl.descs
+    x = W.splitmix64(W.subseed(seed, 0xFE), 0, 2 * fences)
+    pos = np.sort(W.bounded(x[0::2], 0, len(d) - 1))
+    who = W.bounded(x[1::2], 0, npes - 1)
+    parts, last = [], 0
+    for p, w in zip(pos, who):
+        parts.append(d[last:p])
+        parts.append(W.descs([(W.OP_FENCE, W.SCOPE_THREAD, 0, int(w), int(w), W.NO_RESULT, 0, 0, 0, 0, 0)]))
+        last = p
+    parts.append(d[last:])
+    return wl, np.concatenate(parts)
+
+
+def _tunes(v):
+    """(name, device tune or None): the active table; work-group scope with
+    256-byte tasks from 256 B up (many tasks per message); one lane for
+    everything."""
+    t = torch()
+    wg = v.default_tune()
+    for c in range(W.log2_class(256), 40):
+        wg.scope[c] = v.SCOPE_WG
+        wg.chunk[c] = 256
+    lane = v.default_tune()
+    for c in range(40):
+        lane.scope[c] = v.SCOPE_THREAD
+    out = [("active", None)]
+    for name, tb in (("wg_256B_tasks", wg), ("one_lane", lane)):
+        buf = bytes(tb)
+        out.append((name, t.frombuffer(bytearray(buf), dtype=t.uint8).to("cuda")))
+    return out
+
+
+def _check(v, got, ref, res, wl, descs):
+    assert np.array_equal(got, ref)
+    fetched = res.cpu().numpy()[:wl.n_amo]
+    amo = descs[descs["op"] == W.OP_AMO_FETCH_ADD]
+    for c in np.unique(amo["src"]):
+        ids = amo[amo["src"] == c]["result_idx"].astype(np.int64)
+        assert np.array_equal(np.sort(fetched[ids]), np.arange(len(ids))), "fetched values are not a permutation"
+
+
+def test_kernel_written_table_all_forms_match_oracle():
+    t = torch()
+    with heap(4, 2 << 20) as v:
+        wl, descs = _program(W.SEED_SMALL)
+        n = len(descs)
+        table = write_table(descs)
+        ref = wl.init.copy()
+        oracle.run_program(ref, descs, nresults=wl.n_amo)
+        s = t.cuda.Stream()
+        for tname, dtune in _tunes(v):
+            res = t.zeros(n, dtype=t.int64, device="cuda")
+            for form in ("fused", "per_op"):
+                upload(wl.init)
+                res.zero_()
+                with t.cuda.stream(s):
+                    if form == "fused":
+                        v.launch_batch(table, n, results=res, d_tune=dtune, stream=s)
+                    else:
+                        v.launch_per_op(table, n, results=res, d_tune=dtune, stream=s)
+                s.synchronize()
+                _check(v, download(wl.heap_bytes), ref, res, wl, descs)
+            for gform in (0, 1):
+                g = v.Graph(table, n, gform, results=res, d_tune=dtune)
+                for rep in range(3):   # replays with eager work and synchronisation between them
+                    upload(wl.init)
+                    res.zero_()
+                    t.cuda.synchronize()
+                    g.launch(stream=s)
+                    s.synchronize()
+                    _check(v, download(wl.heap_bytes), ref, res, wl, descs)
+                g.destroy()
+            assert_no_device_errors(), tname
+
+
+def test_graph_replays_the_table_as_rewritten():
+    """A fused graph captured once replays whatever the table holds: a
+    kernel rewrites it with another program between replays."""
+    t = torch()
+    with heap(4, 2 << 20) as v:
+        progs = [_program(W.SEED_SMALL + k, n_rma=300, n_amo=1000, fences=10) for k in range(3)]
+        n = max(len(d) for _, d in progs)
+        table = t.zeros(n * 64, dtype=t.uint8, device="cuda")
+        res = t.zeros(n, dtype=t.int64, device="cuda")
+        g = v.Graph(table, n, 1, results=res)
+        for wl, descs in progs:
+            pad = np.zeros(n - len(descs), dtype=W.DESC_DTYPE)        # NOP records
+            full = np.concatenate([descs, pad])
+            write_table(full, out=table)
+            upload(wl.init)
+            res.zero_()
+            t.cuda.synchronize()
+            g.launch()
+            t.cuda.synchronize()
+            ref = wl.init.copy()
+            oracle.run_program(ref, descs, nresults=wl.n_amo)
+            _check(v, download(wl.heap_bytes), ref, res, wl, descs)
+        g.destroy()
+        assert_no_device_errors()
+
+
+def test_invalid_descriptors_are_skipped_and_reported():
+    t = torch()
+    with heap(4, 2 << 20) as v:
+        wl, descs = _program(W.SEED_SMALL + 7, n_rma=200, n_amo=500, fences=5)
+        n = len(descs) + 5
+        ub = v.heap_user_bytes()
+        bad = W.descs([
+            (W.OP_PUT, W.SCOPE_AUTO, 0, 0, 1, W.NO_RESULT, 0, ub - 4, 8, 0, 0),           # past the user heap
+            (W.OP_WAIT_UNTIL, W.SCOPE_THREAD, 0, 1, 1, W.NO_RESULT, 0, 0, 8, 1, 0),       # not in batches
+            (200, W.SCOPE_THREAD, 0, 2, 2, W.NO_RESULT, 0, 0, 8, 0, 0),                   # unknown op code
+            (W.OP_AMO_FETCH_ADD, W.SCOPE_THREAD, 0, 3, 0, n, wl.counter_off, 0, 8, 1, 0),  # result index >= n
+            (W.OP_GET, W.SCOPE_AUTO, 0, 1, 4, W.NO_RESULT, 0, 0, 64, 0, 0),               # target PE 4 of 4
+        ])
+        mixed = np.concatenate([descs[:50], bad[:2], descs[50:400], bad[2:], descs[400:]])
+        assert len(mixed) == n
+        table = write_table(mixed)
+        res = t.zeros(n, dtype=t.int64, device="cuda")
+        ref = wl.init.copy()
+        oracle.run_program(ref, descs, nresults=wl.n_amo)
+        for form in ("fused", "per_op"):
+            upload(wl.init)
+            res.zero_()
+            (v.launch_batch if form == "fused" else v.launch_per_op)(table, n, results=res)
+            t.cuda.synchronize()
+            assert np.array_equal(download(wl.heap_bytes), ref), form
+            assert v.device_errors() & v.DEVERR_BAD_DESC, form
+        # Programs with unequal barrier counts run nothing.
+        extra = W.descs([(W.OP_BARRIER_ALL, W.SCOPE_WG, 0, 0, 0, W.NO_RESULT, 0, 0, 0, 0, 0)])
+        uneven = np.concatenate([descs, extra])
+        table = write_table(uneven)
+        upload(wl.init)
+        v.launch_batch(table, len(uneven), results=res)
+        t.cuda.synchronize()
+        assert np.array_equal(download(wl.heap_bytes), wl.init)
+        assert v.device_errors() & v.DEVERR_BAD_DESC
+
+
+def test_two_plans_on_two_streams_keep_their_barriers_apart():
+    """Multi-phase fused plans launched together on two streams: each plan
+    has its own barrier words, so both equal the oracle.  Each plan's grid is
+    capped so that the two fit the device together."""
+    t = torch()
+    with heap(4, 2 << 20) as v:
+        half = 512 << 10
+        progs = [_program(W.SEED_SMALL + 20 + k, heap_bytes=half, base_off=k * half, n_rma=400, n_amo=1000)
+                 for k in range(2)]
+        init = np.concatenate([progs[0][0].init, progs[1][0].init], axis=1)
+        ref = init.copy()
+        for wl, descs in progs:
+            oracle.run_program(ref, descs, nresults=wl.n_amo)
+        tune = v.default_tune()
+        tune.grid_wgs = 32
+        plans = [v.Plan(d, tune) for _, d in progs]
+        assert all(p.info()["phases"] > 3 for p in plans)
+        streams = [t.cuda.Stream(), t.cuda.Stream()]
+        res = [t.zeros(len(d), dtype=t.int64, device="cuda") for _, d in progs]
+        for rep in range(4):
+            upload(init)
+            for r in res:
+                r.zero_()
+            t.cuda.synchronize()
+            for p, s, r in zip(plans, streams, res):
+                p.launch_fused(results=r, stream=s)
+            t.cuda.synchronize()
+            got = download(2 * half)
+            for k, (wl, descs) in enumerate(progs):
+                lo, hi = k * half, (k + 1) * half
+                _check(v, got[:, lo:hi], ref[:, lo:hi], res[k], wl, descs)
+        for p in plans:
+            p.destroy()
+        assert_no_device_errors()
+
+
+def test_tune_file_at_init_and_tune_set(tmp_path, monkeypatch):
+    import json
+    path = str(tmp_path / "tune.json")
+    with heap(2, 2 << 20) as v:
+        t0, src = v.tune_get()
+        assert src == v.TUNE_SRC_DEFAULT and t0.wg_size == v.default_tune().wg_size
+        t0.wg_size = 512
+        t0.scope[10] = v.SCOPE_WG
+        v.tune_save(t0, path)
+    monkeypatch.setenv("VSHMEM_TUNE_FILE", path)
+    with heap(2, 2 << 20) as v:
+        t1, src = v.tune_get()
+        assert src == v.TUNE_SRC_FILE and t1.wg_size == 512 and t1.scope[10] == v.SCOPE_WG
+        v.tune_set(v.default_tune())
+        t2, src = v.tune_get()
+        assert src == v.TUNE_SRC_SET and t2.wg_size == v.default_tune().wg_size
+        bad = v.default_tune()
+        bad.wg_size = 96
+        with pytest.raises(v.VshmemError):
+            v.tune_set(bad)
+    d = json.load(open(path))
+    d["device"] = "gfx000:not-this-one"
+    json.dump(d, open(path, "w"))
+    with heap(2, 2 << 20) as v:
+        t3, src = v.tune_get()
+        assert src == v.TUNE_SRC_FILE_REFUSED and t3.wg_size == v.default_tune().wg_size
