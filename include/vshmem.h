@@ -744,6 +744,21 @@ int shmemx_graph_build(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_resul
 int shmemx_graph_launch(shmemx_graph_t *graph, void *stream);
 void shmemx_graph_destroy(shmemx_graph_t *graph);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): shmemx_launch_batch
+ * with the same arguments, results and errors, whose workspace is a fixed
+ * 4 MiB array in device memory instead of a per-stream allocation.  It calls
+ * no hipMalloc or hipFree.  The array is set up at initialisation; each
+ * device holds its own until the process ends.  Tables of at most
+ * shmemx_launch_batch_noalloc_max() descriptors (SHMEMX_ERR_ARG above).
+ * Every call on a device shares the array and keeps what the last call left
+ * there (the index kernel clears what it needs): calls that overlap on one
+ * device race and must be ordered by the caller (one stream, or
+ * synchronised). */
+int shmemx_launch_batch_noalloc(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results,
+                                const shmemx_tune_t *d_tune, void *stream);
+uint64_t shmemx_launch_batch_noalloc_max(void);
+
 /* ------------------------------------------------------------- serving
  * Persistent progress kernel (long-lived kernels, Section 3; GPU-driven
  * progress, Section 6.4 and Section 7).  Host threads submit descriptors

@@ -449,6 +449,17 @@ def launch_batch(d_descs, n: int, results=None, d_tune=None, stream=None) -> Non
            "shmemx_launch_batch")
 
 
+def launch_batch_noalloc(d_descs, n: int, results=None, d_tune=None, stream=None) -> None:
+    """launch_batch over the library's fixed device workspace (no allocation);
+    calls that overlap on one device race."""
+    _check(lib.shmemx_launch_batch_noalloc(_ptr(d_descs), n, _ptr(results), _ptr(d_tune), _stream(stream)),
+           "shmemx_launch_batch_noalloc")
+
+
+def launch_batch_noalloc_max() -> int:
+    return int(lib.shmemx_launch_batch_noalloc_max())
+
+
 def launch_per_op(d_descs, n: int, results=None, d_tune=None, stream=None) -> None:
     _check(lib.shmemx_launch_per_op(_ptr(d_descs), n, _ptr(results), _ptr(d_tune), _stream(stream)),
            "shmemx_launch_per_op")

@@ -125,6 +125,8 @@ SIGNATURES = {
     "shmemx_tune_get": (i32, [P(Tune)]),
     "shmemx_launch_batch": (i32, [vp, sz, vp, vp, vp]),
     "shmemx_launch_per_op": (i32, [vp, sz, vp, vp, vp]),
+    "shmemx_launch_batch_noalloc": (i32, [vp, sz, vp, vp, vp]),
+    "shmemx_launch_batch_noalloc_max": (u64, []),
     "shmemx_graph_build": (i32, [vp, sz, vp, vp, i32, P(vp)]),
     "shmemx_graph_launch": (i32, [vp, vp]),
     "shmemx_graph_destroy": (None, [vp]),

@@ -596,7 +596,17 @@ int launch_ops(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, cons
     return SHMEMX_OK;
 }
 
+constexpr uint64_t kNoAllocBytes = 4ull << 20;
+std::mutex g_noalloc_mu;
+std::map<int, uint8_t *> g_noalloc_ptr;     // device ordinal -> address of its copy of `scratch`
+
 }  // namespace
+
+// Workspace of shmemx_launch_batch_noalloc: a fixed array in device memory
+// that every call on a device shares.  Its device address comes from
+// hipGetSymbolAddress once per device; in host code the name is only a
+// stand-in, never an address to hand to a kernel.
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
 
 struct shmemx_graph {
     hipGraph_t graph = nullptr;
@@ -605,6 +615,16 @@ struct shmemx_graph {
 };
 
 namespace vshmem {
+int batch_noalloc_setup(int device)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr.count(device)) return SHMEMX_OK;
+    void *ptr = nullptr;
+    VSHMEM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_noalloc_ptr[device] = (uint8_t *)ptr;
+    return SHMEMX_OK;
+}
+
 void batch_release_workspaces()
 {
     std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -642,6 +662,29 @@ int shmemx_launch_batch(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_resu
     }
     return launch_fused(d_descs, n, d_results, d_tune, buf, cap, hs);
 }
+
+int shmemx_launch_batch_noalloc(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results,
+                                const shmemx_tune_t *d_tune, void *stream)
+{
+    if (int rc = check_table(d_descs, n)) return rc;
+    static const uint64_t cap = ws_capacity(kNoAllocBytes);
+    if (n > cap) {
+        set_error_detail(SHMEMX_ERR_ARG, "shmemx_launch_batch_noalloc: %zu descriptors, at most %llu fit its %llu-byte "
+                         "workspace", n, (unsigned long long)cap, (unsigned long long)kNoAllocBytes);
+        return SHMEMX_ERR_ARG;
+    }
+    if (n == 0) return SHMEMX_OK;
+    uint8_t *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        auto it = g_noalloc_ptr.find(st().device);
+        if (it != g_noalloc_ptr.end()) ws = it->second;
+    }
+    if (!ws) return SHMEMX_ERR_STATE;   // set up at initialisation
+    return launch_fused(d_descs, n, d_results, d_tune, ws, cap, (hipStream_t)stream);
+}
+
+uint64_t shmemx_launch_batch_noalloc_max(void) { return ws_capacity(kNoAllocBytes); }
 
 int shmemx_launch_per_op(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, const shmemx_tune_t *d_tune,
                          void *stream)

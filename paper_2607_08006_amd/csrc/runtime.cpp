@@ -248,6 +248,7 @@ static int finish_init(void *heap, size_t heap_bytes, int npes, hipStream_t stre
             if (s.debug) fprintf(stderr, "vshmem: VSHMEM_TUNE_FILE=%s refused; using the built-in table\n", tf);
         }
     }
+    if (int rc = batch_noalloc_setup(s.device)) return rc;
     VSHMEM_HIP(hipMalloc((void **)&s.d_tune, sizeof(shmemx_tune_t)));
     VSHMEM_HIP(hipMemcpyAsync(s.d_tune, &s.tune, sizeof(shmemx_tune_t), hipMemcpyHostToDevice, stream));
     s.initialised = true;

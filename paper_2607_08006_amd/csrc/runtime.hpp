@@ -126,6 +126,9 @@ void register_bar_block(void *p, size_t bytes);
 void unregister_bar_block(void *p);
 // Free the per-stream workspaces of device-table batches (finalisation).
 void batch_release_workspaces();
+// Take the device address of the no-allocation batch workspace on `device`
+// (current), once per device.
+int batch_noalloc_setup(int device);
 // Validate a tune table (work-group size, scopes); SHMEMX_OK or SHMEMX_ERR_ARG.
 int check_tune(const shmemx_tune_t &t);
 

@@ -9,6 +9,8 @@ import os
 
 import numpy as np
 
+import workload as W
+
 USER_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "devapi", "libvshmem_usertest.so")
 _user = None
 
@@ -107,3 +109,43 @@ def user_lib():
         f.restype = i32
     _user = lib
     return lib
+
+
+def _dev(a, dtype):
+    return torch().from_numpy(np.ascontiguousarray(a).astype(dtype)).to("cuda")
+
+
+def write_table(descs: np.ndarray, out=None):
+    """Have a kernel write `descs` into a device table (a uint8 tensor of
+    64 bytes per record); returns the table."""
+    t = torch()
+    n = len(descs)
+    if out is None:
+        out = t.zeros(max(1, n) * 64, dtype=t.uint8, device="cuda")
+    code = (descs["op"].astype(np.uint32) | (descs["scope"].astype(np.uint32) << 8) |
+            (descs["aux"].astype(np.uint32) << 16) | (descs["flags"].astype(np.uint32) << 24))
+    cols = [_dev(code.view(np.int32), np.int32), _dev(descs["issuer"], np.int32), _dev(descs["target"], np.int32),
+            _dev(descs["result_idx"].view(np.int32), np.int32)]
+    cols += [_dev(descs[f].view(np.int64), np.int64) for f in ("src", "dst", "nbytes", "value", "cond")]
+    rc = user_lib().usertest_write_table(out.data_ptr(), n, *[c.data_ptr() for c in cols], None)
+    assert rc == 0
+    t.cuda.synchronize()
+    return out
+
+
+def program(seed, npes=4, heap_bytes=1 << 20, base_off=0, n_rma=600, n_amo=3000, fences=40):
+    """The 4-PE mixed workload (put/get epochs separated by barriers, then
+    contended fetch_add) with per-PE fences inserted at seeded positions."""
+    wl = W.small_workload(seed=seed, npes=npes, heap_bytes=heap_bytes, n_rma=n_rma, epoch_ops=100, n_amo=n_amo,
+                          base_off=base_off)
+    d = wl.descs
+    x = W.splitmix64(W.subseed(seed, 0xFE), 0, 2 * fences)
+    pos = np.sort(W.bounded(x[0::2], 0, len(d) - 1))
+    who = W.bounded(x[1::2], 0, npes - 1)
+    parts, last = [], 0
+    for p, w in zip(pos, who):
+        parts.append(d[last:p])
+        parts.append(W.descs([(W.OP_FENCE, W.SCOPE_THREAD, 0, int(w), int(w), W.NO_RESULT, 0, 0, 0, 0, 0)]))
+        last = p
+    parts.append(d[last:])
+    return wl, np.concatenate(parts)
