@@ -290,6 +290,7 @@ KERNEL_SOURCES = {
     "k_broadcast": ["paper_2607_08006_amd/csrc/coll.hip"],
     "k_fcollect": ["paper_2607_08006_amd/csrc/coll.hip"],
     "k_reduce": ["paper_2607_08006_amd/csrc/coll.hip"],
+    "k_reduce_waves": ["paper_2607_08006_amd/csrc/coll.hip"],
 }
 COMMON_SOURCES = ["include/vshmem.h", "include/vshmem_device.hpp", "paper_2607_08006_amd/csrc/runtime.hpp"]
 PROFILE_DIR = os.path.join(ROOT, "profiles")
@@ -594,14 +595,58 @@ def run_config_sections(v, torch):
     out["pingpong_256pe"] = pp
     out["device_errors"] = v.device_errors()
     v.finalize()
+    # ---- GUPS at full shape: a 2^27-entry int64 table spread over 256 PEs
+    # (2^19 entries each), 2^28 updates (80% fetch_xor, 20% fetch_add), the
+    # fetched values folded into an accumulator
+    v.init(256, 8 * MiB)
+    tab = v.offset(v.malloc(4 * MiB))
+    for p in range(256):
+        v.fill_typed(v.heap_base() + p * v.heap_stride() + tab, 1 << 19, v.DT_INT64,
+                     W.subseed(W.SEED_GUPS, W.TAG_HEAP + p))
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nupd = 1 << 28
+    ms = timed_ms(torch, lambda: v.gups(tab, 27, nupd, W.subseed(W.SEED_GUPS, W.TAG_OPS), 5, acc=acc), 3)
+    out["gups_256pe"] = {"npes": 256, "table_entries": 1 << 27, "updates": nupd, "mix": "80% fetch_xor, 20% fetch_add",
+                         "ms": round(ms, 3), "Mops_s": round(nupd / (ms * 1e-3) / 1e6, 1),
+                         "GB_s": round(16 * nupd / (ms * 1e-3) / 1e9, 1),
+                         "hbm_frac": round(16 * nupd / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["device_errors_gups"] = v.device_errors()
+    v.finalize()
     return out
 
 
+def _host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
 def cpu_baseline(seconds: float):
-    """Time the CPU oracle (single thread, as written) on bounded samples of
-    the step's rows and report algorithmic GB/s."""
+    """Time the CPU oracle, unchanged, on bounded samples of the step's rows
+    and report algorithmic GB/s, twice: one thread in the defined order, and
+    all cores (up to 16 threads, the box's share) on disjoint partitions of
+    the same work -- put messages split over the threads, broadcast by byte
+    range, reductions by element range -- or, where the oracle has no
+    partitioned form (alltoall, GUPS), one independent instance per thread.
+    The oracle's C calls release the interpreter lock, so the threads run
+    the oracle's arithmetic in parallel."""
     import oracle
-    samples = []
+    from concurrent.futures import ThreadPoolExecutor
+    model, ncpu = _host_cpu()
+    T = max(1, min(16, ncpu))
+
+    def split(n, k):
+        b = np.linspace(0, n, k + 1).astype(np.int64)
+        return [(int(b[i]), int(b[i + 1])) for i in range(k) if b[i + 1] > b[i]]
+
+    samples = []   # (name, bytes of one instance, single-thread fn, parallel parts, parallel bytes)
     # put ring, 16 MiB messages: 4 PEs x 4 messages
     npes, msg, k = 4, 16 * MiB, 4
     heap = np.zeros((npes, 2 * k * msg), dtype=np.uint8)
@@ -609,44 +654,70 @@ def cpu_baseline(seconds: float):
     recs = [(W.OP_PUT, 0, 0, p, (p + 1) % npes, W.NO_RESULT, j * msg, k * msg + j * msg, msg, 0, 0)
             for p in range(npes) for j in range(k)]
     d = W.descs(recs)
-    samples.append(("put_ring_16MiB 4PEx4msg", lambda: oracle.run_program(heap, d), 2 * npes * k * msg))
+    parts = [(lambda dd=d[a:b]: oracle.run_program(heap, dd)) for a, b in split(len(d), T)]
+    samples.append(("put_ring_16MiB 4PEx4msg", 2 * npes * k * msg, lambda: oracle.run_program(heap, d), parts,
+                    2 * npes * k * msg))
     # alltoall 1 MiB blocks over 8 PEs
     P, blk = 8, 1 * MiB
-    h2 = np.zeros((P, 2 * P * blk), dtype=np.uint8)
-    samples.append(("alltoall_1MiB 8PE", lambda: oracle.alltoall(h2, P * blk, 0, blk), 2 * P * P * blk))
+    h2 = [np.zeros((P, 2 * P * blk), dtype=np.uint8) for _ in range(T)]
+    samples.append(("alltoall_1MiB 8PE", 2 * P * P * blk, lambda: oracle.alltoall(h2[0], P * blk, 0, blk),
+                     [(lambda h=h: oracle.alltoall(h, P * blk, 0, blk)) for h in h2], T * 2 * P * P * blk))
     # broadcast 32 MiB over 8 PEs
-    h3 = np.zeros((P, 64 * MiB), dtype=np.uint8)
-    samples.append(("broadcast_32MiB 8PE", lambda: oracle.broadcast(h3, 32 * MiB, 0, 32 * MiB, 0),
-                    32 * MiB * (P + 1)))
+    bc = 32 * MiB
+    h3 = np.zeros((P, 2 * bc), dtype=np.uint8)
+    samples.append(("broadcast_32MiB 8PE", bc * (P + 1), lambda: oracle.broadcast(h3, bc, 0, bc, 0),
+                    [(lambda a=a, b=b: oracle.broadcast(h3, bc + a, a, b - a, 0)) for a, b in split(bc, T)],
+                    bc * (P + 1)))
     # reductions 2^18 elements over 8 PEs
     nr = 1 << 18
-    h4 = np.zeros((P, 2 * nr * 8), dtype=np.uint8)
-    for p in range(P):
-        h4[p, :nr * 8] = W.coll_i64(5, p, nr).view(np.uint8)
-    samples.append(("reduce_sum_i64 2^18 8PE", lambda: oracle.reduce(h4, oracle.DT_INT64, oracle.RO_SUM, nr * 8, 0, nr),
-                    2 * P * nr * 8))
-    h5 = np.zeros((P, 2 * nr * 4), dtype=np.uint8)
-    for p in range(P):
-        h5[p, :nr * 4] = W.coll_f32(6, p, nr).view(np.uint8)
-    samples.append(("reduce_sum_f32 2^18 8PE", lambda: oracle.reduce(h5, oracle.DT_FP32, oracle.RO_SUM, nr * 4, 0, nr),
-                    2 * P * nr * 4))
+    for dt, es, gen, tag in ((oracle.DT_INT64, 8, W.coll_i64, "i64"), (oracle.DT_FP32, 4, W.coll_f32, "f32")):
+        h = np.zeros((P, 2 * nr * es), dtype=np.uint8)
+        for p in range(P):
+            h[p, :nr * es] = gen(5, p, nr).view(np.uint8)
+        samples.append((f"reduce_sum_{tag} 2^18 8PE", 2 * P * nr * es,
+                        (lambda h=h, dt=dt, es=es: oracle.reduce(h, dt, oracle.RO_SUM, nr * es, 0, nr)),
+                        [(lambda h=h, dt=dt, es=es, a=a, b=b: oracle.reduce(h, dt, oracle.RO_SUM, nr * es + a * es,
+                                                                             a * es, b - a)) for a, b in split(nr, T)],
+                        2 * P * nr * es))
     # GUPS 2^22 updates on 2^20 entries
     idx, val, is_add = W.gups_updates(W.SEED_GUPS, 0, 1 << 22, 20)
-    table = np.zeros(1 << 20, dtype=np.int64)
-    samples.append(("gups 2^22 upd", lambda: oracle.gups(table, idx, val, is_add), 16 << 22))
-    tot_b, tot_t, reps = 0, 0.0, 0
-    t_end = time.perf_counter() + seconds
-    while time.perf_counter() < t_end or reps == 0:
-        for _, fn, b in samples:
-            t0 = time.perf_counter()
-            fn()
-            tot_t += time.perf_counter() - t0
-            tot_b += b
-        reps += 1
-    return {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle as written, one thread, repeated %dx over: %s (algorithmic read+write bytes / time)"
-                      % (reps, "; ".join(s[0] for s in samples)),
-            "seconds": round(tot_t, 2)}
+    tables = [np.zeros(1 << 20, dtype=np.int64) for _ in range(T)]
+    samples.append(("gups 2^22 upd", 16 << 22, lambda: oracle.gups(tables[0], idx, val, is_add),
+                    [(lambda tb=tb: oracle.gups(tb, idx, val, is_add)) for tb in tables], T * (16 << 22)))
+
+    def leg(par: bool, budget: float):
+        tot_b, tot_t, reps = 0, 0.0, 0
+        with ThreadPoolExecutor(max_workers=T) as ex:
+            for _, b1, fn, parts, bp in samples:     # untimed: first touch of every page
+                if par:
+                    for f in [ex.submit(p) for p in parts]:
+                        f.result()
+                else:
+                    fn()
+            t_end = time.perf_counter() + budget
+            while time.perf_counter() < t_end or reps == 0:
+                for _, b1, fn, parts, bp in samples:
+                    t0 = time.perf_counter()
+                    if par:
+                        for f in [ex.submit(p) for p in parts]:
+                            f.result()
+                    else:
+                        fn()
+                    tot_t += time.perf_counter() - t0
+                    tot_b += bp if par else b1
+                reps += 1
+        return tot_b / tot_t / 1e9, tot_t, reps
+
+    g1, t1, r1 = leg(False, seconds / 2)
+    gp, tp, rp = leg(True, seconds / 2)
+    names = "; ".join(s[0] for s in samples)
+    return {"value": round(gp, 3), "unit": "GB/s", "cores": T, "kind": "oracle",
+            "sample": "oracle as written on %d threads, repeated %dx over: %s (algorithmic read+write bytes / time); "
+                      "put split by message, broadcast by byte range, reductions by element range, alltoall and "
+                      "GUPS one instance per thread" % (T, rp, names),
+            "seconds": round(tp, 2), "host_cores": ncpu, "cpu_model": model,
+            "single_thread": {"value": round(g1, 3), "unit": "GB/s", "cores": 1, "repeats": r1,
+                              "seconds": round(t1, 2)}}
 
 
 def timed_ms(torch, fn, reps):
@@ -714,11 +785,16 @@ def run_sweep(v, torch, args):
 
 
 def run_serve(v, torch, args):
+    return serve_compare(v, torch, args.serve_requests, args.serve_wg, args.serve_chunk_kib << 10)
+
+
+def serve_compare(v, torch, n, serve_wg=PROGRESS_WG, serve_chunk=PROGRESS_CHUNK):
     """Open-loop serving: saturated burst first, then Poisson arrivals at 50%
     and 80% of the persistent kernel's saturated byte rate, on 128 PEs x
     512 MiB with a 64 GiB budget; every trace runs in four forms: the
     persistent progress kernel, windowed batches replayed from a graph or
-    launched fused, and one launch per request."""
+    launched fused, and one launch per request.  Latency percentiles drop
+    the first 5% of requests (warm-up)."""
     npes, heap = 128, 512 * MiB
     v.init(npes, heap)
     src = v.offset(v.malloc(128 * MiB))
@@ -727,7 +803,6 @@ def run_serve(v, torch, args):
         v.fill_random(v.heap_base() + p * v.heap_stride() + src, 128 * MiB, W.subseed(W.SEED_SERVE, W.TAG_HEAP + p))
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
-    n = args.serve_requests
     budget = 64 << 30
 
     def once(reqs, form="persistent"):
@@ -743,8 +818,7 @@ def run_serve(v, torch, args):
                                                          chunk_bytes=PROGRESS_CHUNK, wg_size=PROGRESS_WG)
             torch.cuda.synchronize()
             return lat, comps, stats
-        v.progress_start(nwg=0, wg_size=args.serve_wg, ring_slots=4096, chunk_bytes=args.serve_chunk_kib << 10,
-                         stream=side)
+        v.progress_start(nwg=0, wg_size=serve_wg, ring_slots=4096, chunk_bytes=serve_chunk, stream=side)
         try:
             dst, lat, comps, stats = v.serve_run(reqs, 8, region, 384 * MiB, budget)
         finally:
@@ -768,7 +842,9 @@ def run_serve(v, torch, args):
     mean_size = payload / n
     forms = ("persistent", "batched_graph", "batched_fused", "per_op")
     out = {"mode": "serve", "npes": npes, "heap_bytes_per_pe": heap, "budget_bytes": budget, "requests": n,
-           "batch_window_us": WINDOW_US, "persistent": {"saturated": summary(burst, lat, stats)}}
+           "sizes": "log-uniform 64 B - 16 MiB; kinds put/get/fetch_add uniform; 8 producer lanes",
+           "warmup_discarded": n // 20, "batch_window_us": WINDOW_US,
+           "persistent": {"saturated": summary(burst, lat, stats)}}
     for form in forms[1:]:
         lat, comps, stats = once(burst, form)
         out[form] = {"saturated": summary(burst, lat, stats)}
@@ -993,6 +1069,13 @@ def main():
     if not want and not args.no_extras:
         log("configuration sections")
         rec["configs"] = run_config_sections(v, torch)
+        g = rec["configs"]["gups_256pe"]
+        rec["amo_Mops_s"] = g["Mops_s"]
+        rec["amo_workload"] = "GUPS: 2^27 int64 entries over 256 virtual PEs, 2^28 updates (80% fetch_xor, 20% fetch_add)"
+        if "ceilings" in rec:
+            g["frac_of_atomic_ceiling_1GiB"] = round(g["Mops_s"] / 1e3 / rec["ceilings"]["atomics_G_updates_s"]["table_1GiB"], 4)
+        log("serving comparison at offered load")
+        rec["serving_offered_load"] = serve_compare(v, torch, args.serve_requests)
     line = json.dumps(rec)
     print(line, flush=True)
     if args.out:

@@ -678,12 +678,19 @@ int shmemx_stamp_launch(uint64_t *dst, void *stream);
 int shmemx_plan_info(const shmemx_plan_t *plan, uint64_t *ntasks, uint64_t *nphases, uint64_t *nlaunches);
 void shmemx_plan_destroy(shmemx_plan_t *plan);
 
-/* Autotuner: for each size class from min_bytes to max_bytes (powers of
- * two) and each candidate (scope, work-group size, chunk), time `reps`
- * fused launches of `msgs` puts between distinct PEs inside the user heap
- * range [scratch_off, scratch_off + scratch_bytes) of every PE (its
- * contents are overwritten), and keep the fastest (median time).  Writes
- * the result to *tune.  Synchronous. */
+/* Autotuner.  For each work-group size of the fused kernel (64, 128, 256,
+ * 512, 1024; sizes that cannot be resident are skipped) it first picks, per
+ * size class from min_bytes to max_bytes (powers of two), the fastest
+ * (scope, chunk) on `msgs` isolated puts of that class at that work-group
+ * size; it then scores complete tables -- that tuned table, the three
+ * uniform-scope tables and the built-in default, each at that work-group
+ * size -- on a served mix: `msgs` put/get with sizes uniform in [min_bytes,
+ * max_bytes] between random PEs, 10 * msgs contended fetch_add on 64
+ * counters, in four epochs separated by barriers.  It returns the table with
+ * the fastest mix (median of `reps` fused launches).  All traffic stays in
+ * the user heap range [scratch_off, scratch_off + scratch_bytes) of every PE,
+ * whose contents are overwritten; scratch_bytes >= 2 * max_bytes + 1024.
+ * Synchronous. */
 int shmemx_autotune(uint64_t scratch_off, uint64_t scratch_bytes, uint64_t min_bytes, uint64_t max_bytes,
                     int msgs, int reps, shmemx_tune_t *tune, void *stream);
 /* Save / load a tune table as JSON keyed by the device name (the HIP

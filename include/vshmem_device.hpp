@@ -1140,6 +1140,40 @@ struct CodecBF16 {
     __device__ __forceinline__ static void store1(uint8_t *p, A v) { *(uint16_t *)p = (uint16_t)bf16_down(v); }
 };
 
+// Elements before the first 16-byte boundary of the source when source and
+// destination lie at the same offset from a boundary (every member's copy
+// does, the member stride being a multiple of 16) and that offset is a
+// whole number of elements; ~0 when the vector path does not apply.
+template <int ES>
+__device__ __forceinline__ uint64_t vec_head(const uint8_t *s0, const uint8_t *d0, uint64_t pstride, uint64_t nelem)
+{
+    const uint64_t sm = (uintptr_t)s0 & 15, dm = (uintptr_t)d0 & 15;
+    if (sm != dm || (pstride & 15) || (sm % ES)) return ~0ull;
+    const uint64_t head = ((16 - sm) & 15) / ES;
+    return head < nelem ? head : nelem;
+}
+
+// Single-element reduce-to-all of elements [0, lo) and [hi, nelem): one lane
+// per element over every worker of the collective.
+template <class CODEC, class OP>
+__device__ __forceinline__ void reduce_singles(int P, uint64_t pstride, const uint8_t *s0, uint8_t *d0, uint64_t nelem,
+                                               uint64_t lo, uint64_t hi, const Workers &W)
+{
+    using A = typename CODEC::A;
+    const uint64_t nsingle = lo + (nelem - hi);
+    for (uint64_t q = (uint64_t)W.w * blockDim.x + threadIdx.x; q < nsingle; q += (uint64_t)W.n * blockDim.x) {
+        const uint64_t k = q < lo ? q : hi + (q - lo);
+        TreeAcc<A, 1, OP> acc;
+        for (int p = 0; p < P; ++p) {
+            A x[1] = {CODEC::load1(s0 + (uint64_t)p * pstride + k * CODEC::ES)};
+            acc.push((uint32_t)p, x);
+        }
+        A r[1];
+        acc.result((uint32_t)P, r);
+        for (int p = 0; p < P; ++p) CODEC::store1(d0 + (uint64_t)p * pstride + k * CODEC::ES, r[0]);
+    }
+}
+
 // Every member's dest[k] <- TREE over members of src[k], for k < nelem.
 // Each lane owns 16-byte vectors of the range: it loads the vector from
 // every member (kRedBatch loads in flight), folds them in member order and
@@ -1158,9 +1192,15 @@ __device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dtea
     const uint64_t pstride = member_stride(ctx, team);
     const uint8_t *s0 = member0(ctx, team, src);
     uint8_t *d0 = member0(ctx, team, dest);
-    const uint64_t nbytes = nelem * CODEC::ES;
-    const bool vec = (((uintptr_t)s0 | (uintptr_t)d0 | pstride) & 15) == 0;
-    const uint64_t nvec = vec ? nbytes / 16 : 0;
+    // Vector part: from the first 16-byte boundary of the source when source
+    // and destination share their offset from it (a head of single
+    // elements before); otherwise everything is single elements.
+    const uint64_t head = vec_head<CODEC::ES>(s0, d0, pstride, nelem);
+    const bool vec = head != ~0ull;
+    const uint64_t h = vec ? head : 0;
+    const uint64_t nvec = vec ? (nelem - h) * CODEC::ES / 16 : 0;
+    const uint8_t *sv = s0 + h * CODEC::ES;
+    uint8_t *dv = d0 + h * CODEC::ES;
     // Vectors per task: the chunk, or an even share per worker when that is
     // smaller, so a small reduction still spreads over every work-group
     // (each element's order over the members does not depend on who runs it).
@@ -1171,7 +1211,7 @@ __device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dtea
         const uint64_t v1 = min(nvec, (t + 1) * vpt);
         for (uint64_t i = t * vpt + threadIdx.x; i < v1; i += blockDim.x) {
             TreeAcc<A, E, OP> acc;
-            const uint8_t *sp = s0 + i * 16;
+            const uint8_t *sp = sv + i * 16;
             for (int p0 = 0; p0 < P; p0 += kRedBatch) {
                 v4u raw[kRedBatch];
 #pragma unroll
@@ -1189,24 +1229,108 @@ __device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dtea
             A r[E];
             acc.result((uint32_t)P, r);
             const v4u out = CODEC::pack(r);
-            uint8_t *dp = d0 + i * 16;
+            uint8_t *dp = dv + i * 16;
             for (int p = 0; p < P; ++p, dp += pstride) st<NT>((v4u *)dp, out);
         }
     }
-    // Elements past the vector part (or all of them when unaligned).
-    const uint64_t e0 = nvec * 16 / CODEC::ES;
-    for (uint64_t k = e0 + (uint64_t)W.w * blockDim.x + threadIdx.x; k < nelem; k += (uint64_t)W.n * blockDim.x) {
-        TreeAcc<A, 1, OP> acc;
-        for (int p = 0; p < P; ++p) {
-            A x[1] = {CODEC::load1(s0 + (uint64_t)p * pstride + k * CODEC::ES)};
-            acc.push((uint32_t)p, x);
-        }
-        A r[1];
-        acc.result((uint32_t)P, r);
-        for (int p = 0; p < P; ++p) CODEC::store1(d0 + (uint64_t)p * pstride + k * CODEC::ES, r[0]);
-    }
+    reduce_singles<CODEC, OP>(P, pstride, s0, d0, nelem, h, h + nvec * 16 / CODEC::ES, W);
     shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
     return 0;
+}
+
+// Reduce-to-all with the team's members split over the work-group's
+// wavefronts.  Member block b is members [8b, 8b + 8) (the last may be
+// shorter).  TREE over all members equals TREE over the blocks' TREE
+// results: TREE's first three levels pair elements only inside aligned
+// blocks of eight, and a block's last element is carried exactly when it
+// is the list's last.  Per step, wavefront w folds block b of one tile of
+// 64 vectors (one vector per lane, the block's up to 8 loads in flight),
+// leaves the block result in LDS, and after one work-group barrier every
+// wavefront of the tile folds the tile's block results in block order and
+// stores the packed result to its own block's members.  A work-group of
+// `waves` wavefronts serves teams of up to 8 * waves members and works on
+// waves / m tiles per step (m = number of blocks); its tasks are `chunk`
+// bytes of every member, walked tile by tile.  The LDS block results
+// are double-buffered, so one barrier per step suffices.  Every thread of
+// the work-group calls it; blockDim.x is a multiple of 64, at most
+// 64 * kRedWaveMax.
+constexpr int kRedWaveMax = 8;
+
+template <class CODEC, class OP, bool NT>
+__device__ __forceinline__ void reduce_waves(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
+                                             const void *src, uint64_t nelem, int rank, int nwgs, uint64_t chunk)
+{
+    using A = typename CODEC::A;
+    constexpr int E = CODEC::E;
+    __shared__ A part[2][kRedWaveMax][E][64];
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
+    const Workers W = team_workers(ctx, team, rank, nwgs);
+    const int P = team.size;
+    const uint32_t waves = blockDim.x / 64, w = threadIdx.x / 64, lane = __lane_id();
+    const uint32_t m = (uint32_t)(P + 7) / 8;          // member blocks
+    const uint32_t G = waves / m;                      // tiles per step
+    const uint32_t j = w / m, b = w - j * m;           // this wavefront's tile slot and block
+    const int p0 = 8 * (int)b, p1 = min(p0 + 8, P);
+    const uint64_t pstride = member_stride(ctx, team);
+    const uint8_t *s0 = member0(ctx, team, src);
+    uint8_t *d0 = member0(ctx, team, dest);
+    const uint64_t head = vec_head<CODEC::ES>(s0, d0, pstride, nelem);
+    const bool vec = head != ~0ull;
+    const uint64_t h = vec ? head : 0;
+    const uint64_t nvec = vec ? (nelem - h) * CODEC::ES / 16 : 0;
+    const uint8_t *sv = s0 + h * CODEC::ES;
+    uint8_t *dv = d0 + h * CODEC::ES;
+    // Tasks of `chunk` bytes per member (whole tiles of 64 vectors), dealt to
+    // the workers round robin; a worker walks its task's tiles in order.
+    const uint64_t ntile = (nvec + 63) / 64;
+    const uint64_t tpt = chunk >= 1024 ? chunk / 1024 : 1;
+    const uint64_t ntask = (ntile + tpt - 1) / tpt;
+    int buf = 0;
+    for (uint64_t task = W.w; task < ntask; task += W.n)
+    for (uint64_t t0 = task * tpt; t0 < (task + 1) * tpt && t0 < ntile; t0 += G) {
+        const uint64_t i = (t0 + j) * 64 + lane;
+        const bool mine = j < G && t0 + j < (task + 1) * tpt && i < nvec;
+        if (mine) {
+            const uint8_t *sp = sv + i * 16 + (uint64_t)p0 * pstride;
+            v4u raw[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (p0 + u < p1) raw[u] = ld<NT>((const v4u *)(sp + (uint64_t)u * pstride));
+            TreeAcc<A, E, OP, 4> acc;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (p0 + u < p1) {
+                    A x[E];
+                    CODEC::unpack(raw[u], x);
+                    acc.push((uint32_t)u, x);
+                }
+            }
+            A r[E];
+            acc.result((uint32_t)(p1 - p0), r);
+#pragma unroll
+            for (int e = 0; e < E; ++e) part[buf][w][e][lane] = r[e];
+        }
+        __syncthreads();
+        if (mine) {
+            TreeAcc<A, E, OP, 4> acc;
+            for (uint32_t bb = 0; bb < m; ++bb) {
+                A x[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) x[e] = part[buf][j * m + bb][e][lane];
+                acc.push(bb, x);
+            }
+            A r[E];
+            acc.result(m, r);
+            const v4u out = CODEC::pack(r);
+            uint8_t *dp = dv + i * 16 + (uint64_t)p0 * pstride;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (p0 + u < p1) st<NT>((v4u *)(dp + (uint64_t)u * pstride), out);
+        }
+        buf ^= 1;
+    }
+    reduce_singles<CODEC, OP>(P, pstride, s0, d0, nelem, h, h + nvec * 16 / CODEC::ES, W);
+    shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
 }
 
 } // namespace vshmem_detail

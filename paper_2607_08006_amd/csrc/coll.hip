@@ -71,6 +71,13 @@ __global__ void __launch_bounds__(256) k_reduce(Geo g)
     (void)vshmem_detail::reduce<CODEC, OP, NT>(a.ctx, g.team, a.dst, a.src, g.n, a.rank, g.wgs_per_pe, g.chunk);
 }
 
+template <class CODEC, class OP, bool NT>
+__global__ void __launch_bounds__(64 * vshmem_detail::kRedWaveMax) k_reduce_waves(Geo g)
+{
+    const Caller a = caller(g);
+    vshmem_detail::reduce_waves<CODEC, OP, NT>(a.ctx, g.team, a.dst, a.src, g.n, a.rank, g.wgs_per_pe, g.chunk);
+}
+
 // ------------------------------------------------------------- launching
 // Bytes a member writes per automatically added work-group: below this a
 // second work-group per member costs more in barrier arrivals than it saves
@@ -209,12 +216,21 @@ int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const
     int rc = (dtype < SHMEMX_DT_INT64 || dtype > SHMEMX_DT_BF16 || op < SHMEMX_RED_SUM || op > SHMEMX_RED_MAX)
                  ? SHMEMX_ERR_ARG
                  : SHMEMX_OK;
+    // Work-groups of up to 256 threads: one lane folds every member
+    // (k_reduce).  Larger ones (up to 512): the members are split over the
+    // wavefronts (k_reduce_waves), for teams of at most 8 members per
+    // wavefront.  On MI355X the two measured the same at their best shapes
+    // (the split form needs two work-groups per CU to get there), so the
+    // default stays with the first.
     shmemx_launch_t L0 = launch ? *launch : shmemx_launch_t{0, 256, 16ull << 10, SHMEMX_LAUNCH_NONTEMPORAL, 0};
     if (L0.wg_size == 0) L0.wg_size = 256;
     if (!rc) rc = make_geo(team, dest, src, nreduce * es, nreduce * es, &L0, 256, g, L);
     // In place is allowed; partial overlap is not.
     if (!rc && g.dst_off != g.src_off && overlap(g.dst_off, nreduce * es, g.src_off, nreduce * es)) rc = SHMEMX_ERR_ARG;
-    if (!rc && (L.wg_size > 256 || L.chunk_bytes == 0)) rc = SHMEMX_ERR_ARG;
+    const bool waves = L.wg_size > 256;
+    if (!rc && (L.wg_size > 64 * vshmem_detail::kRedWaveMax || L.chunk_bytes == 0 ||
+                (waves && g.team.size > 8 * (L.wg_size / 64))))
+        rc = SHMEMX_ERR_ARG;
     if (!rc && g.team.size > 511) rc = SHMEMX_ERR_UNSUPPORTED;   // TreeAcc holds 9 levels
     if (rc) {
         set_last_error(rc);
@@ -225,12 +241,17 @@ int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const
     hipStream_t s = (hipStream_t)stream;
     const bool nt = (L.flags & SHMEMX_LAUNCH_NONTEMPORAL) != 0;
     const uint64_t wb = nreduce * es;
-#define VSHMEM_RED(CODEC)                                                                                   \
+#define VSHMEM_RED_K(K, CODEC)                                                                              \
     if (op == SHMEMX_RED_SUM)                                                                               \
-        return nt ? launch_team_kernel(k_reduce<CODEC, OpSum, true>, g, L.wg_size, s, aw, wb)               \
-                  : launch_team_kernel(k_reduce<CODEC, OpSum, false>, g, L.wg_size, s, aw, wb);             \
-    return nt ? launch_team_kernel(k_reduce<CODEC, OpMax, true>, g, L.wg_size, s, aw, wb)                   \
-              : launch_team_kernel(k_reduce<CODEC, OpMax, false>, g, L.wg_size, s, aw, wb);
+        return nt ? launch_team_kernel(K<CODEC, OpSum, true>, g, L.wg_size, s, aw, wb)                      \
+                  : launch_team_kernel(K<CODEC, OpSum, false>, g, L.wg_size, s, aw, wb);                    \
+    return nt ? launch_team_kernel(K<CODEC, OpMax, true>, g, L.wg_size, s, aw, wb)                          \
+              : launch_team_kernel(K<CODEC, OpMax, false>, g, L.wg_size, s, aw, wb);
+#define VSHMEM_RED(CODEC)                                                                                   \
+    if (waves) {                                                                                            \
+        VSHMEM_RED_K(k_reduce_waves, CODEC)                                                                 \
+    }                                                                                                       \
+    VSHMEM_RED_K(k_reduce, CODEC)
     if (dtype == SHMEMX_DT_INT64) {
         VSHMEM_RED(CodecI64)
     } else if (dtype == SHMEMX_DT_FP32) {
@@ -239,6 +260,7 @@ int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const
         VSHMEM_RED(CodecBF16)
     }
 #undef VSHMEM_RED
+#undef VSHMEM_RED_K
 }
 
 }  // extern "C"

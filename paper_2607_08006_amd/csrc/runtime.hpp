@@ -8,36 +8,18 @@
 #include <mutex>
 #include <vector>
 
+#include "hostalloc.hpp"
 #include "vshmem.h"
 #include "vshmem_device.hpp"
 
 namespace vshmem {
 
 constexpr uint64_t kSliceAlign = 2ull << 20;      // PE slices are 2 MiB aligned
-constexpr uint64_t kMinAlign = 256;               // default allocation alignment
 
 struct Team {
     bool live = false;
     int start = 0, stride = 1, size = 0;
     int slot = 0;
-};
-
-// First-fit allocator over [0, capacity) with a coalescing free list.  The
-// same call sequence always yields the same offsets: allocation is
-// symmetric by construction because one offset names the object on every PE.
-class SymAllocator {
-  public:
-    void reset(uint64_t capacity);
-    // Returns the offset or UINT64_MAX.
-    uint64_t alloc(uint64_t size, uint64_t align);
-    bool free(uint64_t off);
-    uint64_t used() const { return used_; }
-    uint64_t capacity() const { return cap_; }
-
-  private:
-    std::map<uint64_t, uint64_t> free_;   // offset -> length
-    std::map<uint64_t, uint64_t> live_;   // offset -> length
-    uint64_t cap_ = 0, used_ = 0;
 };
 
 struct State {

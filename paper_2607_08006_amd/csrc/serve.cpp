@@ -20,57 +20,6 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-// Admission is sharded so that producers for different PEs do not
-// serialise: the budget is one atomic counter, each PE's destination
-// allocator has its own lock, and counter pools are atomic bump pointers.
-// Producers that cannot be admitted sleep on a generation count that every
-// completion advances.  (One global lock here capped a burst at about
-// 0.7 M requests/s.)
-struct PeRegion {
-    std::mutex mu;
-    SymAllocator dst;                  // offsets relative to the region
-    std::atomic<uint64_t> ctr_next{0}; // bump pointer of the PE's counter pool
-};
-
-struct Admission {
-    std::vector<std::unique_ptr<PeRegion>> pe;
-    uint64_t ctr_base = 0, ctr_bytes = 0, budget = 0;
-    std::atomic<uint64_t> reserved{0}, max_reserved{0}, waits{0}, gen{0};
-    std::atomic<int> waiting{0};
-    std::mutex wait_mu;
-    std::condition_variable cv;
-
-    // Reserve `bytes` of the budget; false when it does not fit now.
-    bool reserve(uint64_t bytes)
-    {
-        uint64_t cur = reserved.load(std::memory_order_relaxed);
-        do {
-            if (cur + bytes > budget) return false;
-        } while (!reserved.compare_exchange_weak(cur, cur + bytes, std::memory_order_relaxed));
-        uint64_t m = max_reserved.load(std::memory_order_relaxed);
-        while (cur + bytes > m && !max_reserved.compare_exchange_weak(m, cur + bytes, std::memory_order_relaxed)) {
-        }
-        return true;
-    }
-    // Wake producers waiting for budget or space (after a release).
-    void released()
-    {
-        {
-            std::lock_guard<std::mutex> lk(wait_mu);
-            gen.fetch_add(1, std::memory_order_release);
-        }
-        if (waiting.load(std::memory_order_acquire) > 0) cv.notify_all();
-    }
-    // Sleep until a completion after generation `seen` (bounded).
-    void wait_after(uint64_t seen)
-    {
-        std::unique_lock<std::mutex> lk(wait_mu);
-        waiting.fetch_add(1, std::memory_order_acq_rel);
-        cv.wait_for(lk, std::chrono::milliseconds(5), [&] { return gen.load(std::memory_order_acquire) != seen; });
-        waiting.fetch_sub(1, std::memory_order_acq_rel);
-    }
-};
-
 struct Slot {
     std::atomic<int> state{0};          // 0 waiting, 1 submitted, 2 done
     uint64_t ticket = 0;

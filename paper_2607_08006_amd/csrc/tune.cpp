@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "exec.hpp"
 #include "runtime.hpp"
 
 using namespace vshmem;
@@ -85,6 +86,101 @@ std::string device_key()
     return std::string(prop.gcnArchName);
 }
 
+// Host-side SplitMix64 for the tuner's synthetic mix (input generation).
+uint64_t mix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// The served mix the candidates are scored on: `msgs` put/get (half each)
+// with sizes uniform in [min_bytes, max_bytes] between random PEs, each
+// message with a destination range of its own (no conflicts), 10 * msgs
+// fetch_add(+1) on 64 counters at the end of the range (contended: the
+// ratio of the 4-PE mixed program, 10^4 atomics to 1000 put/get), in four
+// epochs separated by barriers of every PE.
+std::vector<shmemx_desc_t> make_mix(uint64_t off, uint64_t span, uint64_t min_b, uint64_t max_b, int msgs)
+{
+    const int npes = st().npes;
+    const uint64_t ctr = off + span - 64 * 8;
+    const uint64_t half = (span - 64 * 8) / 2;
+    std::vector<shmemx_desc_t> d;
+    uint64_t used = 0;
+    const int epochs = 4;
+    uint64_t k = 0;
+    for (int e = 0; e < epochs; ++e) {
+        for (int m = e * msgs / epochs; m < (e + 1) * msgs / epochs; ++m) {
+            const uint64_t n = min_b + mix64(0x7E57, k++) % (max_b - min_b + 1);
+            const uint64_t n16 = (n + 15) & ~15ull;
+            if (used + n16 > half) break;
+            shmemx_desc_t x{};
+            x.op = (mix64(0x7E57, k++) & 1) ? SHMEMX_OP_PUT : SHMEMX_OP_GET;
+            x.scope = SHMEMX_SCOPE_AUTO;
+            x.issuer_pe = (int32_t)(mix64(0x7E57, k++) % (uint64_t)npes);
+            x.target_pe = (int32_t)(mix64(0x7E57, k++) % (uint64_t)npes);
+            x.result_idx = SHMEMX_NO_RESULT;
+            x.src = off + used;
+            x.dst = off + half + used;
+            x.nbytes = n;
+            used += n16;
+            d.push_back(x);
+        }
+        for (int a = e * 10 * msgs / epochs; a < (e + 1) * 10 * msgs / epochs; ++a) {
+            shmemx_desc_t x{};
+            x.op = SHMEMX_OP_AMO_FETCH_ADD;
+            x.scope = SHMEMX_SCOPE_AUTO;
+            x.issuer_pe = (int32_t)(mix64(0x7E58, k++) % (uint64_t)npes);
+            const uint64_t c = mix64(0x7E58, k++) % 64;
+            x.target_pe = (int32_t)(c % (uint64_t)npes);
+            x.result_idx = SHMEMX_NO_RESULT;
+            x.src = ctr + 8 * c;
+            x.nbytes = 8;
+            x.value = 1;
+            d.push_back(x);
+        }
+        for (int p = 0; p < npes; ++p) {
+            shmemx_desc_t x{};
+            x.op = SHMEMX_OP_BARRIER_ALL;
+            x.issuer_pe = p;
+            x.target_pe = p;
+            x.result_idx = SHMEMX_NO_RESULT;
+            d.push_back(x);
+        }
+    }
+    return d;
+}
+
+// Median time (ms) of `reps` fused launches of the mix under `t`;
+// SHMEMX_ERR_UNSUPPORTED when its work-groups cannot be resident.
+int score_table(const std::vector<shmemx_desc_t> &mix, const shmemx_tune_t &t, int reps, hipStream_t s, float *ms)
+{
+    shmemx_plan_t *plan = nullptr;
+    int rc = shmemx_plan_create(mix.data(), mix.size(), &t, &plan);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    VSHMEM_HIP(hipEventCreate(&e0));
+    VSHMEM_HIP(hipEventCreate(&e1));
+    std::vector<float> ts;
+    for (int r = 0; r < reps + 1 && !rc; ++r) {
+        (void)hipEventRecord(e0, s);
+        rc = shmemx_plan_launch_fused(plan, nullptr, s);
+        (void)hipEventRecord(e1, s);
+        if (VSHMEM_HIP_FAILED(hipEventSynchronize(e1))) rc = SHMEMX_ERR_HIP;
+        float x = 0;
+        (void)hipEventElapsedTime(&x, e0, e1);
+        if (r > 0) ts.push_back(x);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    shmemx_plan_destroy(plan);
+    if (rc) return rc;
+    std::sort(ts.begin(), ts.end());
+    *ms = ts[ts.size() / 2];
+    return SHMEMX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -94,41 +190,75 @@ int shmemx_autotune(uint64_t scratch_off, uint64_t scratch_bytes, uint64_t min_b
 {
     if (int rc = check_ready()) return rc;
     if (!tune || msgs <= 0 || reps <= 0 || min_bytes == 0 || max_bytes < min_bytes ||
-        !in_user_heap(scratch_off, scratch_bytes) || scratch_bytes < 2 * max_bytes || st().npes < 2)
+        !in_user_heap(scratch_off, scratch_bytes) || scratch_bytes < 2 * max_bytes + 1024 || st().npes < 2)
         return SHMEMX_ERR_ARG;
-    shmemx_tune_default(tune);
     hipStream_t s = (hipStream_t)stream;
     const int wgs[] = {64, 128, 256, 512, 1024};
     const uint64_t chunks[] = {0, 64ull << 10, 256ull << 10, 1ull << 20};
-    for (uint64_t b = min_bytes; b <= max_bytes; b *= 2) {
-        int cls = 0;
-        while (cls + 1 < SHMEMX_TUNE_CLASSES && (2ull << cls) <= b) ++cls;
-        float best = 1e30f;
-        Cand pick{SHMEMX_SCOPE_WG, 256, 0};
-        for (int sc = SHMEMX_SCOPE_THREAD; sc <= SHMEMX_SCOPE_WG; ++sc) {
-            for (int wg : wgs) {
+    const std::vector<shmemx_desc_t> mix = make_mix(scratch_off, scratch_bytes, min_bytes, max_bytes, msgs);
+    shmemx_tune_t best;
+    shmemx_tune_default(&best);
+    float best_ms = 1e30f;
+    auto consider = [&](const shmemx_tune_t &t) -> int {
+        float ms = 0;
+        const int rc = score_table(mix, t, reps, s, &ms);
+        if (rc == SHMEMX_ERR_UNSUPPORTED) return SHMEMX_OK;   // not resident at this work-group size
+        if (rc) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+        return SHMEMX_OK;
+    };
+    for (int wg : wgs) {
+        // Per size class, the fastest (scope, chunk) at THIS work-group size
+        // on isolated puts of that class ...
+        shmemx_tune_t t;
+        shmemx_tune_default(&t);
+        t.wg_size = wg;
+        bool resident = true;
+        for (uint64_t b = min_bytes; b <= max_bytes && resident; b *= 2) {
+            const int cls = vshmem_exec::size_class(b);
+            float cls_best = 1e30f;
+            for (int sc = SHMEMX_SCOPE_THREAD; sc <= SHMEMX_SCOPE_WG; ++sc) {
                 for (uint64_t ch : chunks) {
                     if (sc != SHMEMX_SCOPE_WG && ch != 0) continue;
                     if (ch != 0 && ch >= b) continue;
-                    Cand c{sc, wg, ch};
                     float ms = 0;
-                    int rc = time_candidate(c, scratch_off, scratch_bytes, b, msgs, reps, s, &ms);
-                    if (rc == SHMEMX_ERR_UNSUPPORTED) continue;   // this work-group size cannot be resident
+                    const int rc = time_candidate(Cand{sc, wg, ch}, scratch_off, scratch_bytes, b, msgs, reps, s, &ms);
+                    if (rc == SHMEMX_ERR_UNSUPPORTED) {
+                        resident = false;
+                        break;
+                    }
                     if (rc) return rc;
-                    if (ms < best) {
-                        best = ms;
-                        pick = c;
+                    if (ms < cls_best) {
+                        cls_best = ms;
+                        t.scope[cls] = (uint8_t)sc;
+                        t.chunk[cls] = ch;
                     }
                 }
+                if (!resident) break;
             }
+            if (b > max_bytes / 2) break;
         }
-        tune->scope[cls] = (uint8_t)pick.scope;
-        tune->chunk[cls] = pick.chunk;
-        // One work-group size serves the whole fused kernel: keep the one
-        // that won the largest class.
-        tune->wg_size = pick.wg;
-        if (b > max_bytes / 2) break;
+        if (!resident) continue;
+        // ... and the whole table, with the fixed tables of this size,
+        // scored together on the mix: the work-group size is chosen with
+        // the scopes it was tuned for.
+        if (int rc = consider(t)) return rc;
+        for (int sc = SHMEMX_SCOPE_THREAD; sc <= SHMEMX_SCOPE_WG; ++sc) {
+            shmemx_tune_t u;
+            shmemx_tune_default(&u);
+            u.wg_size = wg;
+            for (int c = 0; c < SHMEMX_TUNE_CLASSES; ++c) u.scope[c] = (uint8_t)sc;
+            if (int rc = consider(u)) return rc;
+        }
+        shmemx_tune_t d;
+        shmemx_tune_default(&d);
+        d.wg_size = wg;
+        if (int rc = consider(d)) return rc;
     }
+    *tune = best;
     return SHMEMX_OK;
 }
 

@@ -146,7 +146,9 @@ def test_reductions_bit_exact(dt, rop):
                 init = np.zeros((npes, region), dtype=np.uint8)
                 init[:, so:so + nreduce * es] = _red_inputs(dt, npes, nreduce, 1000 * npes + nreduce)
                 for L in (dict(wgs_per_pe=2, wg_size=256, chunk_bytes=4096), dict(wgs_per_pe=1, wg_size=64),
-                          dict(wgs_per_pe=3, wg_size=128, chunk_bytes=16384, flags=v.LAUNCH_NONTEMPORAL)):
+                          dict(wgs_per_pe=3, wg_size=128, chunk_bytes=16384, flags=v.LAUNCH_NONTEMPORAL),
+                          dict(wgs_per_pe=1, wg_size=512, chunk_bytes=2048),            # members over wavefronts
+                          dict(wgs_per_pe=2, wg_size=384, chunk_bytes=65536, flags=v.LAUNCH_NONTEMPORAL)):
                     upload(init)
                     v.reduce(dt, rop, dst, src, nreduce, launch=v.launch_cfg(**L))
                     got = download(region)
@@ -264,9 +266,15 @@ def test_reduction_edge_values_bit_exact(npes, dt):
         for shift in (0, es):
             init = np.zeros((npes, region), dtype=np.uint8)
             init[:, so + shift:so + shift + K * es] = np.ascontiguousarray(cols).view(np.uint8).reshape(npes, K * es)
-            for rop in (oracle.RO_SUM, oracle.RO_MAX):
+            # the default launch (one lane folds every member) and, for teams
+            # of up to 64, the members split over 8 wavefronts
+            cases = [(oracle.RO_SUM, None), (oracle.RO_MAX, None)]
+            if npes <= 64:
+                cases += [(oracle.RO_SUM, v.launch_cfg(wg_size=512, flags=v.LAUNCH_NONTEMPORAL)),
+                          (oracle.RO_MAX, v.launch_cfg(wg_size=512, wgs_per_pe=2))]
+            for rop, launch in cases:
                 upload(init)
-                v.reduce(dt, rop, dst + shift, src + shift, K)
+                v.reduce(dt, rop, dst + shift, src + shift, K, launch=launch)
                 got = download(region)
                 ref = init.copy()
                 oracle.reduce(ref, dt, rop, do + shift, so + shift, K)
@@ -275,5 +283,5 @@ def test_reduction_edge_values_bit_exact(npes, dt):
                 for p in (0, npes // 2, npes - 1):
                     assert np.array_equal(got[p, lo:hi], got[0, lo:hi])
                 g, r = got[0, lo:hi].copy(), ref[0, lo:hi].copy()
-                assert _same_results(g, r, dt), (npes, dt, rop, shift)
+                assert _same_results(g, r, dt), (npes, dt, rop, shift, launch is None)
         assert_no_device_errors()
