@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="also run one plain copy of this size (counter scaling reference)")
+    ap.add_argument("--hbm-probe-mib", type=int, default=0,
+                    help="also run each HBM probe kind once on buffers of this size (counter passes)")
     ap.add_argument("--out", default="", help="also write the JSON line to this file")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the step: the full put/get sweep (8 B - 64 MiB, 3 scopes, 2 patterns)")
@@ -355,7 +357,7 @@ def summarize_profiles(prof_dir: str, probe_mib: int) -> None:
                  "-- python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras")
     pmc_cmd = ("rocprofv3 --pmc {ctr} -d " + rel + "/pmc_{ctr} -o pmc --output-format csv -- python3 bench.py "
                "--rows " + ",".join(PMC_ROWS) + " --steps 2 --warmup 1 "
-               f"--no-cpu-baseline --probe-copy-mib {probe_mib}")
+               f"--no-cpu-baseline --probe-copy-mib {probe_mib} --hbm-probe-mib {probe_mib}")
     stats = _csv_rows(os.path.join(prof_dir, "trace", "**", "*kernel_stats.csv"))
     if stats:
         stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
@@ -387,7 +389,15 @@ def summarize_profiles(prof_dir: str, probe_mib: int) -> None:
                       "write_kib_per_launch": round(avg[("WRITE_SIZE", k)], 1),
                       "fetch_bytes": int(kib * 1024 * f_scale), "write_bytes": int(avg[("WRITE_SIZE", k)] * 1024 * w_scale),
                       "launches": len(per[(ctr, k)]), "source_digest": kernel_digest(k)}
-    out = {"probe": {"bytes_read": probe, "bytes_written": probe,
+    hbm = {}
+    for k, reads, writes in (("k_probe_copy_gridstride", probe, probe), ("k_probe_copy_tiles", probe, probe),
+                             ("k_probe_read", probe, 0), ("k_probe_write", 0, probe)):
+        if ("FETCH_SIZE", k) in avg and ("WRITE_SIZE", k) in avg:
+            hbm[k] = {"algorithmic_read": reads, "algorithmic_write": writes,
+                      "fetch_bytes": int(avg[("FETCH_SIZE", k)] * 1024 * f_scale),
+                      "write_bytes": int(avg[("WRITE_SIZE", k)] * 1024 * w_scale)}
+    out = {"hbm_probes": hbm,
+           "probe": {"bytes_read": probe, "bytes_written": probe,
                      "fetch_kib": round(avg[("FETCH_SIZE", "k_probe_copy")], 1),
                      "write_kib": round(avg[("WRITE_SIZE", "k_probe_copy")], 1),
                      "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)},
@@ -426,6 +436,7 @@ def measure_ceilings(v, torch, L: Layout, npes: int):
     b = torch.empty(n, dtype=torch.uint8, device="cuda")
     ms = timed(lambda: v.probe_copy(b, a, n))
     out["copy_GB_s"] = round(2 * n / (ms * 1e-3) / 1e9, 1)
+    out["hbm_probes_GB_s"] = hbm_probe_rates(v, torch, a, b, n, timed)
     del a, b
     acc = torch.zeros(1, dtype=torch.int64, device="cuda")
     nupd = 1 << 26
@@ -449,6 +460,23 @@ def measure_ceilings(v, torch, L: Layout, npes: int):
         ns = rtt.cpu().numpy().astype(np.float64) / hz * 1e9 / 2
         lat[tag] = {"p50": round(percentile(ns, 50), 1), "p99": round(percentile(ns, 99), 1)}
     out["pingpong_one_way_ns"] = lat
+    return out
+
+
+def hbm_probe_rates(v, torch, a, b, n, timed):
+    """HBM rates of the probe kernels on n-byte buffers: three copy schedules
+    (read + write bytes), a read-only and a write-only stream, and the copy
+    rate those two imply when a copy's reads and writes take turns on the
+    memory (2 / (1/read + 1/write))."""
+    acc = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, kind, moved in (("copy_chunked", v.PROBE_COPY_CHUNKED, 2 * n),
+                              ("copy_gridstride", v.PROBE_COPY_GRIDSTRIDE, 2 * n),
+                              ("copy_tiles", v.PROBE_COPY_TILES, 2 * n),
+                              ("read_only", v.PROBE_READ, n), ("write_only", v.PROBE_WRITE, n)):
+        ms = timed(lambda: v.probe_hbm(kind, b, a, n, acc=acc))
+        out[name] = round(moved / (ms * 1e-3) / 1e9, 1)
+    out["copy_bound_from_read_and_write"] = round(2 / (1 / out["read_only"] + 1 / out["write_only"]), 1)
     return out
 
 
@@ -1058,6 +1086,16 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    if args.hbm_probe_mib:
+        n = args.hbm_probe_mib * MiB
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        acc = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for kind in (v.PROBE_COPY_GRIDSTRIDE, v.PROBE_COPY_TILES, v.PROBE_READ, v.PROBE_WRITE):
+            v.probe_hbm(kind, b, a, n, acc=acc)
+        torch.cuda.synchronize()
+        rec["hbm_probe_bytes"] = n
+        del a, b
     if args.probe_copy_mib:
         n = args.probe_copy_mib * MiB
         a = torch.empty(n, dtype=torch.uint8, device="cuda")

@@ -903,6 +903,22 @@ int shmemx_fill_typed(void *dst, uint64_t count, int dtype, uint64_t seed, uint6
  * robin) with nontemporal 16-byte loads and stores, 8 in flight per lane
  * (256 x 1024 was the fastest shape measured on MI355X). */
 int shmemx_probe_copy(void *dst, const void *src, uint64_t nbytes, int nwg, int wg_size, void *stream);
+/* HBM rate probes on DEVICE buffers of nbytes (a multiple of 16, 16-byte
+ * aligned): a copy of src to dst in 16 MiB chunks per work-group (the
+ * copy probe above), as one grid-stride sweep, or in tiles of 8 vectors per
+ * lane dealt round robin; a read-only stream of src (its words folded into
+ * the DEVICE word *acc); a write-only stream to dst.  nwg work-groups of
+ * wg_size threads.  Timing references for the copy-shaped rows: a copy
+ * reads and writes every byte, so its rate is set against the read and
+ * write rates.  Asynchronous on stream; SHMEMX_ERR_ARG for a bad kind or
+ * buffer. */
+#define SHMEMX_PROBE_COPY_CHUNKED 0
+#define SHMEMX_PROBE_COPY_GRIDSTRIDE 1
+#define SHMEMX_PROBE_COPY_TILES 2
+#define SHMEMX_PROBE_READ 3
+#define SHMEMX_PROBE_WRITE 4
+int shmemx_probe_hbm(int kind, void *dst, const void *src, uint64_t nbytes, int nwg, int wg_size, uint32_t *acc,
+                     void *stream);
 /* Agent-scope int64 fetch_add to random words of a DEVICE table of nwords
  * (a power of two): atomic-throughput probe. */
 int shmemx_probe_atomics(uint64_t *table, uint64_t nwords, uint64_t nupdates, uint64_t seed, uint64_t *acc,

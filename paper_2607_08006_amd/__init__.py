@@ -334,6 +334,14 @@ def fill_typed(dst, count: int, dtype: int, seed: int, index0: int = 0, stream=N
     _check(lib.shmemx_fill_typed(_ptr(dst), count, dtype, seed, index0, _stream(stream)), "shmemx_fill_typed")
 
 
+PROBE_COPY_CHUNKED, PROBE_COPY_GRIDSTRIDE, PROBE_COPY_TILES, PROBE_READ, PROBE_WRITE = range(5)
+
+
+def probe_hbm(kind: int, dst, src, nbytes: int, nwg: int = 256, wg_size: int = 1024, acc=None, stream=None) -> None:
+    _check(lib.shmemx_probe_hbm(kind, _ptr(dst), _ptr(src), nbytes, nwg, wg_size, _ptr(acc), _stream(stream)),
+           "shmemx_probe_hbm")
+
+
 def probe_copy(dst, src, nbytes: int, nwg: int = 256, wg_size: int = 1024, stream=None) -> None:
     _check(lib.shmemx_probe_copy(_ptr(dst), _ptr(src), nbytes, nwg, wg_size, _stream(stream)), "shmemx_probe_copy")
 

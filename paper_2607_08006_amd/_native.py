@@ -189,6 +189,7 @@ SIGNATURES = {
     "shmemx_reduce_on_stream": (i32, [C.c_int32, i32, i32, vp, vp, sz, vp]),
     "shmemx_fill_random": (i32, [vp, u64, u64, u64, vp]),
     "shmemx_fill_typed": (i32, [vp, u64, i32, u64, u64, vp]),
+    "shmemx_probe_hbm": (i32, [i32, vp, vp, u64, i32, i32, vp, vp]),
     "shmemx_probe_copy": (i32, [vp, vp, u64, i32, i32, vp]),
     "shmemx_probe_atomics": (i32, [vp, u64, u64, u64, vp, vp]),
     "shmemx_probe_xcd": (i32, [vp, i32, vp]),
