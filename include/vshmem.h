@@ -657,7 +657,9 @@ int shmemx_plan_create(const shmemx_desc_t *descs, size_t n, const shmemx_tune_t
  * the same time on different streams, provided their grids fit the device
  * together (cap them with tune->grid_wgs): work-groups of a multi-phase
  * launch wait for each other.  Launches of ONE plan must be ordered (same
- * stream, or synchronised): they share its barrier words. */
+ * stream, or synchronised): they share its barrier words.  A multi-phase
+ * plan whose grid does not fit the CUs the running progress kernel leaves
+ * free is refused with SHMEMX_ERR_BUSY (nothing is launched). */
 int shmemx_plan_launch_fused(shmemx_plan_t *plan, uint64_t *results, void *stream);
 /* One kernel launch per operation, in program order. */
 int shmemx_plan_launch_per_op(shmemx_plan_t *plan, uint64_t *results, void *stream);

@@ -322,6 +322,9 @@ int shmemx_plan_launch_fused(shmemx_plan_t *plan, uint64_t *results, void *strea
     if (int rc = check_ready()) return rc;
     if (!plan) return SHMEMX_ERR_ARG;
     if (plan->nphases == 0) return SHMEMX_OK;
+    // Work-groups of a multi-phase plan wait for each other at its barriers.
+    if (plan->nphases > 1)
+        if (int rc = check_coresident(k_plan_fused, plan->grid, plan->wg, "fused plan")) return rc;
     hipLaunchKernelGGL(k_plan_fused, dim3(plan->grid), dim3(plan->wg), 0, (hipStream_t)stream, pub(), plan->d_descs,
                        plan->d_tasks, plan->d_phase, (int)plan->nphases, results, plan->stamps, plan->d_bar);
     VSHMEM_HIP(hipGetLastError());

@@ -456,3 +456,51 @@ def test_progress_lanes_are_checked_and_recorded():
         oracle.run_program(ref, W.descs([(op, 0, 0, i, tg, W.NO_RESULT, s, d, n, 0, 0) for op, i, tg, s, d, n in reqs]))
         assert np.array_equal(download(region), ref)
         assert_no_device_errors()
+
+
+def test_waiting_kernels_beside_the_progress_kernel():
+    """Kernels whose work-groups wait for each other (team collectives,
+    barriers, multi-phase fused plans) count only the CUs the persistent
+    progress kernel leaves free: beside a kernel that holds every CU they
+    are refused with SHMEMX_ERR_BUSY before anything is launched; beside
+    one that holds a quarter of the CUs they launch on the rest and still
+    equal the oracle."""
+    npes, n = 8, 4096
+    with heap(npes, 4 << 20) as v:
+        t = torch()
+        src, dst = v.malloc(npes * n), v.malloc(npes * n)
+        so, do = v.offset(src), v.offset(dst)
+        region = do + npes * n
+        init = W.heap_fill(0xC0DE5, npes, region)
+        wl = W.small_workload(npes=npes, heap_bytes=1 << 20, n_rma=100, epoch_ops=50, n_amo=100,
+                              base_off=region, fill=False)
+        plan = v.Plan(wl.descs)
+        assert plan.info()["phases"] > 1
+        side = t.cuda.Stream()
+        upload(init)
+        v.progress_start(nwg=0, wg_size=1024, stream=side)        # one work-group on every CU
+        try:
+            for name, call in (("alltoall", lambda: v.alltoallmem(dst, src, n)),
+                               ("barrier", lambda: v.barrier(v.DEVICE_TEAM_WORLD, iters=1)),
+                               ("fused plan", lambda: plan.launch_fused())):
+                with pytest.raises(v.VshmemError) as e:
+                    call()
+                assert e.value.code == v.ERR_BUSY, name
+        finally:
+            v.progress_stop(10000)
+            side.synchronize()
+        assert np.array_equal(download(region), init)              # nothing ran
+        quarter = max(2, t.cuda.get_device_properties(0).multi_processor_count // 4)
+        v.progress_start(nwg=quarter, wg_size=1024, stream=side)
+        try:
+            v.alltoallmem(dst, src, n)
+            v.barrier(v.DEVICE_TEAM_WORLD, iters=3)
+            t.cuda.current_stream().synchronize()
+        finally:
+            v.progress_stop(10000)
+            side.synchronize()
+        ref = init.copy()
+        oracle.alltoall(ref, do, so, n)
+        assert np.array_equal(download(region), ref)
+        plan.destroy()
+        assert_no_device_errors()
