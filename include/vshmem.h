@@ -350,7 +350,8 @@ typedef struct shmemx_launch {
     int32_t reserved;
 } shmemx_launch_t;
 #define SHMEMX_LAUNCH_NONTEMPORAL 0x1  /* streaming loads/stores in copies */
-#define SHMEMX_LAUNCH_DEEP 0x2         /* 8 vectors in flight per lane instead of 4 */
+#define SHMEMX_LAUNCH_DEEP 0x2         /* copies: 8 vectors in flight per lane instead of 4;
+                                          reductions of teams below 128: two vectors per lane */
 
 /*
  * Pattern put/get (device-initiated RMA, Section 6.3): every PE p with

@@ -1175,17 +1175,23 @@ __device__ __forceinline__ void reduce_singles(int P, uint64_t pstride, const ui
 }
 
 // Every member's dest[k] <- TREE over members of src[k], for k < nelem.
-// Each lane owns 16-byte vectors of the range: it loads the vector from
-// every member (kRedBatch loads in flight), folds them in member order and
-// writes the result to every member.  Returns SHMEMX_ERR_UNSUPPORTED,
-// without synchronising, for teams larger than the fold's depth allows.
-template <class CODEC, class OP, bool NT>
+// Each lane owns K 16-byte vectors of the range, blockDim.x vectors apart:
+// it loads them from every member (kRedBatch loads in flight), folds each
+// in member order and writes the results to every member.  With K > 1 a
+// wavefront's consecutive loads and stores fall K times in a row into one
+// member's page, so each address translation serves K KiB instead of 1
+// KiB: the member walk visits 2P pages per vector, more than a CU's
+// first-level translation cache holds.  LEVELS bounds the team size
+// (2^LEVELS - 1 members).  Returns SHMEMX_ERR_UNSUPPORTED, without
+// synchronising, for teams larger than that.
+template <class CODEC, class OP, bool NT, int K = 1, int LEVELS = kTreeLevels>
 __device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dteam_t &team, void *dest,
                                       const void *src, uint64_t nelem, int rank, int nwgs, uint64_t chunk)
 {
     using A = typename CODEC::A;
     constexpr int E = CODEC::E;
-    if (team.size >= (1 << kTreeLevels)) return SHMEMX_ERR_UNSUPPORTED;
+    constexpr int B = kRedBatch / K > 0 ? kRedBatch / K : 1;   // members per load batch
+    if (team.size >= (1 << LEVELS)) return SHMEMX_ERR_UNSUPPORTED;
     shmemx_team_sync_units(ctx, team, (uint64_t)nwgs);
     const Workers W = team_workers(ctx, team, rank, nwgs);
     const int P = team.size;
@@ -1207,30 +1213,44 @@ __device__ __forceinline__ int reduce(const shmem_dctx_t &ctx, const shmemx_dtea
     const uint64_t share = (nvec + W.n - 1) / W.n;
     const uint64_t vpt = max<uint64_t>(1, min<uint64_t>(chunk / 16, share));
     const uint64_t ntask = (nvec + vpt - 1) / vpt;
+    const uint64_t bd = blockDim.x;
     for (uint64_t t = W.w; t < ntask; t += W.n) {
         const uint64_t v1 = min(nvec, (t + 1) * vpt);
-        for (uint64_t i = t * vpt + threadIdx.x; i < v1; i += blockDim.x) {
-            TreeAcc<A, E, OP> acc;
+        for (uint64_t i = t * vpt + threadIdx.x; i < v1; i += K * bd) {
+            TreeAcc<A, E, OP, LEVELS> acc[K];
             const uint8_t *sp = sv + i * 16;
-            for (int p0 = 0; p0 < P; p0 += kRedBatch) {
-                v4u raw[kRedBatch];
+            for (int p0 = 0; p0 < P; p0 += B) {
+                v4u raw[B][K];
 #pragma unroll
-                for (int u = 0; u < kRedBatch; ++u)
-                    if (p0 + u < P) raw[u] = ld<NT>((const v4u *)(sp + (uint64_t)(p0 + u) * pstride));
+                for (int u = 0; u < B; ++u)
 #pragma unroll
-                for (int u = 0; u < kRedBatch; ++u) {
+                    for (int k = 0; k < K; ++k)
+                        if (p0 + u < P && i + k * bd < v1)
+                            raw[u][k] = ld<NT>((const v4u *)(sp + k * bd * 16 + (uint64_t)(p0 + u) * pstride));
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
                     if (p0 + u < P) {
-                        A x[E];
-                        CODEC::unpack(raw[u], x);
-                        acc.push((uint32_t)(p0 + u), x);
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            A x[E];
+                            CODEC::unpack(raw[u][k], x);
+                            acc[k].push((uint32_t)(p0 + u), x);
+                        }
                     }
                 }
             }
-            A r[E];
-            acc.result((uint32_t)P, r);
-            const v4u out = CODEC::pack(r);
+            v4u out[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                A r[E];
+                acc[k].result((uint32_t)P, r);
+                out[k] = CODEC::pack(r);
+            }
             uint8_t *dp = dv + i * 16;
-            for (int p = 0; p < P; ++p, dp += pstride) st<NT>((v4u *)dp, out);
+            for (int p = 0; p < P; ++p, dp += pstride)
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (i + k * bd < v1) st<NT>((v4u *)(dp + k * bd * 16), out[k]);
         }
     }
     reduce_singles<CODEC, OP>(P, pstride, s0, d0, nelem, h, h + nvec * 16 / CODEC::ES, W);

@@ -71,6 +71,15 @@ __global__ void __launch_bounds__(256) k_reduce(Geo g)
     (void)vshmem_detail::reduce<CODEC, OP, NT>(a.ctx, g.team, a.dst, a.src, g.n, a.rank, g.wgs_per_pe, g.chunk);
 }
 
+// Two vectors per lane and a TREE stack for teams of up to 127 members.
+template <class CODEC, class OP, bool NT>
+__global__ void __launch_bounds__(256) k_reduce2(Geo g)
+{
+    const Caller a = caller(g);
+    (void)vshmem_detail::reduce<CODEC, OP, NT, 2, 7>(a.ctx, g.team, a.dst, a.src, g.n, a.rank, g.wgs_per_pe,
+                                                      g.chunk);
+}
+
 template <class CODEC, class OP, bool NT>
 __global__ void __launch_bounds__(64 * vshmem_detail::kRedWaveMax) k_reduce_waves(Geo g)
 {
@@ -228,6 +237,8 @@ int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const
     // In place is allowed; partial overlap is not.
     if (!rc && g.dst_off != g.src_off && overlap(g.dst_off, nreduce * es, g.src_off, nreduce * es)) rc = SHMEMX_ERR_ARG;
     const bool waves = L.wg_size > 256;
+    // SHMEMX_LAUNCH_DEEP: two vectors per lane (teams of up to 127 members).
+    const bool two = !waves && (L.flags & SHMEMX_LAUNCH_DEEP) && g.team.size < 128;
     if (!rc && (L.wg_size > 64 * vshmem_detail::kRedWaveMax || L.chunk_bytes == 0 ||
                 (waves && g.team.size > 8 * (L.wg_size / 64))))
         rc = SHMEMX_ERR_ARG;
@@ -250,6 +261,9 @@ int shmemx_reduce_launch(shmem_team_t team, int dtype, int op, void *dest, const
 #define VSHMEM_RED(CODEC)                                                                                   \
     if (waves) {                                                                                            \
         VSHMEM_RED_K(k_reduce_waves, CODEC)                                                                 \
+    }                                                                                                       \
+    if (two) {                                                                                              \
+        VSHMEM_RED_K(k_reduce2, CODEC)                                                                      \
     }                                                                                                       \
     VSHMEM_RED_K(k_reduce, CODEC)
     if (dtype == SHMEMX_DT_INT64) {

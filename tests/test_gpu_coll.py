@@ -148,7 +148,9 @@ def test_reductions_bit_exact(dt, rop):
                 for L in (dict(wgs_per_pe=2, wg_size=256, chunk_bytes=4096), dict(wgs_per_pe=1, wg_size=64),
                           dict(wgs_per_pe=3, wg_size=128, chunk_bytes=16384, flags=v.LAUNCH_NONTEMPORAL),
                           dict(wgs_per_pe=1, wg_size=512, chunk_bytes=2048),            # members over wavefronts
-                          dict(wgs_per_pe=2, wg_size=384, chunk_bytes=65536, flags=v.LAUNCH_NONTEMPORAL)):
+                          dict(wgs_per_pe=2, wg_size=384, chunk_bytes=65536, flags=v.LAUNCH_NONTEMPORAL),
+                          dict(wgs_per_pe=2, wg_size=128, chunk_bytes=4096, flags=v.LAUNCH_DEEP),  # two vectors per lane
+                          dict(wgs_per_pe=1, wg_size=256, flags=v.LAUNCH_DEEP | v.LAUNCH_NONTEMPORAL)):
                     upload(init)
                     v.reduce(dt, rop, dst, src, nreduce, launch=v.launch_cfg(**L))
                     got = download(region)
@@ -266,12 +268,16 @@ def test_reduction_edge_values_bit_exact(npes, dt):
         for shift in (0, es):
             init = np.zeros((npes, region), dtype=np.uint8)
             init[:, so + shift:so + shift + K * es] = np.ascontiguousarray(cols).view(np.uint8).reshape(npes, K * es)
-            # the default launch (one lane folds every member) and, for teams
-            # of up to 64, the members split over 8 wavefronts
+            # the default launch (one lane folds every member), for teams of
+            # up to 64 the members split over 8 wavefronts, and for teams of
+            # up to 127 two vectors per lane
             cases = [(oracle.RO_SUM, None), (oracle.RO_MAX, None)]
             if npes <= 64:
                 cases += [(oracle.RO_SUM, v.launch_cfg(wg_size=512, flags=v.LAUNCH_NONTEMPORAL)),
                           (oracle.RO_MAX, v.launch_cfg(wg_size=512, wgs_per_pe=2))]
+            if npes < 128:
+                cases += [(oracle.RO_SUM, v.launch_cfg(flags=v.LAUNCH_DEEP | v.LAUNCH_NONTEMPORAL)),
+                          (oracle.RO_MAX, v.launch_cfg(wg_size=128, flags=v.LAUNCH_DEEP))]
             for rop, launch in cases:
                 upload(init)
                 v.reduce(dt, rop, dst + shift, src + shift, K, launch=launch)
