@@ -603,7 +603,38 @@ def run_config_sections(v, torch):
         plan.destroy()
         graph.destroy()
         small[label] = forms
+    # The same program from a descriptor table in device memory (index kernel
+    # and cursor executor), against the host-built plan, both event-timed
+    # from launch to completion on the stream.
+    nd = len(wl.descs)
+    table = torch.from_numpy(np.ascontiguousarray(wl.descs).view(np.uint8).copy()).cuda()
+    res_t = torch.zeros(nd, dtype=torch.int64, device="cuda")
+    dplan = v.Plan(wl.descs)
+    dgraph = v.Graph(table, nd, 1, results=res_t)
+
+    def ev_ms(fn, reps=8):
+        ts = []
+        for r in range(reps + 1):
+            v.heap_view()[:, :wl.heap_bytes].copy_(torch.from_numpy(wl.init).cuda())
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1) * 1e3)
+        return round(float(np.median(ts)), 2)
+
+    small_dev = {"plan_fused_us": ev_ms(lambda: dplan.launch_fused(results=res)),
+                 "table_fused_us": ev_ms(lambda: v.launch_batch(table, nd, results=res_t)),
+                 "table_graph_us": ev_ms(lambda: dgraph.launch()),
+                 "table_per_op_us": ev_ms(lambda: v.launch_per_op(table, nd, results=res_t), reps=2)}
+    dgraph.destroy()
+    dplan.destroy()
     out["small_program_4pe"] = {"ops": int(is_op.sum()), "fetch_add": n_amo, "heap": "4 PEs x 1 MiB",
+                                "device_table_event_timed": small_dev,
                                 "autotuned_scopes_log2_3_to_12": [int(tune_auto.scope[c]) for c in range(3, 13)],
                                 "autotuned_wg_size": int(tune_auto.wg_size), **small}
     v.finalize()

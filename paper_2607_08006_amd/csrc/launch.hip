@@ -2,11 +2,13 @@
 // read on the device at every launch, so a kernel (or a copy) may rewrite it
 // between launches; the host never sees its contents.
 //
-// The fused form runs two kernels on the caller's stream.  The index kernel
-// (one work-group) derives what the host plan builder derives: each
+// The fused form runs three kernels on the caller's stream and together they
+// derive what the host plan builder derives.  The classify kernel (one
+// thread per descriptor) validates each operation and resolves its scope and
+// chunking from the tune table; the index kernel (one work-group) finds each
 // operation's phase from its issuer's ordering points (barriers seen, fences
-// and quiets since the last barrier), its scope and chunking from the tune
-// table, and a counting sort of the operations by (phase, kind).  The
+// and quiets since the last barrier) and counting-sorts the operations by
+// (phase, kind).  The
 // executor then runs the phases in order; inside a phase its work-groups pop
 // tasks from an atomic cursor (work-group byte ranges first, then wavefront
 // packs, then single-lane packs) and a grid barrier separates the phases.
@@ -29,7 +31,14 @@ namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kIndexThreads = 1024;
+constexpr int kIndexWaves = kIndexThreads / 64;
+constexpr int kClassifyThreads = 256;
 constexpr int kIndexMaxPes = 4096;          // per-issuer ordering state held in LDS
+constexpr int kIndexItems = 8;              // descriptors per index thread per tile
+constexpr uint32_t kLdsEpochs = 4096;       // epochs whose counters the index kernel keeps in LDS
+constexpr uint32_t kLdsBuckets = 8192;      // buckets whose counters the index kernel keeps in LDS
+constexpr uint32_t kIndexTile = kIndexThreads * kIndexItems;
+static_assert(kIndexThreads <= (1 << 19) && kIndexMaxPes <= (1 << 12), "sync_entry packs 19 + 1 + 12 bits");
 constexpr uint64_t kMaxTable = 1ull << 26;  // descriptors per table
 
 // Control words of one workspace (written by the index kernel).
@@ -49,7 +58,7 @@ struct Ws {
     Ctl *ctl;
     uint32_t *eb;      // per op: barrier epoch (kNone: not executed)
     uint32_t *ef;      // per op: fences since the epoch began
-    uint32_t *key;     // per op: bucket = 3 * phase + kind (kNone: not executed)
+    uint32_t *key;     // per op: class word, then bucket = 3 * phase + kind (kNone: not executed)
     uint32_t *nch;     // per op: work-group tasks (0 for packed kinds)
     uint32_t *sorted;  // op indices by bucket
     uint32_t *maxf;    // per epoch: largest fence count of an op in it
@@ -163,13 +172,14 @@ __device__ __forceinline__ bool is_data_op(uint8_t op)
     return op == SHMEMX_OP_PUT || op == SHMEMX_OP_GET || op == SHMEMX_OP_PUT_SIGNAL || is_amo_op(op);
 }
 
-// Exclusive prefix sum over the work-group (blockDim.x a multiple of 64, at
-// most 1024); *total receives the sum.  Every thread calls it.
-template <typename T>
+// Exclusive prefix sum over a work-group of NW wavefronts; *total receives
+// the sum.  Every thread calls it.  The wavefront totals are read back all
+// at once (one LDS latency, not NW).
+template <int NW, typename T>
 __device__ __forceinline__ T block_scan(T x, T *total)
 {
-    __shared__ T wsum[16];
-    const uint32_t lane = __lane_id(), w = threadIdx.x / 64, nw = blockDim.x / 64;
+    __shared__ __align__(16) T wsum[NW];
+    const uint32_t lane = __lane_id(), w = threadIdx.x / 64;
     T incl = x;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -178,11 +188,14 @@ __device__ __forceinline__ T block_scan(T x, T *total)
     }
     if (lane == 63) wsum[w] = incl;
     __syncthreads();
+    T v[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) v[k] = wsum[k];
     T before = 0, all = 0;
-    for (uint32_t k = 0; k < nw; ++k) {
-        const T v = wsum[k];
-        if (k < w) before += v;
-        all += v;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        before += (uint32_t)k < w ? v[k] : 0;
+        all += v[k];
     }
     __syncthreads();
     *total = all;
@@ -200,27 +213,234 @@ __device__ __forceinline__ shmemx_desc_t load_desc(const shmemx_desc_t *p)
     return d;
 }
 
+// The fields the classify kernel reads: all but value and reserved (zero in
+// the copy).
+__device__ __forceinline__ shmemx_desc_t load_desc_head(const shmemx_desc_t *p)
+{
+    const vshmem_detail::v4u *q = (const vshmem_detail::v4u *)p;
+    const vshmem_detail::v4u w0 = q[0], w1 = q[1];
+    const uint64_t *u = (const uint64_t *)p;
+    shmemx_desc_t d;
+    memcpy(&d, &w0, 16);
+    memcpy((uint8_t *)&d + 16, &w1, 16);
+    d.nbytes = u[4];
+    d.value = 0;
+    d.cond = u[6];
+    d.reserved = 0;
+    return d;
+}
+
 __device__ __forceinline__ uint32_t ld_l2(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Index kernel: one work-group of kIndexThreads threads.
+// Wavefront-aggregated counters over R items per lane.  Consecutive
+// descriptors mostly share their (phase, kind) and their epoch, so one atomic
+// per distinct key per wavefront replaces one per descriptor: a single
+// counter hit by every descriptor of a table serialises in L2.
+
+// Picks the next key still to do: the key of the first (item, lane) in
+// `todo` order.  Every lane returns the same key.
+template <int R>
+__device__ __forceinline__ uint32_t agg_next(const uint32_t (&key)[R], const uint64_t (&todo)[R])
+{
+    uint32_t k = 0;
+    bool found = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!found && todo[r]) {
+            k = __builtin_amdgcn_readlane(key[r], __builtin_ctzll(todo[r]));
+            found = true;
+        }
+    }
+    return k;
+}
+
+// counter[key[r]] += 1 for each item with valid[r].  With RET, pos[r]
+// receives the item's slot: the counter's value before the item's own
+// increment.  When every valid item of the wavefront has one key (runs of
+// operations of one phase and kind), one atomic serves them all; otherwise
+// an LDS counter takes one atomic per item (the LDS resolves equal
+// addresses itself) and a counter in memory one per distinct key.
+template <int R, bool RET, bool LDS>
+__device__ __forceinline__ void agg_inc(uint32_t *counter, const uint32_t (&key)[R], const bool (&valid)[R],
+                                        uint32_t (&pos)[R])
+{
+    const uint32_t lane = __lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t todo[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        todo[r] = __ballot(valid[r]);
+        any |= todo[r] != 0;
+    }
+    if (!any) return;
+    uint32_t k = agg_next<R>(key, todo);
+    bool one = true;
+#pragma unroll
+    for (int r = 0; r < R; ++r) one &= __ballot(valid[r] && key[r] != k) == 0;
+    if (LDS && !one) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (valid[r]) {
+                if (RET) pos[r] = atomicAdd(counter + key[r], 1u);
+                else (void)atomicAdd(counter + key[r], 1u);
+            }
+        }
+        return;
+    }
+    for (;;) {
+        uint64_t same[R];
+        uint32_t total = 0;
+        int leader = 64;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            same[r] = __ballot(valid[r] && key[r] == k) & todo[r];
+            total += (uint32_t)__builtin_popcountll(same[r]);
+            if (leader == 64 && same[r]) leader = __builtin_ctzll(same[r]);
+        }
+        uint32_t base = 0;
+        if ((int)lane == leader) {
+            if (RET) base = atomicAdd(counter + k, total);
+            else (void)atomicAdd(counter + k, total);
+        }
+        if (RET) {
+            base = __builtin_amdgcn_readlane(base, leader);
+            uint32_t before = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if ((same[r] >> lane) & 1ull) pos[r] = base + before + (uint32_t)__builtin_popcountll(same[r] & below);
+                before += (uint32_t)__builtin_popcountll(same[r]);
+            }
+        }
+        any = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            todo[r] &= ~same[r];
+            any |= todo[r] != 0;
+        }
+        if (!any) break;
+        k = agg_next<R>(key, todo);
+    }
+}
+
+// Class word of a descriptor, written by the classify kernel: issuer in
+// bits 0-11, type in bits 12-13, kind in bits 14-15.
+constexpr uint32_t kTypeSkip = 0;      // NOP or invalid: not executed
+constexpr uint32_t kTypeFence = 1;     // fence or quiet
+constexpr uint32_t kTypeBarrier = 2;   // barrier_all
+constexpr uint32_t kTypeData = 3;      // executes
+__device__ __forceinline__ uint32_t class_word(uint32_t iss, uint32_t type, uint32_t kind)
+{
+    return iss | (type << 12) | (kind << 14);
+}
+__device__ __forceinline__ uint32_t class_type(uint32_t cw) { return (cw >> 12) & 3u; }
+__device__ __forceinline__ uint32_t class_kind(uint32_t cw) { return cw >> 14; }
+__device__ __forceinline__ uint32_t class_issuer(uint32_t cw) { return cw & 0xFFFu; }
+
+// One entry of a tile's list of ordering points: tile position, barrier
+// flag, issuer.
+__device__ __forceinline__ uint32_t sync_entry(uint32_t pos, bool barrier, uint32_t iss)
+{
+    return (pos << 13) | ((uint32_t)barrier << 12) | iss;
+}
+
+// v[r] = p[i0 + r] for i0 + r < n, else `fill`.  A whole run is read as
+// 16-byte vectors (i0 is a multiple of R and the sections are 256-byte
+// aligned).
+template <int R>
+__device__ __forceinline__ void load_run(const uint32_t *p, uint32_t i0, uint32_t n, uint32_t fill, uint32_t (&v)[R])
+{
+    if (i0 + R <= n) {
+#pragma unroll
+        for (int q = 0; q < R / 4; ++q) {
+            const vshmem_detail::v4u x = *(const vshmem_detail::v4u *)(p + i0 + 4 * q);
+            v[4 * q] = x.x;
+            v[4 * q + 1] = x.y;
+            v[4 * q + 2] = x.z;
+            v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = i0 + r < n ? p[i0 + r] : fill;
+    }
+}
+
+// p[i0 + r] = v[r] for i0 + r < n.
+template <int R>
+__device__ __forceinline__ void store_run(uint32_t *p, uint32_t i0, uint32_t n, const uint32_t (&v)[R])
+{
+    if (i0 + R <= n) {
+#pragma unroll
+        for (int q = 0; q < R / 4; ++q)
+            *(vshmem_detail::v4u *)(p + i0 + 4 * q) = vshmem_detail::v4u{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (i0 + r < n) p[i0 + r] = v[r];
+    }
+}
+
+// Classify kernel: one thread per descriptor, over the whole GPU.  It
+// validates the descriptor, resolves its scope and chunking, and writes its
+// class word (to the key section) and its work-group task count.  Invalid
+// descriptors latch SHMEMX_DEVERR_BAD_DESC and are skipped.
+__global__ void __launch_bounds__(kClassifyThreads) k_batch_classify(BatchArgs a)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const shmemx_desc_t d = load_desc_head(a.D + i);
+    const uint32_t iss = (uint32_t)d.issuer_pe;
+    const bool iss_ok = iss < (uint32_t)a.c.npes;
+    uint32_t type = kTypeSkip, kind = 0, nch = 0;
+    if (iss_ok && is_sync_op(d.op)) {
+        type = d.op == SHMEMX_OP_BARRIER_ALL ? kTypeBarrier : kTypeFence;
+    } else if (iss_ok && is_data_op(d.op) && dev_valid(a.c, d, a.n, a.results)) {
+        const shmemx_tune_t &tune = *a.tune;
+        const int sc = resolve_scope(d, tune);
+        kind = sc == SHMEMX_SCOPE_THREAD ? 2u : (sc == SHMEMX_SCOPE_WAVE ? 1u : 0u);
+        if (kind == 0) {
+            const uint64_t ch = resolve_chunk(d, sc, tune);
+            const uint64_t k = d.nbytes ? (d.nbytes + ch - 1) / ch : 1;
+            nch = k < 0xFFFFFFFFull ? (uint32_t)k : 0xFFFFFFFFu;
+        }
+        type = kTypeData;
+    } else if (d.op != SHMEMX_OP_NOP) {
+        // A bad code, WAIT_UNTIL, a bad issuer or an invalid operation.
+        vshmem_detail::latch_error(a.c, SHMEMX_DEVERR_BAD_DESC);
+    }
+    a.w.key[i] = class_word(iss_ok ? iss : 0, type, kind);
+    a.w.nch[i] = nch;
+}
+
+// Index kernel: one work-group of kIndexThreads threads, after the classify
+// kernel.  It walks the table in tiles of kIndexTile positions and loads a
+// tile's words before it uses them, so one work-group pays one memory
+// latency per tile and pass.  Past pass 1, thread t takes the run of
+// kIndexItems consecutive positions starting at t * kIndexItems: it reads
+// and writes its per-descriptor words as 16-byte vectors, and a tile needs
+// one work-group scan of per-thread sums.  The per-epoch and per-bucket
+// counters live in LDS while they fit (the usual case), so the counting
+// sort runs on LDS atomics.
 __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
 {
+    constexpr int R = kIndexItems;
     __shared__ uint32_t nbar[kIndexMaxPes], nfen[kIndexMaxPes];
-    __shared__ uint32_t lpos[kIndexThreads], liss[kIndexThreads];
-    __shared__ uint8_t ltyp[kIndexThreads];
-    __shared__ uint32_t s_flag, s_max, s_last, s_bad;
+    __shared__ uint32_t lsync[kIndexThreads];
+    __shared__ __align__(16) uint32_t wcount[2][kIndexWaves];
+    __shared__ uint32_t lepoch[kLdsEpochs];    // per epoch: largest fence count, then first phase
+    __shared__ uint32_t lcnt[kLdsBuckets];     // per bucket: count, then scatter cursor
+    __shared__ uint32_t s_max, s_last, s_bad;
     const uint32_t tid = threadIdx.x, nt = blockDim.x, n = a.n;
     const int npes = a.c.npes;
     const Ws &w = a.w;
-    const shmemx_tune_t &tune = *a.tune;
 
     for (int p = tid; p < npes; p += nt) nbar[p] = nfen[p] = 0;
-    for (uint32_t i = tid; i <= n; i += nt) w.maxf[i] = 0;
+    for (uint32_t b = tid; b < kLdsEpochs; b += nt) lepoch[b] = 0;
+    for (uint32_t b = kLdsEpochs + tid; b <= n; b += nt) w.maxf[b] = 0;   // epochs past the LDS ones
     if (tid == 0) {
-        s_flag = 0;
         s_max = 0;
         s_last = 0;
         s_bad = 0;
@@ -228,67 +448,120 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
     __syncthreads();
 
     // Pass 1: each operation's (barrier epoch, fences since) from its issuer's
-    // ordering points, one chunk of the table at a time.  The chunk's ordering
-    // points are listed in table order; an operation starts from its issuer's
-    // state at the chunk's start and applies the listed points before it.
-    for (uint32_t c0 = 0; c0 < n; c0 += nt) {
-        const uint32_t i = c0 + tid;
-        uint32_t op = SHMEMX_OP_NOP;
-        int iss = -1;
-        if (i < n) {
-            const uint32_t w0 = ((const uint32_t *)(a.D + i))[0];
-            op = w0 & 0xFFu;
-            iss = ((const int32_t *)(a.D + i))[1];
+    // ordering points.  A tile's class words are loaded at once (position
+    // r * kIndexThreads + t of the tile in item r of thread t), then walked
+    // one sub-tile of kIndexThreads positions at a time: an operation starts
+    // from its issuer's state at the sub-tile's start and applies the
+    // sub-tile's points that precede it, so the walk costs the sub-tile's
+    // points, not the tile's.
+    const uint32_t lane = __lane_id(), wave = tid / 64;
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    for (uint32_t t0 = 0; t0 < n; t0 += kIndexTile) {
+        uint32_t cw[R], ebr[R], efr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t i = t0 + r * nt + tid;
+            cw[r] = i < n ? w.key[i] : 0;
+            ebr[r] = kNone;
+            efr[r] = 0;
         }
-        const bool iss_ok = iss >= 0 && iss < npes;
-        const bool sync = i < n && iss_ok && is_sync_op((uint8_t)op);
-        const bool data = i < n && iss_ok && is_data_op((uint8_t)op);
-        if (i < n && op != SHMEMX_OP_NOP && !sync && !data) s_bad = 1;   // bad code, WAIT_UNTIL, or bad issuer
-        uint32_t nsync = 0;
-        const uint32_t pos = block_scan<uint32_t>(sync ? 1u : 0u, &nsync);
-        if (sync) {
-            lpos[pos] = tid;
-            liss[pos] = (uint32_t)iss;
-            ltyp[pos] = op == SHMEMX_OP_BARRIER_ALL ? 1 : 0;
-        }
-        __syncthreads();
-        if (data) {
-            uint32_t b = nbar[iss], f = nfen[iss];
-            for (uint32_t j = 0; j < nsync && lpos[j] < tid; ++j) {
-                if (liss[j] == (uint32_t)iss) {
-                    if (ltyp[j]) {
-                        ++b;
-                        f = 0;
-                    } else {
-                        ++f;
+        // Results are stored once per tile: a work-group barrier waits for
+        // every outstanding global access of the waves it joins.
+#pragma unroll 1
+        for (int r = 0; r < R && t0 + r * nt < n; ++r) {
+            uint32_t c = cw[0];
+#pragma unroll
+            for (int q = 1; q < R; ++q) c = r == q ? cw[q] : c;
+            const uint32_t ty = class_type(c), pe = class_issuer(c);
+            const bool sync = ty == kTypeFence || ty == kTypeBarrier, live = ty == kTypeData;
+            // The sub-tile's ordering points, in table order: a ballot per
+            // wavefront and a prefix over the wavefront counts.
+            const uint64_t m = __ballot(sync);
+            uint32_t *wc = wcount[r & 1];   // alternate: a fast wave may already write the next sub-tile's
+            if (lane == 0) wc[wave] = (uint32_t)__builtin_popcountll(m);
+            __syncthreads();
+            uint32_t wv[kIndexWaves], before = 0, nsync = 0;
+#pragma unroll
+            for (int k = 0; k < kIndexWaves; ++k) wv[k] = wc[k];
+#pragma unroll
+            for (int k = 0; k < kIndexWaves; ++k) {
+                before += (uint32_t)k < wave ? wv[k] : 0;
+                nsync += wv[k];
+            }
+            const uint32_t nb = before + (uint32_t)__builtin_popcountll(m & lanes_below);   // points before me
+            if (nsync) {
+                if (sync) lsync[nb] = sync_entry(tid, ty == kTypeBarrier, pe);
+                __syncthreads();
+            }
+            // An operation's state, and an ordering point's state after it;
+            // the last point of an issuer in the sub-tile carries the issuer's
+            // state into the next.
+            uint32_t eb = 0, ef = 0;
+            bool last = false;
+            if (live || sync) {
+                eb = nbar[pe];
+                ef = nfen[pe];
+                for (uint32_t j = 0; j < nb; ++j) {
+                    const uint32_t e = lsync[j];
+                    if ((e & 0xFFFu) == pe) {
+                        const bool bar = (e >> 12) & 1u;
+                        eb = bar ? eb + 1 : eb;
+                        ef = bar ? 0 : ef + 1;
+                    }
+                }
+                if (sync) {
+                    const bool bar = ty == kTypeBarrier;
+                    eb = bar ? eb + 1 : eb;
+                    ef = bar ? 0 : ef + 1;
+                    last = true;
+                    for (uint32_t j = nb + 1; j < nsync; ++j) {
+                        if ((lsync[j] & 0xFFFu) == pe) {
+                            last = false;
+                            break;
+                        }
                     }
                 }
             }
-            w.eb[i] = b;
-            w.ef[i] = f;
-            atomicMax(&w.maxf[b], f);
-        } else if (i < n) {
-            w.eb[i] = kNone;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (uint32_t j = 0; j < nsync; ++j) {
-                const uint32_t p = liss[j];
-                if (ltyp[j]) {
-                    ++nbar[p];
-                    nfen[p] = 0;
-                } else {
-                    ++nfen[p];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                ebr[q] = r == q ? (live ? eb : kNone) : ebr[q];
+                efr[q] = r == q ? ef : efr[q];
+            }
+            // Epoch maxima: one atomic per wavefront when its operations share
+            // (epoch, fences), as runs of operations between ordering points do.
+            const uint64_t lm = __ballot(live);
+            if (lm) {
+                const int fl = __builtin_ctzll(lm);
+                const uint32_t eb0 = __builtin_amdgcn_readlane(eb, fl), ef0 = __builtin_amdgcn_readlane(ef, fl);
+                const bool one = __ballot(live && (eb != eb0 || ef != ef0)) == 0;
+                if (one ? (int)lane == fl : live) {
+                    if (eb < kLdsEpochs) atomicMax(&lepoch[eb], ef);
+                    else atomicMax(&w.maxf[eb], ef);
                 }
             }
+            if (nsync) {
+                __syncthreads();   // the walks' reads of nbar, nfen and lsync precede the update
+                if (last) {
+                    nbar[pe] = eb;
+                    nfen[pe] = ef;
+                }
+                __syncthreads();
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t i = t0 + r * nt + tid;
+            if (i < n) {
+                w.eb[i] = ebr[r];
+                w.ef[i] = efr[r];
+            }
+        }
     }
     // Every PE's program holds the same number of barriers.
     for (int p = tid; p < npes; p += nt)
-        if (nbar[p] != nbar[0]) s_bad = 2;
+        if (nbar[p] != nbar[0]) s_bad = 1;
     __syncthreads();
-    if (s_bad == 2) {
+    if (s_bad) {
         if (tid == 0) {
             vshmem_detail::latch_error(a.c, SHMEMX_DEVERR_BAD_DESC);
             w.ctl->nphases = 0;
@@ -304,55 +577,65 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
     uint32_t carry = 0;
     for (uint32_t b0 = 0; b0 < nepochs; b0 += nt) {
         const uint32_t b = b0 + tid;
-        // maxf was built with atomics (performed in L2): read it the same way.
-        const uint32_t v = b < nepochs ? ld_l2(w.maxf + b) + 1 : 0;
+        // Past the LDS epochs maxf was built with atomics (performed in L2):
+        // read it the same way.
+        const uint32_t v = b < nepochs ? (b < kLdsEpochs ? lepoch[b] : ld_l2(w.maxf + b)) + 1 : 0;
         uint32_t tot = 0;
-        const uint32_t ex = block_scan<uint32_t>(v, &tot);
-        if (b < nepochs) w.base[b] = carry + ex;
+        const uint32_t ex = block_scan<kIndexWaves, uint32_t>(v, &tot);
+        if (b < nepochs) {
+            if (b < kLdsEpochs) lepoch[b] = carry + ex;
+            else w.base[b] = carry + ex;
+        }
         carry += tot;
     }
     const uint32_t nphases = carry;
     const uint32_t nbk = 3 * nphases;
-    for (uint32_t k = tid; k <= nbk; k += nt) w.cnt[k] = 0;
-    __syncthreads();
-
-    // Pass 3: validate, resolve scope and chunks, count per bucket.  Kinds in
-    // bucket order: 0 work-group byte ranges, 1 wavefront, 2 single lane.
-    for (uint32_t i = tid; i < n; i += nt) {
-        uint32_t key = kNone, nch = 0;
-        const uint32_t b = w.eb[i];
-        if (b != kNone) {
-            const shmemx_desc_t d = load_desc(a.D + i);
-            if (dev_valid(a.c, d, n, a.results)) {
-                const int sc = resolve_scope(d, tune);
-                const uint32_t kind = sc == SHMEMX_SCOPE_THREAD ? 2u : (sc == SHMEMX_SCOPE_WAVE ? 1u : 0u);
-                if (kind == 0) {
-                    const uint64_t ch = resolve_chunk(d, sc, tune);
-                    const uint64_t k = d.nbytes ? (d.nbytes + ch - 1) / ch : 1;
-                    nch = k < 0xFFFFFFFFull ? (uint32_t)k : 0xFFFFFFFFu;
-                }
-                key = 3 * (w.base[b] + w.ef[i]) + kind;
-                atomicAdd(&w.cnt[key], 1u);
-            } else {
-                s_bad = 1;
-            }
-        }
-        w.key[i] = key;
-        w.nch[i] = nch;
+    const bool lds_cnt = nbk <= kLdsBuckets;
+    if (lds_cnt) {
+        for (uint32_t k = tid; k < nbk; k += nt) lcnt[k] = 0;
+    } else {
+        for (uint32_t k = tid; k <= nbk; k += nt) w.cnt[k] = 0;
     }
     __syncthreads();
-    if (tid == 0 && s_bad) vshmem_detail::latch_error(a.c, SHMEMX_DEVERR_BAD_DESC);
+
+    // Pass 3: bucket of each operation (3 * phase + kind; kinds in bucket
+    // order: 0 work-group byte ranges, 1 wavefront, 2 single lane) and the
+    // count per bucket.
+    for (uint32_t t0 = 0; t0 < n; t0 += kIndexTile) {
+        const uint32_t i0 = t0 + tid * R;
+        uint32_t eb[R], ef[R], key[R], unused[R];
+        bool live[R];
+        load_run<R>(w.eb, i0, n, kNone, eb);
+        load_run<R>(w.ef, i0, n, 0, ef);
+        load_run<R>(w.key, i0, n, 0, key);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            live[r] = eb[r] != kNone;
+            if (live[r]) {
+                const uint32_t base = eb[r] < kLdsEpochs ? lepoch[eb[r]] : w.base[eb[r]];
+                key[r] = 3 * (base + ef[r]) + class_kind(key[r]);
+            } else {
+                key[r] = kNone;
+            }
+        }
+        if (lds_cnt) agg_inc<R, false, true>(lcnt, key, live, unused);
+        else agg_inc<R, false, false>(w.cnt, key, live, unused);
+        store_run<R>(w.key, i0, n, key);
+    }
+    __syncthreads();
 
     // Pass 4: bucket offsets; the counts become scatter cursors.
     carry = 0;
     for (uint32_t k0 = 0; k0 < nbk; k0 += nt) {
         const uint32_t k = k0 + tid;
-        const uint32_t v = k < nbk ? ld_l2(w.cnt + k) : 0;
+        // Counters in memory were built with atomics (performed in L2).
+        const uint32_t v = k < nbk ? (lds_cnt ? lcnt[k] : ld_l2(w.cnt + k)) : 0;
         uint32_t tot = 0;
-        const uint32_t ex = block_scan<uint32_t>(v, &tot);
+        const uint32_t ex = block_scan<kIndexWaves, uint32_t>(v, &tot);
         if (k < nbk) {
             w.off[k] = carry + ex;
-            w.cnt[k] = carry + ex;
+            if (lds_cnt) lcnt[k] = carry + ex;
+            else w.cnt[k] = carry + ex;
         }
         carry += tot;
     }
@@ -362,26 +645,65 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
 
     // Pass 5: scatter.  The order inside a bucket is free: its operations run
     // concurrently anyway.
-    for (uint32_t i = tid; i < n; i += nt) {
-        const uint32_t key = w.key[i];
-        if (key != kNone) {
-            const uint32_t pos = atomicAdd(&w.cnt[key], 1u);
-            w.sorted[pos] = i;
-            w.cs[pos] = w.nch[i];
+    for (uint32_t t0 = 0; t0 < n; t0 += kIndexTile) {
+        const uint32_t i0 = t0 + tid * R;
+        uint32_t key[R], nch[R], pos[R];
+        bool live[R];
+        load_run<R>(w.key, i0, n, kNone, key);
+        load_run<R>(w.nch, i0, n, 0, nch);
+#pragma unroll
+        for (int r = 0; r < R; ++r) live[r] = key[r] != kNone;
+        if (lds_cnt) agg_inc<R, true, true>(lcnt, key, live, pos);
+        else agg_inc<R, true, false>(w.cnt, key, live, pos);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (live[r]) {
+                w.sorted[pos[r]] = i0 + r;
+                w.cs[pos[r]] = nch[r];
+            }
         }
     }
     __syncthreads();
 
-    // Pass 6: work-group task offsets over the sorted order.
+    // Pass 6: work-group task offsets over the sorted order.  Each position
+    // is read and rewritten by the same thread.
     uint64_t carry64 = 0;
-    for (uint32_t s0 = 0; s0 < nvalid; s0 += nt) {
-        const uint32_t s = s0 + tid;
-        const uint64_t v = s < nvalid ? w.cs[s] : 0;
+    for (uint32_t t0 = 0; t0 < nvalid; t0 += kIndexTile) {
+        const uint32_t s0 = t0 + tid * R;
+        uint64_t v[R], mine = 0;
+        if (s0 + R <= nvalid) {
+#pragma unroll
+            for (int q = 0; q < R / 2; ++q) {
+                const vshmem_detail::v4u x = *(const vshmem_detail::v4u *)(w.cs + s0 + 2 * q);
+                v[2 * q] = (uint64_t)x.x | ((uint64_t)x.y << 32);
+                v[2 * q + 1] = (uint64_t)x.z | ((uint64_t)x.w << 32);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = s0 + r < nvalid ? w.cs[s0 + r] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) mine += v[r];
         uint64_t tot = 0;
-        const uint64_t ex = block_scan<uint64_t>(v, &tot);
-        __syncthreads();   // every read of this chunk precedes its writes
-        if (s < nvalid) w.cs[s] = carry64 + ex;
+        uint64_t run = carry64 + block_scan<kIndexWaves, uint64_t>(mine, &tot);
         carry64 += tot;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t x = v[r];
+            v[r] = run;
+            run += x;
+        }
+        if (s0 + R <= nvalid) {
+#pragma unroll
+            for (int q = 0; q < R / 2; ++q)
+                *(vshmem_detail::v4u *)(w.cs + s0 + 2 * q) =
+                    vshmem_detail::v4u{(uint32_t)v[2 * q], (uint32_t)(v[2 * q] >> 32), (uint32_t)v[2 * q + 1],
+                                       (uint32_t)(v[2 * q + 1] >> 32)};
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (s0 + r < nvalid) w.cs[s0 + r] = v[r];
+        }
     }
     if (tid == 0) w.cs[nvalid] = carry64;
     __syncthreads();
@@ -435,10 +757,12 @@ __device__ __forceinline__ uint32_t wave_search(const uint64_t *cs, uint32_t lo,
 __global__ void __launch_bounds__(1024) k_batch_exec(BatchArgs a)
 {
     __shared__ uint32_t s_t[4];
+    __shared__ shmemx_tune_t tune;
     const Ws &w = a.w;
     const uint32_t active = rfl(w.ctl->active), last = rfl(w.ctl->last);
     if (blockIdx.x >= active) return;
-    const shmemx_tune_t &tune = *a.tune;
+    if (threadIdx.x == 0) tune = *a.tune;
+    __syncthreads();
     const uint32_t bd = blockDim.x, waves = bd / 64;
     for (uint32_t ph = 0; ph < last; ++ph) {
         const uint32_t o0 = rfl(w.off[3 * ph]), o1 = rfl(w.off[3 * ph + 1]);
@@ -576,6 +900,8 @@ int launch_fused(const shmemx_desc_t *d_descs, size_t n, uint64_t *d_results, co
     a.tune = d_tune ? d_tune : st().d_tune;
     a.results = d_results;
     a.w = ws_carve(ws, cap);
+    const uint32_t ncls = (uint32_t)((n + kClassifyThreads - 1) / kClassifyThreads);
+    hipLaunchKernelGGL(k_batch_classify, dim3(ncls), dim3(kClassifyThreads), 0, stream, a);
     hipLaunchKernelGGL(k_batch_index, dim3(1), dim3(kIndexThreads), 0, stream, a);
     hipLaunchKernelGGL(k_batch_exec, dim3(grid), dim3(wg), 0, stream, a);
     VSHMEM_HIP(hipGetLastError());

@@ -202,3 +202,61 @@ def test_tune_file_at_init_and_tune_set(tmp_path, monkeypatch):
     with heap(2, 2 << 20) as v:
         t3, src = v.tune_get()
         assert src == v.TUNE_SRC_FILE_REFUSED and t3.wg_size == v.default_tune().wg_size
+
+
+def test_signal_puts_and_every_amo_kind_from_a_device_table():
+    """Signal-puts at three scopes and every atomic kind, with a fence and a
+    quiet splitting the issuer's program, through the fused, per-op and
+    graph forms over a kernel-written table: signals after their data, one
+    compare-swap winner, and every other word and fetched value as the
+    oracle's."""
+    t = torch()
+    npes = 3
+    with heap(npes, 1 << 20) as v:
+        init = W.heap_fill(77, npes, 8192)
+        init[:, 4096:4096 + 256] = 0
+        recs = [
+            (W.OP_PUT_SIGNAL, W.SCOPE_WG, W.SIGNAL_SET, 0, 1, W.NO_RESULT, 0, 1024, 500, 7, 4096),
+            (W.OP_PUT_SIGNAL, W.SCOPE_WAVE, W.SIGNAL_ADD, 1, 2, W.NO_RESULT, 64, 2048, 300, 5, 4104),
+            (W.OP_PUT_SIGNAL, W.SCOPE_THREAD, W.SIGNAL_ADD, 2, 2, W.NO_RESULT, 128, 3000, 100, 11, 4104),
+            (W.OP_AMO_COMPARE_SWAP, W.SCOPE_THREAD, 0, 0, 0, 0, 4160, 0, 8, 9, 0),
+            (W.OP_AMO_COMPARE_SWAP, W.SCOPE_THREAD, 0, 1, 0, 1, 4160, 0, 8, 10, 0),
+            (W.OP_AMO_COMPARE_SWAP, W.SCOPE_THREAD, 0, 2, 0, 2, 4160, 0, 8, 11, 0),
+            (W.OP_AMO_SET, W.SCOPE_THREAD, 0, 0, 1, W.NO_RESULT, 4168, 0, 8, 42, 0),
+            (W.OP_AMO_XOR, W.SCOPE_THREAD, 0, 1, 2, W.NO_RESULT, 4176, 0, 8, 0xF0F0, 0),
+            (W.OP_AMO_ADD, W.SCOPE_THREAD, 0, 2, 2, W.NO_RESULT, 4184, 0, 8, (1 << 64) - 3, 0),
+            (W.OP_AMO_FETCH_XOR, W.SCOPE_WAVE, 0, 1, 0, 5, 4192, 0, 8, 0x55, 0),
+            (W.OP_FENCE, 0, 0, 0, 0, W.NO_RESULT, 0, 0, 0, 0, 0),
+            (W.OP_AMO_SWAP, W.SCOPE_THREAD, 0, 0, 1, 3, 4168, 0, 8, 99, 0),
+            (W.OP_QUIET, 0, 0, 0, 0, W.NO_RESULT, 0, 0, 0, 0, 0),
+            (W.OP_AMO_FETCH, W.SCOPE_THREAD, 0, 0, 1, 4, 4168, 0, 8, 0, 0),
+        ]
+        d = W.descs(recs)
+        n = len(d)
+        table = write_table(d)
+        ref = init.copy()
+        ref_r = oracle.run_program(ref, d, nresults=6)
+        res = t.zeros(n, dtype=t.int64, device="cuda")
+        runs = {"fused": lambda: v.launch_batch(table, n, results=res),
+                "per_op": lambda: v.launch_per_op(table, n, results=res)}
+        graphs = {f"graph{f}": v.Graph(table, n, f, results=res) for f in (0, 1)}
+        runs.update({k: g.launch for k, g in graphs.items()})
+        for name, run in runs.items():
+            upload(init)
+            res.zero_()
+            t.cuda.synchronize()
+            run()
+            t.cuda.synchronize()
+            got = download(8192)
+            r = res.cpu().numpy().view(np.uint64)
+            cas = got[0, 4160:4168].view(np.uint64)[0]
+            winners = [i for i in range(3) if r[i] == 0]
+            assert len(winners) == 1 and cas == 9 + winners[0], name
+            assert all(r[i] == cas for i in range(3) if i not in winners), name
+            mask = np.ones_like(got, dtype=bool)
+            mask[0, 4160:4168] = False
+            assert np.array_equal(got[mask], ref[mask]), name
+            assert r[3] == ref_r[3] == 42 and r[4] == ref_r[4] == 99 and r[5] == ref_r[5], name
+        for g in graphs.values():
+            g.destroy()
+        assert_no_device_errors()
