@@ -730,11 +730,12 @@ int shmemx_tune_load(shmemx_tune_t *tune, const char *path);
  * PEs: the ordering state of the index kernel is per PE), SHMEMX_ERR_BUSY
  * (no CU free next to the progress kernel), SHMEMX_ERR_HIP.
  *
- * shmemx_launch_batch: the fused form.  An index kernel (one work-group)
- * derives phases, scopes, chunks and a counting sort by (phase, kind) in a
+ * shmemx_launch_batch: the fused form.  A classify kernel (one thread per
+ * descriptor) validates and resolves scopes and chunks; an index kernel (one
+ * work-group) derives phases and a counting sort by (phase, kind), both in a
  * workspace the library keeps per stream (grown on demand; growing
- * synchronises that stream); an executor of up to grid-cap work-groups pops
- * tasks from an atomic cursor per phase, with a grid barrier between phases.
+ * synchronises that stream); an executor of up to grid-cap work-groups takes
+ * each phase's tasks round robin, with a grid barrier between phases.
  * Launches on one stream are ordered; launches on different streams use
  * different workspaces and must fit the device together.
  * shmemx_launch_per_op: one kernel launch per descriptor, in table order

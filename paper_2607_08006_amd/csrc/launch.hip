@@ -8,10 +8,10 @@
 // chunking from the tune table; the index kernel (one work-group) finds each
 // operation's phase from its issuer's ordering points (barriers seen, fences
 // and quiets since the last barrier) and counting-sorts the operations by
-// (phase, kind).  The
-// executor then runs the phases in order; inside a phase its work-groups pop
-// tasks from an atomic cursor (work-group byte ranges first, then wavefront
-// packs, then single-lane packs) and a grid barrier separates the phases.
+// (phase, kind).  The executor then runs the phases in order; inside a
+// phase the tasks (work-group byte ranges first, then wavefront packs, then
+// single-lane packs) are dealt to its work-groups round robin, and a grid
+// barrier separates the phases.
 // Long-lived kernels that consume descriptor tables are the paper's Section 3
 // case for device-side batching; the stream-ordered forms of Section 4.3 are
 // what the caller's stream gives.
@@ -65,7 +65,6 @@ struct Ws {
     uint32_t *base;    // per epoch: its first phase
     uint32_t *cnt;     // per bucket: count, then scatter cursor
     uint32_t *off;     // per bucket: first sorted position (one extra entry: the end)
-    uint32_t *cursor;  // per phase: next task
     uint64_t *cs;      // per sorted position: first work-group task (one extra entry)
 };
 
@@ -88,16 +87,15 @@ void sections(uint64_t cap, uint64_t out[12])
     out[6] = (cap + 1) * 4;                   // base
     out[7] = bucket_cap(cap) * 4;             // cnt
     out[8] = bucket_cap(cap) * 4;             // off
-    out[9] = phase_cap(cap) * 4;              // cursor
-    out[10] = (cap + 1) * 8;                  // cs
-    out[11] = 0;
+    out[9] = (cap + 1) * 8;                   // cs
+    out[10] = 0;
 }
 
 uint64_t ws_bytes(uint64_t cap)
 {
     uint64_t s[12], total = kHeaderBytes;
     sections(cap, s);
-    for (int i = 0; i < 11; ++i) total += align256(s[i]);
+    for (int i = 0; i < 10; ++i) total += align256(s[i]);
     return total;
 }
 
@@ -121,10 +119,10 @@ Ws ws_carve(uint8_t *w, uint64_t cap)
     uint64_t s[12];
     sections(cap, s);
     uint8_t *p = w + kHeaderBytes;
-    void **dst[11] = {(void **)&r.eb,   (void **)&r.ef,  (void **)&r.key, (void **)&r.nch,
+    void **dst[10] = {(void **)&r.eb,     (void **)&r.ef,   (void **)&r.key,  (void **)&r.nch,
                       (void **)&r.sorted, (void **)&r.maxf, (void **)&r.base, (void **)&r.cnt,
-                      (void **)&r.off,  (void **)&r.cursor, (void **)&r.cs};
-    for (int i = 0; i < 11; ++i) {
+                      (void **)&r.off,    (void **)&r.cs};
+    for (int i = 0; i < 10; ++i) {
         *dst[i] = p;
         p += align256(s[i]);
     }
@@ -712,7 +710,6 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
     // phase with tasks.
     const uint32_t bd = a.exec_wg, waves = bd / 64;
     for (uint32_t ph = tid; ph < nphases; ph += nt) {
-        w.cursor[ph] = 0;
         const uint32_t o0 = w.off[3 * ph], o1 = w.off[3 * ph + 1], o2 = w.off[3 * ph + 2], o3 = w.off[3 * ph + 3];
         const uint64_t nt_ph = (w.cs[o1] - w.cs[o0]) + (o2 - o1 + waves - 1) / waves + (o3 - o2 + bd - 1) / bd;
         if (nt_ph) {
@@ -756,7 +753,6 @@ __device__ __forceinline__ uint32_t wave_search(const uint64_t *cs, uint32_t lo,
 // Executor: up to exec_grid work-groups; those past ctl->active leave.
 __global__ void __launch_bounds__(1024) k_batch_exec(BatchArgs a)
 {
-    __shared__ uint32_t s_t[4];
     __shared__ shmemx_tune_t tune;
     const Ws &w = a.w;
     const uint32_t active = rfl(w.ctl->active), last = rfl(w.ctl->last);
@@ -772,23 +768,12 @@ __global__ void __launch_bounds__(1024) k_batch_exec(BatchArgs a)
         const uint64_t nwv = (o2 - o1 + waves - 1) / waves;
         const uint64_t ntask = nwg + nwv + (o3 - o2 + bd - 1) / bd;
         if (ntask == 0) continue;
-        for (;;) {
-            if (threadIdx.x < 64) {
-                uint64_t t = 0;
-                if (threadIdx.x == 0) t = __hip_atomic_fetch_add(w.cursor + ph, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                t = __shfl(t, 0, 64);
-                uint32_t s = 0;
-                if (t < nwg) s = wave_search(w.cs, o0, o1, c0 + t);
-                if (threadIdx.x == 0) {
-                    s_t[0] = (uint32_t)t;
-                    s_t[1] = s;
-                }
-            }
-            __syncthreads();
-            const uint32_t t = rfl(s_t[0]), s = rfl(s_t[1]);
-            __syncthreads();   // s_t is rewritten by the next pop
-            if (t >= ntask) break;
+        // Tasks are dealt round robin (no shared cursor: a pop would cost
+        // a returning atomic and two work-group barriers per task).  Every
+        // wavefront finds a task's operation itself.
+        for (uint64_t t = blockIdx.x; t < ntask; t += active) {
             if (t < nwg) {
+                const uint32_t s = wave_search(w.cs, o0, o1, c0 + t);
                 const shmemx_desc_t d = load_desc(a.D + rfl(w.sorted[s]));
                 const int sc = resolve_scope(d, tune);
                 const uint64_t ch = resolve_chunk(d, sc, tune);
