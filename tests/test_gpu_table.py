@@ -1,7 +1,7 @@
 """GPU parity: batches over a descriptor table in DEVICE memory, written by a
 kernel (the test's own user kernel assembles it from column arrays), in the
-fused form (index kernel + cursor executor), the per-operation form and
-graphs of both, against the oracle run on the same program.  Also: graphs
+fused form (classify, index and executor kernels), the per-operation form
+and graphs of both, against the oracle run on the same program.  Also: graphs
 replay what the table holds at replay time, invalid descriptors are skipped
 and reported, plans launched together on two streams keep their barriers
 apart, and the active tune table comes from VSHMEM_TUNE_FILE."""
@@ -259,4 +259,67 @@ def test_signal_puts_and_every_amo_kind_from_a_device_table():
             assert r[3] == ref_r[3] == 42 and r[4] == ref_r[4] == 99 and r[5] == ref_r[5], name
         for g in graphs.values():
             g.destroy()
+        assert_no_device_errors()
+
+
+def _long_program(npes, epochs, fences):
+    """`epochs` barrier epochs (puts at three scopes in some of them, each
+    rewriting the same destination slots), then one epoch whose issuers
+    alternate put, fetch_add and fence `fences` times: every phase rewrites
+    the slots and bumps a counter only its issuer touches, so the final bytes
+    and every fetched value depend on the phases running in order."""
+    heap_bytes = 1 << 19
+    init = W.heap_fill(91, npes, heap_bytes)
+    recs = []
+    for e in range(epochs):
+        for p in range(npes):
+            recs.append((W.OP_BARRIER_ALL, W.SCOPE_WG, 0, p, p, W.NO_RESULT, 0, 0, 0, 0, 0))
+        if e % 97 == 0 or 4090 <= e < 4110:
+            for p in range(npes):
+                scope = (W.SCOPE_THREAD, W.SCOPE_WAVE, W.SCOPE_WG)[e % 3]
+                recs.append((W.OP_PUT, scope, 0, p, (p + 1) % npes, W.NO_RESULT, 4096 + 8 * (e % 500),
+                             65536 + 64 * p, 64, 0, 0))
+    nres = 0
+    for f in range(fences):
+        for p in range(npes):
+            q = (p + 1) % npes
+            scope = (W.SCOPE_WAVE, W.SCOPE_WG, W.SCOPE_THREAD)[(f + p) % 3]
+            recs.append((W.OP_PUT, scope, 0, p, q, W.NO_RESULT, 8192 + 8 * (f % 1000), 131072 + 64 * p, 64, 0, 0))
+            recs.append((W.OP_AMO_FETCH_ADD, W.SCOPE_THREAD, 0, p, q, nres, 262144 + 8 * p, 0, 8, 1 + f, 0))
+            recs.append((W.OP_FENCE, 0, 0, p, 0, W.NO_RESULT, 0, 0, 0, 0, 0))
+            nres += 1
+    return init, W.descs(recs), nres
+
+
+@pytest.mark.parametrize("epochs,fences", [(4200, 3000), (3, 2000)])
+def test_long_programs_past_the_index_kernels_lds_counters(epochs, fences):
+    """Tables of 14k-27k descriptors over several index tiles: 4200 epochs
+    and 7200 phases put the epoch and bucket counters in memory; 2000 fences
+    in one epoch keep them in LDS.  Fused, no-allocation, fused-graph and
+    per-op forms against the oracle, bytes and every fetched value."""
+    t = torch()
+    npes = 2
+    with heap(npes, 1 << 20) as v:
+        init, d, nres = _long_program(npes, epochs, fences)
+        n = len(d)
+        assert n <= v.launch_batch_noalloc_max()
+        table = write_table(d)
+        ref = init.copy()
+        ref_r = oracle.run_program(ref, d, nresults=nres)
+        res = t.zeros(n, dtype=t.int64, device="cuda")
+        g = v.Graph(table, n, 0, results=res)
+        runs = {"fused": lambda: v.launch_batch(table, n, results=res),
+                "noalloc": lambda: v.launch_batch_noalloc(table, n, results=res),
+                "graph0": g.launch,
+                "per_op": lambda: v.launch_per_op(table, n, results=res)}
+        for name, run in runs.items():
+            upload(init)
+            res.zero_()
+            t.cuda.synchronize()
+            run()
+            t.cuda.synchronize()
+            got = download(init.shape[1])
+            assert np.array_equal(got, ref), name
+            assert np.array_equal(res.cpu().numpy().view(np.uint64)[:nres], ref_r), name
+        g.destroy()
         assert_no_device_errors()
