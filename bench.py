@@ -952,6 +952,7 @@ def main():
     if v.initialized():
         v.finalize()
     v.init(npes, args.heap_mib * MiB)
+    heap_stride = v.heap_stride()
     L = Layout(v, args.heap_mib)
     fill_heap(v, L, npes)
     torch.cuda.synchronize()
@@ -1086,12 +1087,14 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": f"{npes} virtual PEs x {args.heap_mib} MiB symmetric heap each; one pass of every "
+        "config": {"workload": f"{npes} virtual PEs x {args.heap_mib} MiB symmetric heap each (slices "
+                               f"{heap_stride // MiB} MiB apart); one pass of every "
                                "hot-path row (put/get sweep points at thread/wavefront/work-group scope on ring and "
                                "derangement patterns, random atomics, signal ping-pong, barrier, broadcast 256 MiB, "
                                "fcollect 4 MiB, alltoall 1 MiB blocks, sum/max reduce 2^24 elements int64/fp32/bf16, "
                                "2000-op mixed batch in fused, per-op and graph forms)",
-                   "npes": npes, "heap_bytes_per_pe": args.heap_mib * MiB, "step_algorithmic_bytes": step_bytes},
+                   "npes": npes, "heap_bytes_per_pe": args.heap_mib * MiB, "heap_stride_bytes": heap_stride,
+                   "step_algorithmic_bytes": step_bytes},
         "amo_Mops_s": gups.get("Mops_s"),
         "rows": out_rows,
         "latency": latency,

@@ -197,11 +197,29 @@ typedef struct shmemx_caps {
  * (already initialised) or SHMEMX_ERR_HIP. */
 int shmemx_init_attach(void *heap, size_t heap_bytes, int npes, void *stream);
 
+/* Slice stride for PE slices with at least `bytes_per_pe` allocatable bytes
+ * (host only; needs no device and no init).  spread = 0: the smallest,
+ * bytes_per_pe plus the library's 64 KiB scratch tail, rounded up to 2 MiB.
+ * spread = 1: the stride the library uses itself, and recommends for
+ * shmemx_init_attach: when the smallest stride s lies in [2^k,
+ * 1.5 * 2^k + 2 MiB) for some 2^k >= 64 MiB (a slice at or just above a
+ * power of two, as most requested sizes are), it becomes 1.5 * 2^k + 2 MiB.  Members
+ * of a team then sit at p * stride offsets that do not pile onto the same
+ * HBM channels and banks: on MI355X a 64-member reduction over 1 GiB slices
+ * ran at 5.03-5.07 TB/s with 1026 MiB apart and 6.04-6.06 TB/s with
+ * 1538 MiB apart on each of four boxes, a broadcast at 5.63-5.66 against
+ * 6.31-6.35 TB/s; copies between two slices were not affected.  The cost is
+ * up to a third of the heap's memory.  Returns 0 when the stride would
+ * overflow 64 bits. */
+uint64_t shmemx_heap_stride_for(uint64_t bytes_per_pe, int spread);
+
 /* OpenSHMEM initialisation (Section 6.1, heaps created at init with traits
  * from the environment): VSHMEM_NPES (default 4) virtual PEs with
  * VSHMEM_SYMMETRIC_SIZE allocatable bytes each (default 64 MiB; suffixes
- * K, M, G); the library allocates the heap with hipMalloc and owns it.
- * Failure is recorded for shmemx_last_error(). */
+ * K, M, G); the library allocates the heap with hipMalloc and owns it,
+ * with slices shmemx_heap_stride_for(size, 1) apart (the smallest stride
+ * when that much does not fit).  Failure is recorded for
+ * shmemx_last_error(). */
 void shmem_init(void);
 
 /* Destroy the device context and release library resources (Section 6.2

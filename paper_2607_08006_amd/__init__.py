@@ -41,7 +41,6 @@ LAUNCH_NONTEMPORAL = 0x1
 LAUNCH_DEEP = 0x2
 NO_RESULT = 0xFFFFFFFF
 
-SCRATCH_BYTES = 64 << 10
 SLICE_ALIGN = 2 << 20
 
 
@@ -91,17 +90,28 @@ def launch_cfg(wgs_per_pe: int = 0, wg_size: int = 0, chunk_bytes: int = 0, flag
 _heap_tensor = None
 
 
-def stride_for(bytes_per_pe: int) -> int:
-    return (bytes_per_pe + SCRATCH_BYTES + SLICE_ALIGN - 1) // SLICE_ALIGN * SLICE_ALIGN
+def stride_for(bytes_per_pe: int, spread: bool = True) -> int:
+    """shmemx_heap_stride_for: the library's slice stride (spread) or the
+    smallest one."""
+    s = int(lib.shmemx_heap_stride_for(bytes_per_pe, 1 if spread else 0))
+    if s == 0:
+        raise VshmemError(ERR_ARG, "stride_for (size out of range)")
+    return s
 
 
 def init(npes: int, bytes_per_pe: int, stream=None) -> None:
     """Attach a PyTorch-allocated heap of npes slices with at least
-    bytes_per_pe allocatable bytes each (shmemx_init_attach)."""
+    bytes_per_pe allocatable bytes each (shmemx_init_attach), with slices
+    stride_for(bytes_per_pe) apart, or the smallest stride when that much
+    memory cannot be allocated."""
     global _heap_tensor
     torch = _torch()
     stride = stride_for(bytes_per_pe)
-    t = torch.empty(npes * stride + SLICE_ALIGN, dtype=torch.uint8, device="cuda")
+    try:
+        t = torch.empty(npes * stride + SLICE_ALIGN, dtype=torch.uint8, device="cuda")
+    except torch.OutOfMemoryError:
+        stride = stride_for(bytes_per_pe, spread=False)
+        t = torch.empty(npes * stride + SLICE_ALIGN, dtype=torch.uint8, device="cuda")
     base = (t.data_ptr() + SLICE_ALIGN - 1) // SLICE_ALIGN * SLICE_ALIGN
     _check(lib.shmemx_init_attach(base, npes * stride, npes, _stream(stream)), "shmemx_init_attach")
     _heap_tensor = t

@@ -69,6 +69,7 @@ P = C.POINTER
 # name: (restype, argtypes)
 SIGNATURES = {
     "shmemx_init_attach": (i32, [vp, sz, i32, vp]),
+    "shmemx_heap_stride_for": (u64, [u64, i32]),
     "shmem_init": (None, []),
     "shmem_finalize": (None, []),
     "shmem_n_pes": (i32, []),

@@ -267,6 +267,19 @@ int shmemx_init_attach(void *heap, size_t heap_bytes, int npes, void *stream)
     return finish_init(heap, heap_bytes, npes, (hipStream_t)stream);
 }
 
+uint64_t shmemx_heap_stride_for(uint64_t bytes_per_pe, int spread)
+{
+    constexpr uint64_t kMaxBytes = 1ull << 50;
+    if (bytes_per_pe > kMaxBytes) return 0;
+    const uint64_t s = (bytes_per_pe + VSHMEM_SCRATCH_BYTES + kSliceAlign - 1) & ~(kSliceAlign - 1);
+    if (!spread) return s;
+    // The largest power of two 2^k <= s.
+    if (s < (64ull << 20)) return s;
+    const uint64_t p2 = 1ull << (63 - __builtin_clzll(s));
+    const uint64_t spread_stride = p2 + p2 / 2 + kSliceAlign;
+    return s < spread_stride ? spread_stride : s;
+}
+
 void shmem_init(void)
 {
     State &s = st();
@@ -281,11 +294,16 @@ void shmem_init(void)
         set_last_error(SHMEMX_ERR_ARG);
         return;
     }
-    uint64_t stride = (user + VSHMEM_SCRATCH_BYTES + kSliceAlign - 1) & ~(kSliceAlign - 1);
+    uint64_t stride = shmemx_heap_stride_for(user, 1);
     void *heap = nullptr;
-    if (VSHMEM_HIP_FAILED(hipMalloc(&heap, stride * (uint64_t)npes))) {
-        set_last_error(SHMEMX_ERR_NOMEM);
-        return;
+    if (stride == 0 || VSHMEM_HIP_FAILED(hipMalloc(&heap, stride * (uint64_t)npes))) {
+        // The spread stride does not fit: fall back to the smallest.
+        (void)hipGetLastError();
+        stride = shmemx_heap_stride_for(user, 0);
+        if (stride == 0 || VSHMEM_HIP_FAILED(hipMalloc(&heap, stride * (uint64_t)npes))) {
+            set_last_error(SHMEMX_ERR_NOMEM);
+            return;
+        }
     }
     s.owns_heap = true;
     if (finish_init(heap, stride * (uint64_t)npes, npes, nullptr) != SHMEMX_OK) {

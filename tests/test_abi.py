@@ -171,3 +171,25 @@ def test_tune_load_refuses_other_devices_and_invalid_tables(tmp_path):
         with pytest.raises(v.VshmemError) as err:
             v.tune_load(bad)
         assert err.value.code == v.ERR_ARG, name
+
+
+def test_heap_stride_policy():
+    """shmemx_heap_stride_for needs no device: the smallest stride is the
+    request plus the 64 KiB scratch tail rounded to 2 MiB; the spread stride
+    moves slices at or just above a power of two (from 64 MiB) to 1.5 times
+    it plus 2 MiB, and leaves every other size alone."""
+    _ensure_built()
+    lib = ctypes.CDLL(LIB)
+    f = lib.shmemx_heap_stride_for
+    f.restype, f.argtypes = ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_int]
+    MiB = 1 << 20
+    for b in (1, 4 * MiB, 62 * MiB, 64 * MiB, 512 * MiB, 1024 * MiB - 65536, 1024 * MiB, 1536 * MiB, 1600 * MiB,
+              3 * 1024 * MiB, 40 * 1024 * MiB):
+        lo, sp = f(b, 0), f(b, 1)
+        assert lo >= b + 65536 and lo % (2 * MiB) == 0 and lo - (b + 65536) < 2 * MiB
+        assert sp >= lo and sp % (2 * MiB) == 0
+        p2 = 1 << (lo.bit_length() - 1)
+        want = p2 + p2 // 2 + 2 * MiB if lo >= 64 * MiB and lo < p2 + p2 // 2 + 2 * MiB else lo
+        assert sp == want, (b, lo, sp)
+    assert f(1024 * MiB, 1) == 1538 * MiB and f(512 * MiB, 1) == 770 * MiB and f(4 * MiB, 1) == 6 * MiB
+    assert f(1600 * MiB, 1) == 1602 * MiB and f(1 << 51, 1) == 0 and f(1 << 51, 0) == 0
