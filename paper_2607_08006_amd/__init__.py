@@ -99,14 +99,14 @@ def stride_for(bytes_per_pe: int, spread: bool = True) -> int:
     return s
 
 
-def init(npes: int, bytes_per_pe: int, stream=None) -> None:
+def init(npes: int, bytes_per_pe: int, stream=None, spread: bool = True) -> None:
     """Attach a PyTorch-allocated heap of npes slices with at least
     bytes_per_pe allocatable bytes each (shmemx_init_attach), with slices
     stride_for(bytes_per_pe) apart, or the smallest stride when that much
-    memory cannot be allocated."""
+    memory cannot be allocated (or when spread is False)."""
     global _heap_tensor
     torch = _torch()
-    stride = stride_for(bytes_per_pe)
+    stride = stride_for(bytes_per_pe, spread)
     try:
         t = torch.empty(npes * stride + SLICE_ALIGN, dtype=torch.uint8, device="cuda")
     except torch.OutOfMemoryError:

@@ -26,11 +26,11 @@ def torch():
 
 
 @contextlib.contextmanager
-def heap(npes: int, bytes_per_pe: int):
+def heap(npes: int, bytes_per_pe: int, spread: bool = True):
     v = vs()
     if v.initialized():
         v.finalize()
-    v.init(npes, bytes_per_pe)
+    v.init(npes, bytes_per_pe, spread=spread)
     try:
         yield v
     finally:

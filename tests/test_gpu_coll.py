@@ -291,3 +291,38 @@ def test_reduction_edge_values_bit_exact(npes, dt):
                 g, r = got[0, lo:hi].copy(), ref[0, lo:hi].copy()
                 assert _same_results(g, r, dt), (npes, dt, rop, shift, launch is None)
         assert_no_device_errors()
+
+
+@pytest.mark.parametrize("spread", [True, False])
+def test_collectives_at_both_slice_strides(spread):
+    """The same movement collectives and a reduction over 64 MiB slices with the
+    library's spread stride (98 MiB) and with the smallest one (66 MiB):
+    byte-exact against the oracle either way, so the layout is only a
+    matter of speed."""
+    npes, MiB = 8, 1 << 20
+    with heap(npes, 64 * MiB, spread=spread) as v:
+        assert v.heap_stride() == (98 if spread else 66) * MiB
+        n = 300_001
+        src, dst, red = v.malloc(4 * MiB), v.malloc(8 * MiB), v.malloc(4 * n)
+        so, do, ro = v.offset(src), v.offset(dst), v.offset(red)
+        region = ro + 4 * n
+        init = W.heap_fill(W.SEED_COLL + 64, npes, region)
+        init[:, ro:ro + 4 * n] = _red_inputs(oracle.DT_FP32, npes, n, 64)
+        steps = [
+            ("broadcast", lambda: v.broadcastmem(dst, src, 3 * MiB + 5, 3),
+             lambda ref: oracle.broadcast(ref, do, so, 3 * MiB + 5, 3)),
+            ("fcollect", lambda: v.fcollectmem(dst, src, MiB - 3),
+             lambda ref: oracle.fcollect(ref, do, so, MiB - 3)),
+            ("alltoall", lambda: v.alltoallmem(dst, src, 512 * 1024 - 16),
+             lambda ref: oracle.alltoall(ref, do, so, 512 * 1024 - 16)),
+            ("reduce", lambda: v.reduce(oracle.DT_FP32, oracle.RO_SUM, red, red, n),
+             lambda ref: oracle.reduce(ref, oracle.DT_FP32, oracle.RO_SUM, ro, ro, n)),
+        ]
+        for name, run, model in steps:
+            upload(init)
+            run()
+            got = download(region)
+            ref = init.copy()
+            model(ref)
+            assert np.array_equal(got, ref), (name, spread)
+        assert_no_device_errors()
