@@ -428,6 +428,7 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
     __shared__ uint32_t nbar[kIndexMaxPes], nfen[kIndexMaxPes];
     __shared__ uint32_t lsync[kIndexThreads];
     __shared__ __align__(16) uint32_t wcount[2][kIndexWaves];
+    __shared__ uint32_t s_tmask[3];
     __shared__ uint32_t lepoch[kLdsEpochs];    // per epoch: largest fence count, then first phase
     __shared__ uint32_t lcnt[kLdsBuckets];     // per bucket: count, then scatter cursor
     __shared__ uint32_t s_max, s_last, s_bad;
@@ -442,6 +443,7 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
         s_max = 0;
         s_last = 0;
         s_bad = 0;
+        s_tmask[0] = 0;
     }
     __syncthreads();
 
@@ -463,6 +465,22 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
             ebr[r] = kNone;
             efr[r] = 0;
         }
+        // The sub-tiles that hold ordering points (bit r), once per tile: the
+        // others need no barrier at all.  Three masks in turn: thread 0 clears
+        // the one the next tile fills, which every thread last read two tiles
+        // ago, before the previous tile's mask barrier that thread 0 has
+        // passed; the next tile fills it only after this tile's.
+        uint32_t msk = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t ty = class_type(cw[r]);
+            msk |= __ballot(ty == kTypeFence || ty == kTypeBarrier) ? 1u << r : 0u;
+        }
+        const uint32_t tix = (t0 / kIndexTile) % 3;
+        if (tid == 0) s_tmask[(tix + 1) % 3] = 0;
+        if (lane == 0 && msk) atomicOr(&s_tmask[tix], msk);
+        __syncthreads();
+        const uint32_t tmask = s_tmask[tix];
         // Results are stored once per tile: a work-group barrier waits for
         // every outstanding global access of the waves it joins.
 #pragma unroll 1
@@ -474,19 +492,22 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
             const bool sync = ty == kTypeFence || ty == kTypeBarrier, live = ty == kTypeData;
             // The sub-tile's ordering points, in table order: a ballot per
             // wavefront and a prefix over the wavefront counts.
-            const uint64_t m = __ballot(sync);
-            uint32_t *wc = wcount[r & 1];   // alternate: a fast wave may already write the next sub-tile's
-            if (lane == 0) wc[wave] = (uint32_t)__builtin_popcountll(m);
-            __syncthreads();
-            uint32_t wv[kIndexWaves], before = 0, nsync = 0;
+            uint32_t nsync = 0, nb = 0;
+            if ((tmask >> r) & 1u) {
+                const uint64_t m = __ballot(sync);
+                uint32_t *wc = wcount[r & 1];   // alternate: a fast wave may already write the next sub-tile's
+                if (lane == 0) wc[wave] = (uint32_t)__builtin_popcountll(m);
+                __syncthreads();
+                uint32_t wv[kIndexWaves], before = 0;
 #pragma unroll
-            for (int k = 0; k < kIndexWaves; ++k) wv[k] = wc[k];
+                for (int k = 0; k < kIndexWaves; ++k) wv[k] = wc[k];
 #pragma unroll
-            for (int k = 0; k < kIndexWaves; ++k) {
-                before += (uint32_t)k < wave ? wv[k] : 0;
-                nsync += wv[k];
+                for (int k = 0; k < kIndexWaves; ++k) {
+                    before += (uint32_t)k < wave ? wv[k] : 0;
+                    nsync += wv[k];
+                }
+                nb = before + (uint32_t)__builtin_popcountll(m & lanes_below);   // points before me
             }
-            const uint32_t nb = before + (uint32_t)__builtin_popcountll(m & lanes_below);   // points before me
             if (nsync) {
                 if (sync) lsync[nb] = sync_entry(tid, ty == kTypeBarrier, pe);
                 __syncthreads();
