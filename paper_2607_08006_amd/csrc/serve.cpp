@@ -300,6 +300,9 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
     adm.budget = budget_bytes;
     std::vector<Slot> slots(n);
     std::atomic<int> failed{0};
+    // One past the largest request index submitted so far: the completion
+    // thread's passes stop there instead of walking the whole trace.
+    std::atomic<size_t> submitted_end{0};
     std::atomic<size_t> ndone{0};
     // Arrival times count from `start`, a short lead after this point that
     // lets the producer and completion threads start first.
@@ -392,6 +395,9 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
             sl.ticket = t;
             sl.submitted = Clock::now();
             sl.state.store(1, std::memory_order_release);
+            size_t e = submitted_end.load(std::memory_order_relaxed);
+            while (e < i + 1 && !submitted_end.compare_exchange_weak(e, i + 1, std::memory_order_release)) {
+            }
         }
     };
 
@@ -400,7 +406,7 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
         Clock::time_point last_progress = Clock::now();
         while (ndone.load() < n && !failed.load()) {
             bool any = false;
-            size_t scan_end = n;
+            const size_t scan_end = submitted_end.load(std::memory_order_acquire);
             for (size_t i = lo; i < scan_end; ++i) {
                 Slot &sl = slots[i];
                 const int stt = sl.state.load(std::memory_order_acquire);
