@@ -39,10 +39,38 @@ class SymAllocator {
 // Producers that cannot be admitted sleep on a generation count that every
 // completion advances.  (One global lock here capped a burst at about
 // 0.7 M requests/s.)
+//
+// The completion thread does not free a finished request's range itself:
+// it queues the offset (release_later) and the next producer that
+// allocates on the PE, which holds the PE's lock anyway, frees everything
+// queued first (alloc).  Freeing on the single completion thread, under
+// locks the producers were holding, cost 230-370 ns per request and capped
+// serving at about 2 M requests/s.
 struct PeRegion {
     std::mutex mu;
     SymAllocator dst;                  // offsets relative to the region
     std::atomic<uint64_t> ctr_next{0}; // bump pointer of the PE's counter pool
+    std::mutex pend_mu;
+    std::vector<uint64_t> pending;     // finished ranges not yet returned to dst (pend_mu)
+    std::vector<uint64_t> draining;    // their storage while they are freed (mu)
+
+    void release_later(uint64_t off)
+    {
+        std::lock_guard<std::mutex> lk(pend_mu);
+        pending.push_back(off);
+    }
+    // Return the queued ranges, then allocate.  UINT64_MAX when it does not fit.
+    uint64_t alloc(uint64_t size, uint64_t align)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        draining.clear();
+        {
+            std::lock_guard<std::mutex> lp(pend_mu);
+            draining.swap(pending);   // both keep their capacity: no allocation in steady state
+        }
+        for (uint64_t off : draining) dst.free(off);
+        return dst.alloc(size, align);
+    }
 };
 
 struct Admission {

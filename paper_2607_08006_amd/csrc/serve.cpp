@@ -341,12 +341,7 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
                     if (failed.load()) return;
                     const uint64_t seen = adm.gen.load(std::memory_order_acquire);
                     if (adm.reserve(extra)) {
-                        PeRegion &pr = *adm.pe[dpe];
-                        uint64_t off;
-                        {
-                            std::lock_guard<std::mutex> lk(pr.mu);
-                            off = pr.dst.alloc(need, 256);
-                        }
+                        const uint64_t off = adm.pe[dpe]->alloc(need, 256);
                         if (off != UINT64_MAX) {
                             sl.dst = region_off + off;
                             sl.dst_pe = dpe;
@@ -423,11 +418,7 @@ int serve_common(Backend &be, const shmemx_request_t *reqs, size_t n, int lanes,
                     c.submit_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(sl.submitted - sl.arrival).count();
                     if (completions) completions[i] = c;
                     if (dst_off_out) dst_off_out[i] = sl.dst;
-                    {
-                        PeRegion &pr = *adm.pe[sl.dst_pe];
-                        std::lock_guard<std::mutex> lk(pr.mu);
-                        pr.dst.free(sl.dst - region_off);
-                    }
+                    adm.pe[sl.dst_pe]->release_later(sl.dst - region_off);
                     adm.reserved.fetch_sub(sl.bytes, std::memory_order_relaxed);
                     adm.released();
                     sl.state.store(2, std::memory_order_release);

@@ -120,11 +120,72 @@ static void admission_budget()
     CHECK(over.load() == 0 && adm.reserved.load() == 0 && adm.max_reserved.load() <= 64);
 }
 
+// Deferred frees of a PE's destination region: a range queued by the
+// completion side comes back at the next allocation, a producer and a
+// completion thread running together never hand out a range twice, and
+// everything is returned in the end.
+static void region_deferred_frees()
+{
+    vshmem::PeRegion pr;
+    pr.dst.reset(1 << 20);
+    const uint64_t a = pr.alloc(1 << 19, 256), b = pr.alloc(1 << 19, 256);
+    CHECK(a == 0 && b == (1u << 19) && pr.alloc(256, 256) == UINT64_MAX);   // full
+    pr.release_later(a);
+    CHECK(pr.dst.used() == (1u << 20));                                     // not yet returned
+    CHECK(pr.alloc(1 << 18, 256) == 0);                                     // returned, then reused
+    pr.release_later(0);
+    pr.release_later(b);
+    CHECK(pr.alloc(1 << 20, 256) == 0);                                     // both returned and coalesced
+    pr.release_later(0);
+    // One producer and one completion thread: live ranges never overlap.
+    pr.dst.reset(1 << 16);
+    std::atomic<bool> stop{false};
+    std::vector<std::atomic<int>> owner(256);
+    for (auto &o : owner) o.store(0);
+    std::atomic<int> overlaps{0};
+    std::vector<std::pair<uint64_t, uint64_t>> handoff;
+    std::mutex hm;
+    std::thread completer([&] {
+        for (;;) {
+            const bool last = stop.load();
+            std::pair<uint64_t, uint64_t> r{UINT64_MAX, 0};
+            {
+                std::lock_guard<std::mutex> lk(hm);
+                if (!handoff.empty()) {
+                    r = handoff.back();
+                    handoff.pop_back();
+                }
+            }
+            if (r.first == UINT64_MAX) {
+                if (last) break;   // the producer had stopped before this empty look
+                continue;
+            }
+            for (uint64_t k = r.first / 256; k < (r.first + r.second) / 256; ++k) owner[k].fetch_sub(1);
+            pr.release_later(r.first);
+        }
+    });
+    uint64_t s = 99;
+    for (int i = 0; i < 20000; ++i) {
+        const uint64_t len = 256 * (1 + rng(s) % 8);
+        const uint64_t off = pr.alloc(len, 256);
+        if (off == UINT64_MAX) continue;
+        for (uint64_t k = off / 256; k < (off + len) / 256; ++k)
+            if (owner[k].fetch_add(1) != 0) overlaps.fetch_add(1);
+        std::lock_guard<std::mutex> lk(hm);
+        handoff.emplace_back(off, len);
+    }
+    stop.store(true);
+    completer.join();
+    CHECK(overlaps.load() == 0);
+    CHECK(pr.alloc(1 << 16, 256) == 0);   // every range came back
+}
+
 int main()
 {
     allocator_basics();
     allocator_against_byte_map();
     admission_budget();
+    region_deferred_frees();
     if (failures) return 1;
     std::printf("ok\n");
     return 0;
