@@ -37,6 +37,7 @@ constexpr int kIndexMaxPes = 4096;          // per-issuer ordering state held in
 constexpr int kIndexItems = 8;              // descriptors per index thread per tile
 constexpr uint32_t kLdsEpochs = 4096;       // epochs whose counters the index kernel keeps in LDS
 constexpr uint32_t kLdsBuckets = 8192;      // buckets whose counters the index kernel keeps in LDS
+constexpr uint32_t kExecLdsPhases = 512;    // phases whose bounds the executor keeps in LDS
 constexpr uint32_t kIndexTile = kIndexThreads * kIndexItems;
 static_assert(kIndexThreads <= (1 << 19) && kIndexMaxPes <= (1 << 12), "sync_entry packs 19 + 1 + 12 bits");
 constexpr uint64_t kMaxTable = 1ull << 26;  // descriptors per table
@@ -775,17 +776,32 @@ __device__ __forceinline__ uint32_t wave_search(const uint64_t *cs, uint32_t lo,
 __global__ void __launch_bounds__(1024) k_batch_exec(BatchArgs a)
 {
     __shared__ shmemx_tune_t tune;
+    // Every phase's bounds (its bucket offsets and first work-group tasks),
+    // read from the workspace once for all phases: per phase they were two
+    // dependent memory round trips in every work-group.
+    __shared__ uint32_t s_off[3 * kExecLdsPhases + 1];
+    __shared__ uint64_t s_c0[kExecLdsPhases], s_c1[kExecLdsPhases];
     const Ws &w = a.w;
     const uint32_t active = rfl(w.ctl->active), last = rfl(w.ctl->last);
     if (blockIdx.x >= active) return;
     if (threadIdx.x == 0) tune = *a.tune;
+    const bool lds = last <= kExecLdsPhases;
+    if (lds) {
+        for (uint32_t k = threadIdx.x; k <= 3 * last; k += blockDim.x) s_off[k] = w.off[k];
+        __syncthreads();
+        for (uint32_t ph = threadIdx.x; ph < last; ph += blockDim.x) {
+            s_c0[ph] = w.cs[s_off[3 * ph]];
+            s_c1[ph] = w.cs[s_off[3 * ph + 1]];
+        }
+    }
     __syncthreads();
     const uint32_t bd = blockDim.x, waves = bd / 64;
     for (uint32_t ph = 0; ph < last; ++ph) {
-        const uint32_t o0 = rfl(w.off[3 * ph]), o1 = rfl(w.off[3 * ph + 1]);
-        const uint32_t o2 = rfl(w.off[3 * ph + 2]), o3 = rfl(w.off[3 * ph + 3]);
-        const uint64_t c0 = rfl64(w.cs[o0]);
-        const uint64_t nwg = rfl64(w.cs[o1]) - c0;
+        const uint32_t *off = lds ? s_off : w.off;
+        const uint32_t o0 = rfl(off[3 * ph]), o1 = rfl(off[3 * ph + 1]);
+        const uint32_t o2 = rfl(off[3 * ph + 2]), o3 = rfl(off[3 * ph + 3]);
+        const uint64_t c0 = rfl64(lds ? s_c0[ph] : w.cs[o0]);
+        const uint64_t nwg = rfl64(lds ? s_c1[ph] : w.cs[o1]) - c0;
         const uint64_t nwv = (o2 - o1 + waves - 1) / waves;
         const uint64_t ntask = nwg + nwv + (o3 - o2 + bd - 1) / bd;
         if (ntask == 0) continue;
