@@ -323,3 +323,28 @@ def test_long_programs_past_the_index_kernels_lds_counters(epochs, fences):
             assert np.array_equal(res.cpu().numpy().view(np.uint64)[:nres], ref_r), name
         g.destroy()
         assert_no_device_errors()
+
+
+def test_many_issuers_from_a_device_table():
+    """256 PEs: every epoch ends with 256 barrier descriptors (sub-tiles made
+    of ordering points of many issuers), 200 fences at seeded places, and
+    3000 fetch_add spread over every issuer; fused form against the oracle,
+    bytes and the counters' fetched values."""
+    t = torch()
+    npes = 256
+    with heap(npes, 1 << 20) as v:
+        wl, descs = _program(W.SEED_SMALL + 11, npes=npes, n_rma=1200, n_amo=3000, fences=200)
+        n = len(descs)
+        table = write_table(descs)
+        ref = wl.init.copy()
+        oracle.run_program(ref, descs, nresults=wl.n_amo)
+        res = t.zeros(n, dtype=t.int64, device="cuda")
+        for run in (lambda: v.launch_batch(table, n, results=res),
+                    lambda: v.launch_batch_noalloc(table, n, results=res)):
+            upload(wl.init)
+            res.zero_()
+            t.cuda.synchronize()
+            run()
+            t.cuda.synchronize()
+            _check(v, download(wl.heap_bytes), ref, res, wl, descs)
+        assert_no_device_errors()
