@@ -155,7 +155,7 @@ def build_rows(v, torch, L: Layout, npes: int, want):
     add("put_wave_4KiB_perm", f, b, kernel="k_rma_pattern<1,true,true,4,256>")
     f, b = rma(v.OP_GET, v.SCOPE_THREAD, ring, 64, 4, 256)
     add("get_thread_64B_ring", f, b)
-    f, b = rma(v.OP_PUT, v.SCOPE_THREAD, perm, 8, 4, 1024)
+    f, b = rma(v.OP_PUT, v.SCOPE_THREAD, perm, 8, 2, 1024)
     add("put_thread_8B_perm", f, b)
 
     # ---- atomics (a4): 2^26 random fetch_xor / fetch_add updates on a 2^27-entry table
@@ -796,11 +796,12 @@ def timed_ms(torch, fn, reps):
 
 def sweep_launch(v, scope, size):
     """Launch shape per scope from the measured shape sweeps: about one
-    work-group per CU; nontemporal copies from 4 KiB (wave) or 64 KiB (work-
+    work-group per CU (for thread-scope messages up to 32 bytes half as
+    many, of 1024 threads, which measured faster); nontemporal copies from 4 KiB (wave) or 64 KiB (work-
     group, grid) up, 8 deep for work-group and grid scope."""
     nt, deep = v.LAUNCH_NONTEMPORAL, v.LAUNCH_DEEP
     if scope == v.SCOPE_THREAD:
-        return v.launch_cfg(wgs_per_pe=4, wg_size=512)
+        return v.launch_cfg(wgs_per_pe=2, wg_size=1024) if size <= 32 else v.launch_cfg(wgs_per_pe=4, wg_size=256)
     if scope == v.SCOPE_WAVE:
         return v.launch_cfg(wgs_per_pe=4, wg_size=256, flags=nt if size >= 4096 else 0)
     if scope == v.SCOPE_WG:

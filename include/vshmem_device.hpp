@@ -220,17 +220,53 @@ __device__ __forceinline__ void copy_body(V *__restrict__ d, const V *__restrict
     for (; i < nv; i += nl) st<NT>(d + i, ld<NT>(s + i));
 }
 
-template <typename V, int U, bool NT>
+/* The n < A bytes before or after the vector body of a copy by one lane
+ * whose source and destination agree modulo A, in the widest naturally
+ * aligned pieces: an 8-byte message is one 8-byte move, not eight. */
+template <uint64_t A>
+__device__ __forceinline__ void copy_edge_lone(uint8_t *d, const uint8_t *s, uint64_t n)
+{
+    for (uint64_t o = 0; o < n;) {
+        const uint64_t a = (uintptr_t)(d + o), r = n - o;
+        if (A > 8 && (a & 7) == 0 && r >= 8) {
+            *(uint64_t *)(d + o) = *(const uint64_t *)(s + o);
+            o += 8;
+        } else if (A > 4 && (a & 3) == 0 && r >= 4) {
+            *(uint32_t *)(d + o) = *(const uint32_t *)(s + o);
+            o += 4;
+        } else if (A > 2 && (a & 1) == 0 && r >= 2) {
+            *(uint16_t *)(d + o) = *(const uint16_t *)(s + o);
+            o += 2;
+        } else {
+            d[o] = s[o];
+            o += 1;
+        }
+    }
+}
+
+/* Copy n bytes whose source and destination agree modulo sizeof(V): byte
+ * edges, then the vector body.  Cooperating lanes take one edge byte each
+ * (one instruction); a lone lane (LONE: the caller passes lane 0 of 1)
+ * takes wide pieces.  LONE is a template parameter rather than a test of
+ * nl so that the cooperative copies compile exactly as without it. */
+template <typename V, int U, bool NT, bool LONE = false>
 __device__ __forceinline__ void copy_aligned(uint8_t *__restrict__ d, const uint8_t *__restrict__ s,
                                              uint64_t n, uint64_t lane, uint64_t nl)
 {
     constexpr uint64_t A = sizeof(V);
     uint64_t head = (A - ((uintptr_t)d & (A - 1))) & (A - 1);
     if (head > n) head = n;
-    for (uint64_t i = lane; i < head; i += nl) d[i] = s[i];
+    if constexpr (LONE) copy_edge_lone<A>(d, s, head);
+    else
+        for (uint64_t i = lane; i < head; i += nl) d[i] = s[i];
     uint64_t nv = (n - head) / A;
     copy_body<V, U, NT>((V *)(d + head), (const V *)(s + head), nv, lane, nl);
-    for (uint64_t i = head + nv * A + lane; i < n; i += nl) d[i] = s[i];
+    if constexpr (LONE) {
+        const uint64_t t = head + nv * A;
+        copy_edge_lone<A>(d + t, s + t, n - t);
+    } else {
+        for (uint64_t i = head + nv * A + lane; i < n; i += nl) d[i] = s[i];
+    }
 }
 
 /* Body of a copy whose source is `sh` = 4*Q + r bytes (1 <= sh <= 15) past
@@ -303,15 +339,17 @@ constexpr uint64_t kShiftedMin = 256;
  * elements.  SHIFT is for callers that see arbitrary offsets (the device
  * API, serving, plans, host-issued moves); the put/get pattern kernels keep
  * it off so that their aligned path's registers stay as they were (the
- * grid-scope kernel is already at the 128-register limit of its launch). */
-template <int U, bool NT, bool SHIFT = false>
+ * grid-scope kernel is already at the 128-register limit of its launch).
+ * LONE marks a copy by one lane (lane 0 of 1), whose unaligned edges move
+ * in wide pieces. */
+template <int U, bool NT, bool SHIFT = false, bool LONE = false>
 __device__ __forceinline__ void copy_bytes(uint8_t *d, const uint8_t *s, uint64_t n, uint64_t lane, uint64_t nl)
 {
     uint64_t x = (uintptr_t)d ^ (uintptr_t)s;
-    if ((x & 15) == 0) copy_aligned<v4u, U, NT>(d, s, n, lane, nl);
+    if ((x & 15) == 0) copy_aligned<v4u, U, NT, LONE>(d, s, n, lane, nl);
     else if (SHIFT && n >= kShiftedMin) copy_shifted<U, NT>(d, s, n, lane, nl);
-    else if ((x & 7) == 0) copy_aligned<uint64_t, U, NT>(d, s, n, lane, nl);
-    else if ((x & 3) == 0) copy_aligned<uint32_t, U, NT>(d, s, n, lane, nl);
+    else if ((x & 7) == 0) copy_aligned<uint64_t, U, NT, LONE>(d, s, n, lane, nl);
+    else if ((x & 3) == 0) copy_aligned<uint32_t, U, NT, LONE>(d, s, n, lane, nl);
     else
         for (uint64_t i = lane; i < n; i += nl) d[i] = s[i];
 }
@@ -499,8 +537,8 @@ __device__ __forceinline__ bool wg_agree(const shmem_dctx_t &ctx, bool ok, uint6
 __device__ __forceinline__ void shmem_putmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
     if (!vshmem_detail::rma_ok(ctx, dest, src, n, pe)) return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmem_ptr(ctx, (uint8_t *)dest, pe),
-                                                         shmemx_local_ptr(ctx, (const uint8_t *)src), n, 0, 1);
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true, true>(shmem_ptr(ctx, (uint8_t *)dest, pe),
+                                                               shmemx_local_ptr(ctx, (const uint8_t *)src), n, 0, 1);
 }
 __device__ __forceinline__ void shmem_putmem_nbi(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
@@ -552,8 +590,8 @@ __device__ __forceinline__ void shmemx_putmem_grid(const shmem_dctx_t &ctx, void
 __device__ __forceinline__ void shmem_getmem(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {
     if (!vshmem_detail::rma_ok(ctx, dest, src, n, pe)) return;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(shmemx_local_ptr(ctx, (uint8_t *)dest),
-                                                         shmem_ptr(ctx, (const uint8_t *)src, pe), n, 0, 1);
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true, true>(shmemx_local_ptr(ctx, (uint8_t *)dest),
+                                                               shmem_ptr(ctx, (const uint8_t *)src, pe), n, 0, 1);
 }
 __device__ __forceinline__ void shmem_getmem_nbi(const shmem_dctx_t &ctx, void *dest, const void *src, size_t n, int pe)
 {

@@ -82,7 +82,8 @@ __device__ __forceinline__ void exec_amo(const shmemx_dctx_pub_t &c, const shmem
     if (fetch && results && d.result_idx != SHMEMX_NO_RESULT) results[d.result_idx] = old;
 }
 
-// Byte range [lo, hi) of a put/get, copied by nl lanes.
+// Byte range [lo, hi) of a put/get, copied by nl lanes (LONE: by one lane).
+template <bool LONE = false>
 __device__ __forceinline__ void exec_copy(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d, uint64_t lo, uint64_t hi,
                                           uint64_t lane, uint64_t nl)
 {
@@ -91,7 +92,7 @@ __device__ __forceinline__ void exec_copy(const shmemx_dctx_pub_t &c, const shme
     const int dpe = get ? d.issuer_pe : d.target_pe;
     const uint8_t *S = c.base + (uint64_t)spe * c.stride + d.src + lo;
     uint8_t *D = c.base + (uint64_t)dpe * c.stride + d.dst + lo;
-    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true>(D, S, hi - lo, lane, nl);
+    vshmem_detail::copy_bytes<VSHMEM_COPY_UNROLL, false, true, LONE>(D, S, hi - lo, lane, nl);
 }
 
 __device__ __forceinline__ void signal_of(const shmemx_dctx_pub_t &c, const shmemx_desc_t &d)
@@ -109,7 +110,7 @@ __device__ __forceinline__ void exec_thread(const shmemx_dctx_pub_t &c, const sh
     if (is_amo_op(d.op)) {
         exec_amo(c, d, results);
     } else if (d.op == SHMEMX_OP_PUT || d.op == SHMEMX_OP_GET || d.op == SHMEMX_OP_PUT_SIGNAL) {
-        exec_copy(c, d, 0, d.nbytes, 0, 1);
+        exec_copy<true>(c, d, 0, d.nbytes, 0, 1);
         if (d.op == SHMEMX_OP_PUT_SIGNAL) {
             vshmem_detail::release_agent();
             signal_of(c, d);

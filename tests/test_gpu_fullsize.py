@@ -22,15 +22,22 @@ def _windows(rng_seed, count, span, width):
     return (W.bounded(x, 0, (span - width) // 16) * 16).tolist()
 
 
-@pytest.mark.parametrize("op,scope,pattern,size", [
-    (W.OP_PUT, W.SCOPE_WG, "ring", 16 * MiB),
-    (W.OP_GET, W.SCOPE_WG, "perm", 16 * MiB),
-    (W.OP_PUT, W.SCOPE_GRID, "perm", 64 * MiB),
-    (W.OP_PUT, W.SCOPE_WAVE, "perm", 4096),
-    (W.OP_GET, W.SCOPE_THREAD, "ring", 64),
-    (W.OP_PUT, W.SCOPE_THREAD, "perm", 8),
+NT, DEEP = 1, 2   # launch flags: nontemporal, 8 deep
+
+
+# The benchmark's put/get rows, each in the launch shape (work-groups per PE,
+# work-group size, flags) the benchmark times it in.
+@pytest.mark.parametrize("op,scope,pattern,size,shape", [
+    (W.OP_PUT, W.SCOPE_WG, "ring", 16 * MiB, (4, 1024, NT | DEEP)),
+    (W.OP_GET, W.SCOPE_WG, "perm", 16 * MiB, (4, 1024, NT | DEEP)),
+    (W.OP_PUT, W.SCOPE_GRID, "perm", 64 * MiB, (4, 256, NT | DEEP)),
+    (W.OP_PUT, W.SCOPE_WAVE, "perm", 4096, (4, 256, NT)),
+    (W.OP_GET, W.SCOPE_THREAD, "ring", 64, (4, 256, 0)),
+    (W.OP_PUT, W.SCOPE_THREAD, "perm", 8, (2, 1024, 0)),
+    (W.OP_PUT, W.SCOPE_WG, "ring", 4096, (16, 512, 0)),
+    (W.OP_GET, W.SCOPE_THREAD, "perm", 16, (16, 256, 0)),
 ])
-def test_sweep_points_64pes_1gib(op, scope, pattern, size):
+def test_sweep_points_64pes_1gib(op, scope, pattern, size, shape):
     npes = 64
     with heap(npes, 1024 * MiB) as v:
         t = torch()
@@ -44,7 +51,8 @@ def test_sweep_points_64pes_1gib(op, scope, pattern, size):
         while k * size > 256 * MiB:
             k //= 2
         tg = W.pattern_targets(pattern, npes)
-        launch = v.launch_cfg(wgs_per_pe=16, wg_size=512 if scope != W.SCOPE_THREAD else 256)
+        assert v.LAUNCH_NONTEMPORAL == NT and v.LAUNCH_DEEP == DEEP
+        launch = v.launch_cfg(wgs_per_pe=shape[0], wg_size=shape[1], flags=shape[2])
         v.rma_pattern(op, scope, t.from_numpy(tg.astype(np.int32)).cuda(), A, B, size, k, launch=launch)
         t.cuda.synchronize()
         h = v.heap_view()

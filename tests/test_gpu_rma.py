@@ -50,6 +50,46 @@ def test_pattern_put_get_bit_exact(scope):
         assert_no_device_errors()
 
 
+def test_thread_scope_message_runs():
+    """One lane per message, more messages than lanes: the lane moves its
+    messages four at a time (16- and 8-byte elements, one or two per
+    message) and the rest one by one; other sizes and alignments take the
+    generic copy, whose edges a lone lane moves in wide pieces."""
+    npes, user = 5, 1 << 20
+    K = 300 << 10
+    with heap(npes, user) as v:
+        region = 600 << 10
+        init = W.heap_fill(0x3A7, npes, region)
+        cases = [
+            # (op, msg, nmsg, src_off, dst_off, src_step, dst_step)
+            (W.OP_PUT, 16, 4 * 64 * 3 + 17, 0, K, 16, 16),
+            (W.OP_GET, 64, 4 * 64 + 63, 64, K, 80, 80),
+            (W.OP_PUT, 48, 4 * 64 * 2 + 1, 16, K + 32, 48, 48),
+            (W.OP_GET, 8, 4 * 64 * 5 + 7, 8, K, 8, 8),
+            (W.OP_PUT, 24, 4 * 64 + 5, 8, K + 8, 24, 24),
+            (W.OP_PUT, 32, 4 * 64 + 100, 8, K, 40, 40),
+            (W.OP_PUT, 16, 4 * 64 * 2 + 9, 32, K, 0, 16),     # every message reads one source
+            (W.OP_GET, 72, 300, 0, K, 72, 72),                # above 64 bytes: generic
+            (W.OP_PUT, 12, 600, 4, K + 4, 12, 12),            # 4-byte aligned: generic, 2- and 4-byte edges
+            (W.OP_PUT, 8, 4 * 64 + 3, 4, K + 4, 8, 8),        # 8 bytes, 4-aligned: generic
+            (W.OP_PUT, 7, 500, 1, K + 3, 9, 9),               # byte path
+            (W.OP_GET, 15, 700, 1, K + 1, 16, 16),            # 1-, 2-, 4- and 8-byte head pieces
+        ]
+        shapes = [v.launch_cfg(wgs_per_pe=1, wg_size=64),
+                  v.launch_cfg(wgs_per_pe=2, wg_size=128, flags=v.LAUNCH_NONTEMPORAL | v.LAUNCH_DEEP),
+                  v.launch_cfg(wgs_per_pe=1, wg_size=1024)]
+        for li, launch in enumerate(shapes):
+            for ci, (op, msg, nmsg, so, do, ss, ds) in enumerate(cases):
+                targets = W.pattern_targets("perm" if ci % 2 else "ring", npes, seed=W.SEED_SWEEP + ci).astype(np.int32)
+                upload(init)
+                v.rma_pattern(op, W.SCOPE_THREAD, device_array(targets), so, do, msg, nmsg, ss, ds, launch=launch)
+                got = download(region)
+                ref = init.copy()
+                oracle.run_program(ref, _pattern_descs(op, targets, so, do, msg, nmsg, ss, ds))
+                assert np.array_equal(got, ref), (li, op, msg, nmsg, so, do, ss, ds)
+        assert_no_device_errors()
+
+
 def test_pattern_idle_pes_and_arg_checks():
     npes = 4
     with heap(npes, 1 << 20) as v:
