@@ -559,6 +559,25 @@ def run_config_sections(v, torch):
     tune_auto = v.autotune(v.offset(v.malloc(3 * MiB)) + MiB, 2 * MiB, 8, 4096, msgs=1024, reps=5)
     stamps = torch.zeros(len(wl.descs), dtype=torch.int64, device="cuda")
     t0 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    init_dev = torch.from_numpy(wl.init).cuda()
+
+    def ev_us(fn, reps=10):
+        """Median launch-to-completion time on the stream (HIP events), with
+        the heap restored before each launch."""
+        ts = []
+        for r in range(reps + 1):
+            v.heap_view()[:, :wl.heap_bytes].copy_(init_dev)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1) * 1e3)
+        return round(float(np.median(ts)), 2)
+
     small = {}
     for label, scope in (("thread", v.SCOPE_THREAD), ("wave", v.SCOPE_WAVE), ("wg", v.SCOPE_WG),
                          ("default_table", "default"), ("autotuned", None)):
@@ -600,6 +619,16 @@ def run_config_sections(v, torch):
             forms[form] = {"p50_us": round(percentile(lat, 50), 2), "p99_us": round(percentile(lat, 99), 2),
                            "burst_us": round(burst, 2), "ops_s": round(int(is_op.sum()) / (burst * 1e-6), 0),
                            "amo_Mops_s": round(n_amo / (burst * 1e-6) / 1e6, 2)}
+        # The same forms without completion stamps, event-timed: a stamp
+        # waits for its operation's stores and writes a timestamp, which
+        # weighs on small work-groups more than on large ones.
+        bare = v.Plan(wl.descs, tune)
+        bare_graph = v.Plan(wl.descs, tune)
+        bare_graph.graph_build(1, results=res)
+        forms["no_stamps_event_us"] = {"fused": ev_us(lambda: bare.launch_fused(results=res)),
+                                       "graph": ev_us(lambda: bare_graph.graph_launch())}
+        bare.destroy()
+        bare_graph.destroy()
         plan.destroy()
         graph.destroy()
         small[label] = forms

@@ -705,10 +705,13 @@ void shmemx_plan_destroy(shmemx_plan_t *plan);
  * (scope, chunk) on `msgs` isolated puts of that class at that work-group
  * size; it then scores complete tables -- that tuned table, the three
  * uniform-scope tables and the built-in default, each at that work-group
- * size -- on a served mix: `msgs` put/get with sizes uniform in [min_bytes,
- * max_bytes] between random PEs, 10 * msgs contended fetch_add on 64
- * counters, in four epochs separated by barriers.  It returns the table with
- * the fastest mix (median of `reps` fused launches).  All traffic stays in
+ * size -- on a served mix shaped like a mixed program: `msgs` put/get with
+ * sizes uniform in [min_bytes, max_bytes] between random PEs in eight
+ * epochs separated by barriers, then 10 * msgs contended fetch_add on 64
+ * counters.  Each table's score is the median of max(reps, 9) fused
+ * launches of the mix; the four best are scored again in five interleaved
+ * rounds and the one with the lowest total is returned (the built-in table
+ * when no work-group size is resident).  All traffic stays in
  * the user heap range [scratch_off, scratch_off + scratch_bytes) of every PE,
  * whose contents are overwritten; scratch_bytes >= 2 * max_bytes + 1024.
  * Synchronous. */
