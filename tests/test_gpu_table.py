@@ -4,7 +4,8 @@ fused form (classify, index and executor kernels), the per-operation form
 and graphs of both, against the oracle run on the same program.  Also: graphs
 replay what the table holds at replay time, invalid descriptors are skipped
 and reported, plans launched together on two streams keep their barriers
-apart, and the active tune table comes from VSHMEM_TUNE_FILE."""
+apart, the active tune table comes from VSHMEM_TUNE_FILE, and empty,
+one-operation, ordering-only and zero-byte tables run cleanly."""
 import numpy as np
 import pytest
 
@@ -348,3 +349,45 @@ def test_many_issuers_from_a_device_table():
             t.cuda.synchronize()
             _check(v, download(wl.heap_bytes), ref, res, wl, descs)
         assert_no_device_errors()
+
+
+def test_degenerate_tables():
+    """An empty table, a table of one put, a table of ordering points only,
+    and zero-byte operations (one ending exactly at the user heap's end)
+    between NOPs: each runs in the fused, no-allocation and per-op forms,
+    changes exactly what the oracle changes, and latches no error."""
+    t = torch()
+    npes, region = 4, 64 << 10
+    with heap(npes, 1 << 20) as v:
+        ub = v.heap_user_bytes()
+        init = W.heap_fill(0xDE6, npes, region)
+        res = t.zeros(4, dtype=t.int64, device="cuda")
+        one_put = W.descs([(W.OP_PUT, W.SCOPE_AUTO, 0, 2, 1, W.NO_RESULT, 128, 40000, 1000, 0, 0)])
+        order_only = W.descs([(W.OP_FENCE, W.SCOPE_THREAD, 0, 0, 0, W.NO_RESULT, 0, 0, 0, 0, 0)] +
+                             [(W.OP_BARRIER_ALL, W.SCOPE_WG, 0, p, p, W.NO_RESULT, 0, 0, 0, 0, 0)
+                              for p in range(npes)] +
+                             [(W.OP_QUIET, W.SCOPE_THREAD, 0, 3, 3, W.NO_RESULT, 0, 0, 0, 0, 0)])
+        zero = W.descs([(W.OP_NOP, W.SCOPE_THREAD, 0, 0, 0, W.NO_RESULT, 0, 0, 0, 0, 0),
+                        (W.OP_PUT, W.SCOPE_THREAD, 0, 0, 1, W.NO_RESULT, ub, ub, 0, 0, 0),
+                        (W.OP_GET, W.SCOPE_WG, 0, 1, 2, W.NO_RESULT, 64, 4096, 0, 0, 0),
+                        (W.OP_NOP, W.SCOPE_THREAD, 0, 3, 3, W.NO_RESULT, 0, 0, 0, 0, 0),
+                        (W.OP_PUT, W.SCOPE_WAVE, 0, 3, 0, W.NO_RESULT, 8, 50000, 24, 0, 0)])
+        cases = {"empty": W.descs([]), "one_put": one_put, "ordering_only": order_only, "zero_bytes": zero}
+        for name, d in cases.items():
+            n = len(d)
+            table = write_table(d)
+            ref = init.copy()
+            if name != "zero_bytes":
+                oracle.run_program(ref, d)
+            else:
+                # the zero-byte operations change nothing; the last put moves 24 bytes
+                oracle.run_program(ref, d[-1:])
+            runs = {"fused": lambda: v.launch_batch(table, n, results=res),
+                    "noalloc": lambda: v.launch_batch_noalloc(table, n, results=res),
+                    "per_op": lambda: v.launch_per_op(table, n, results=res)}
+            for form, run in runs.items():
+                upload(init)
+                run()
+                t.cuda.synchronize()
+                assert np.array_equal(download(region), ref), (name, form)
+                assert_no_device_errors()
