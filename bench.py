@@ -1119,10 +1119,12 @@ def main():
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"{npes} virtual PEs x {args.heap_mib} MiB symmetric heap each (slices "
                                f"{heap_stride // MiB} MiB apart); one pass of every "
-                               "hot-path row (put/get sweep points at thread/wavefront/work-group scope on ring and "
-                               "derangement patterns, random atomics, signal ping-pong, barrier, broadcast 256 MiB, "
-                               "fcollect 4 MiB, alltoall 1 MiB blocks, sum/max reduce 2^24 elements int64/fp32/bf16, "
-                               "2000-op mixed batch in fused, per-op and graph forms)",
+                               "hot-path row (put/get at thread (8 B, 64 B), wavefront (4 KiB), work-group "
+                               "(16 MiB) and grid (64 MiB) scope on ring and derangement patterns, 2^26 random "
+                               "fetch_xor/fetch_add on a 2^27-entry int64 table, signal ping-pong 32 pairs x 200, "
+                               "100 barriers, broadcast 256 MiB, fcollect 4 MiB, alltoall 1 MiB blocks, sum/max "
+                               "reduce 2^24 elements int64/fp32/bf16, a 2000-op mixed batch in fused, per-op and "
+                               "graph forms, and a 1000-request serving burst on the persistent progress kernel)",
                    "npes": npes, "heap_bytes_per_pe": args.heap_mib * MiB, "heap_stride_bytes": heap_stride,
                    "step_algorithmic_bytes": step_bytes},
         "amo_Mops_s": gups.get("Mops_s"),
