@@ -292,12 +292,14 @@ def _long_program(npes, epochs, fences):
     return init, W.descs(recs), nres
 
 
-@pytest.mark.parametrize("epochs,fences", [(4200, 3000), (3, 2000)])
+@pytest.mark.parametrize("epochs,fences", [(4200, 3000), (3, 2000), (5000, 10)])
 def test_long_programs_past_the_index_kernels_lds_counters(epochs, fences):
-    """Tables of 14k-27k descriptors over several index tiles: 4200 epochs
+    """Tables of 10k-27k descriptors over several index tiles: 4200 epochs
     and 7200 phases put the epoch and bucket counters in memory; 2000 fences
-    in one epoch keep them in LDS.  Fused, no-allocation, fused-graph and
-    per-op forms against the oracle, bytes and every fetched value."""
+    in one epoch keep them in LDS; 5000 epochs with few operations put the
+    counters in memory in a table of two index tiles.  Fused, no-allocation,
+    fused-graph and per-op forms against the oracle, bytes and every fetched
+    value."""
     t = torch()
     npes = 2
     with heap(npes, 1 << 20) as v:
