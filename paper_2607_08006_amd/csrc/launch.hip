@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
     __shared__ uint32_t s_tmask[3];
     __shared__ uint32_t lepoch[kLdsEpochs];    // per epoch: largest fence count, then first phase
     __shared__ uint32_t lcnt[kLdsBuckets];     // per bucket: count, then scatter cursor
-    __shared__ uint32_t s_max, s_last, s_bad;
+    __shared__ uint32_t s_max, s_last, s_bad, s_wg;
     const uint32_t tid = threadIdx.x, nt = blockDim.x, n = a.n;
     const int npes = a.c.npes;
     const Ws &w = a.w;
@@ -442,6 +442,7 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
     for (uint32_t b = kLdsEpochs + tid; b <= n; b += nt) w.maxf[b] = 0;   // epochs past the LDS ones
     if (tid == 0) {
         s_max = 0;
+        s_wg = 0;
         s_last = 0;
         s_bad = 0;
         s_tmask[0] = 0;
@@ -675,20 +676,26 @@ __global__ void __launch_bounds__(kIndexThreads) k_batch_index(BatchArgs a)
         for (int r = 0; r < R; ++r) live[r] = key[r] != kNone;
         if (lds_cnt) agg_inc<R, true, true>(lcnt, key, live, pos);
         else agg_inc<R, true, false>(w.cnt, key, live, pos);
+        bool wg = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (live[r]) {
                 w.sorted[pos[r]] = i0 + r;
                 w.cs[pos[r]] = nch[r];
+                wg |= nch[r] != 0;
             }
         }
+        if (wg) s_wg = 1;   // every writer stores the same value
     }
     __syncthreads();
 
     // Pass 6: work-group task offsets over the sorted order.  Each position
-    // is read and rewritten by the same thread.
+    // is read and rewritten by the same thread.  Only work-group operations
+    // have tasks; without any, every position's count is 0 and so is its
+    // prefix: pass 5 already wrote it.
     uint64_t carry64 = 0;
-    for (uint32_t t0 = 0; t0 < nvalid; t0 += kIndexTile) {
+    const bool any_wg = s_wg != 0;
+    for (uint32_t t0 = 0; any_wg && t0 < nvalid; t0 += kIndexTile) {
         const uint32_t s0 = t0 + tid * R;
         uint64_t v[R], mine = 0;
         if (s0 + R <= nvalid) {
